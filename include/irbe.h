@@ -1,0 +1,193 @@
+/*
+ * irbe.h -- C ABI of the MI355X (gfx950) implementation of the non-bonded force
+ * of the improved random batch Ewald (IRBE) method:
+ *
+ *   Liang, Xu, Zhao, "Improved random batch Ewald method in molecular dynamics
+ *   simulations", arXiv:2204.13595.
+ *
+ * The force on atom i is F_i = F_i^core + F_i^shell,* - F^corr + F_i^excl + F_i^long,*:
+ *   - F_i^core: exact sum over the core set C(i) = {j != i : r_ij <= r_core}
+ *     (Sec. 2.3; the paper's r_eta), pair force of Eq. (2.10);
+ *   - F_i^shell,*: (N_S / p_shell) times the sum over a random batch of p_shell
+ *     members of the shell set S(i) = {j : r_core < r_ij <= r_shell} (Eq. (2.11);
+ *     the paper's r_c), all members with weight 1 when N_S <= p_shell;
+ *   - F^corr: the mean of F^core + F^shell,* over all atoms, subtracted from
+ *     every atom (Eq. (2.12));
+ *   - F_i^excl: removal of the reciprocal-space interaction erf(beta r)/r of
+ *     intramolecular (excluded) pairs, which are absent from C(i) and S(i);
+ *   - F_i^long,*: the random batch Ewald estimator of Eq. (2.9) over p_kspace
+ *     k-vectors drawn from P_k = exp(-k^2/(4 alpha))/S (Eqs. (2.6)-(2.8)),
+ *     alpha = beta^2.
+ * With p_shell <= 0 the library computes the full-list variant instead: every
+ * pair within r_shell with weight 1 and no F^corr (the paper's "RBE" column,
+ * RBE without the random batch list).
+ *
+ * Conventions.
+ *   - Units: nm, e, kJ/mol, kJ/mol/nm (coulomb_k = 138.935458 for these).
+ *   - Positions, charges, forces and gradients are DEVICE pointers to arrays in
+ *     the caller's atom order: positions/forces/gradients [N][3] row-major.
+ *     Their element type is float for IRBE_MIXED_FP32 and double for IRBE_FP64.
+ *     Arrays whose name ends in _host are host pointers.
+ *   - Positions need not be wrapped into the box. Each is stored as a 32-bit
+ *     fixed-point fraction of the box, s = rint(frac(x / L) * 2^32) mod 2^32,
+ *     so cells, lists and k-space phases are exact integer arithmetic and the
+ *     separation of two atoms is the minimum image (requires r_shell < L/2).
+ *   - Randomness is counter-based (Philox4x32-10 keyed by the seed): the shell
+ *     batch of atom i is a function of (seed, step, i) only, and the k-vectors
+ *     of (seed, step) only. Calls with the same step use the same samples.
+ *
+ * Ownership and streams. The caller owns every pointer argument and keeps the
+ * memory alive until the work queued on the handle's stream has completed. The
+ * library owns its scratch (allocated in irbe_create / irbe_set_system, grown in
+ * irbe_build_lists, freed in irbe_destroy) and keeps no caller pointer across
+ * calls. Every call queues work on the stream given to irbe_create and returns
+ * without waiting, except irbe_set_system, irbe_build_lists (one wait, to read
+ * the list sizes) and the debug/sync calls. A handle is not thread-safe.
+ *
+ * Errors. Arguments are checked on the host before anything is queued; a bad
+ * argument returns IRBE_EINVAL and leaves the handle as it was. Device-side
+ * conditions (non-finite positions) set an error word that the next waiting
+ * call (irbe_build_lists, irbe_sync, irbe_get_debug) reports. No call aborts or
+ * throws; irbe_last_error() describes the most recent failure.
+ */
+#ifndef IRBE_H
+#define IRBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IRBE_ABI_VERSION 1
+
+typedef struct irbe_ctx* irbe_handle;
+
+typedef enum {
+    IRBE_OK = 0,
+    IRBE_EINVAL = -1,       /* invalid argument or state                         */
+    IRBE_ENOMEM = -2,       /* device allocation failed                          */
+    IRBE_EHIP = -3,         /* a HIP runtime call failed                         */
+    IRBE_ECAPACITY = -4,    /* a list would exceed the hard capacity limit      */
+    IRBE_ESTATE = -5,       /* call out of order (e.g. forces before lists)      */
+    IRBE_EUNSUPPORTED = -6, /* valid but outside what this build supports       */
+    IRBE_ENONFINITE = -7    /* non-finite position seen on the device            */
+} irbe_status;
+
+enum { IRBE_MIXED_FP32 = 0, IRBE_FP64 = 1 };
+
+/* compute_forces flags */
+enum { IRBE_ENERGY = 1u, IRBE_VIRIAL = 2u };
+
+typedef struct {
+    int32_t abi_version;   /* IRBE_ABI_VERSION                                       */
+    int32_t precision;     /* IRBE_MIXED_FP32: pair and k-space arithmetic in FP32,
+                              structure factor, momentum correction, energies and
+                              virial accumulated in FP64. IRBE_FP64: all FP64.      */
+    int64_t n_atoms;       /* N >= 1                                                 */
+    double box_length;     /* L, cubic periodic box                                  */
+    double ewald_beta;     /* beta = sqrt(alpha): erfc(beta r) real-space split      */
+    double coulomb_k;      /* multiplies every Coulomb term                          */
+    double r_core;         /* the paper's r_eta; floor(L / r_core) >= 3              */
+    double r_shell;        /* the paper's r_c (erfc and LJ cutoff); r_core < r_shell < L/2 */
+    int32_t p_shell;       /* shell batch size p~ (> 0), or <= 0 for the full list   */
+    int32_t p_kspace;      /* number of sampled k-vectors p (>= 1)                   */
+    int32_t n_types;       /* LJ atom types, 1..64                                   */
+    int32_t reserved;      /* 0                                                      */
+    uint64_t seed;         /* Philox key                                             */
+    double capacity_hint;  /* expected list entries per atom, 0 = from density       */
+} irbe_config;
+
+/* Create a handle for one system size and parameter set; work is queued on
+ * hip_stream (a hipStream_t; NULL = the default stream). On success *out is a
+ * new handle. Returns IRBE_EINVAL for a bad configuration (message in
+ * irbe_last_error(NULL)). */
+irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* out);
+
+/* Set the topology and parameters (Sec. 2.1: charges q_i, LJ sigma_ij and
+ * epsilon_ij per type pair).
+ *   type[N] (device, int32 in [0, n_types)), charge[N] (device, float|double),
+ *   molecule[N] (device, int32; atoms with the same id >= 0 form excluded pairs,
+ *   -1 = no exclusions), lj_sigma_host / lj_eps_host [n_types * n_types] (host,
+ *   double, entry [t_i * n_types + t_j] used for the pair (i, j)).
+ * Waits on the stream (the exclusion table is built on the host). */
+irbe_status irbe_set_system(irbe_handle h, const int32_t* type, const void* charge, const int32_t* molecule,
+                            const double* lj_sigma_host, const double* lj_eps_host);
+
+/* Replace charges (device, N) and the LJ tables (host, n_types^2) without
+ * touching the topology; NULL leaves that part unchanged. Does not wait. */
+irbe_status irbe_update_parameters(irbe_handle h, const void* charge, const double* lj_sigma_host,
+                                   const double* lj_eps_host);
+
+/* Bin atoms into cells and build the core and shell lists (Sec. 2.3,
+ * Algorithm 1 step "create the core neighbor lists") from pos [N][3] (device).
+ * Lists are kept until the next call. Waits once on the stream to read the
+ * list sizes; grows the list storage and rebuilds when they exceed it. */
+irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step);
+
+/* Forces of the last built lists at positions pos (Algorithm 1, force steps):
+ * F written to force [N][3] (device, caller order). List membership, N_S and
+ * the batch are those of the last build; distances are exact at pos. The
+ * samples of `step` are used. With flags & (IRBE_ENERGY | IRBE_VIRIAL),
+ * energy_virial (device, 11 doubles) receives
+ *   [0] U_coul,short* [1] U_lj* [2] U_long* [3] U_self [4] U_excl
+ *   [5..10] W_xx W_yy W_zz W_xy W_xz W_yz,
+ * W_ab = sum over pairs of (r_i - r_j)_a f_ij,b plus the k-space term; the
+ * starred terms are the estimators matching Eq. (2.3) in expectation. */
+irbe_status irbe_compute_forces(irbe_handle h, const void* pos, uint64_t step, void* force, uint32_t flags,
+                                double* energy_virial);
+
+/* Vector-Jacobian product of irbe_compute_forces at fixed samples and lists:
+ * given grad_force = dL/dF [N][3] (device), writes grad_pos = dL/dr [N][3]
+ * (device), grad_charge = dL/dq [N] (device, or NULL) and grad_lj =
+ * [dL/dsigma (n_types^2), dL/deps (n_types^2)] (device, 2 n_types^2 doubles,
+ * or NULL; needs n_types <= 4). The shell scatter uses atomics, so results
+ * may differ in the last bits from run to run. */
+irbe_status irbe_compute_forces_backward(irbe_handle h, const void* pos, uint64_t step, const void* grad_force,
+                                         void* grad_pos, void* grad_charge, double* grad_lj);
+
+/* Wait for the handle's queued work and report a deferred device error. */
+irbe_status irbe_sync(irbe_handle h);
+
+/* Debug/parity read-back (waits). `what` selects the array; dst_host receives
+ * up to `capacity` elements; *written = the number of elements available.
+ *   IRBE_DBG_CELL_START  int64 [n_c^3 + 1]  atoms of cell c are
+ *   IRBE_DBG_CELL_ATOMS  int64 [N]          cell_atoms[cell_start[c] .. cell_start[c+1])
+ *   IRBE_DBG_CORE_OFF    int64 [N + 1]      C(i) of atom i (caller order) at
+ *   IRBE_DBG_CORE_IDX    int32 [..]         core_idx[core_off[i] .. core_off[i+1]) (atom ids)
+ *   IRBE_DBG_SHELL_OFF   int64 [N + 1]      S(i) (or the full list), same layout
+ *   IRBE_DBG_SHELL_IDX   int32 [..]
+ *   IRBE_DBG_BATCH_OFF   int64 [N + 1]      batch ranks into S(i), draw order, for
+ *   IRBE_DBG_BATCH_RANK  int32 [..]         the step of the last compute_forces
+ *   IRBE_DBG_KVEC        int32 [3 P]        sampled m (k = 2 pi m / L)
+ *   IRBE_DBG_RHO         double [2 P]       rho(k) (re, im)
+ *   IRBE_DBG_FCORR       double [3]         F^corr
+ *   IRBE_DBG_SCALARS     double [4]         S, H, n_c, R */
+enum {
+    IRBE_DBG_CELL_START = 1,
+    IRBE_DBG_CELL_ATOMS = 2,
+    IRBE_DBG_CORE_OFF = 3,
+    IRBE_DBG_CORE_IDX = 4,
+    IRBE_DBG_SHELL_OFF = 5,
+    IRBE_DBG_SHELL_IDX = 6,
+    IRBE_DBG_BATCH_OFF = 7,
+    IRBE_DBG_BATCH_RANK = 8,
+    IRBE_DBG_KVEC = 9,
+    IRBE_DBG_RHO = 10,
+    IRBE_DBG_FCORR = 11,
+    IRBE_DBG_SCALARS = 12
+};
+irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written);
+
+/* Message of the last failure on h (or of the last failed irbe_create when h is
+ * NULL). The string stays valid until the next call on h. */
+const char* irbe_last_error(irbe_handle h);
+
+/* Wait for the handle's work and free everything it owns. */
+irbe_status irbe_destroy(irbe_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRBE_H */

@@ -128,7 +128,9 @@ static inline int orc_excluded(const int32_t* mol, int64_t i, int64_t j)
  * S(i) = {j : r_core < r_ij <= r_shell} (Sec. 2.3), intramolecular pairs
  * removed. Canonical order: cell offsets (dz, dy, dx) in lexicographic order,
  * then the atoms of each cell in id order. Core offsets are -1..1 on each axis;
- * shell offsets are -R..R when 2R+1 <= n_c, else 0..n_c-1 (each cell once).
+ * shell offsets are -R..R when 2R+1 <= n_c, else -h..n_c-1-h with
+ * h = floor((n_c-1)/2) (each cell once, and the 27 core cells keep their
+ * relative order).
  *
  * Rows are the atoms sel[0..n_sel) (all atoms, in id order, when sel is NULL).
  * Pass 1 (idx == NULL) writes the row counts into *_off[k+1]; pass 2 fills.
@@ -149,7 +151,7 @@ static int64_t orc_list_row(int64_t i, const uint32_t* s, const int32_t* mol, in
     } else if (2 * R + 1 <= n_c) {
         lo = -R; hi = R;
     } else {
-        lo = 0; hi = n_c - 1;
+        lo = -((n_c - 1) / 2); hi = lo + n_c - 1;
     }
     for (int32_t dz = lo; dz <= hi; ++dz)
         for (int32_t dy = lo; dy <= hi; ++dy)

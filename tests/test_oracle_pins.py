@@ -145,6 +145,9 @@ def _brute_lists(s, mol, box, r_core, r_shell, rows, full=False):
             off = (cell[js] - cell[i]) % n_c
             if 2 * reach + 1 <= n_c:
                 off = np.where(off > reach, off - n_c, off)
+            else:
+                h = (n_c - 1) // 2
+                off = (off + h) % n_c - h
             key = np.lexsort((js, off[:, 0], off[:, 1], off[:, 2]))
             return js[key]
 
