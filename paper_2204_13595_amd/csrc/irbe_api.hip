@@ -1,0 +1,651 @@
+// Host runtime behind the C ABI of include/irbe.h: argument checks, device
+// memory ownership, the k-sampling table, the exclusion table, and the order of
+// the kernels of one force evaluation (Algorithm 1 of Liang, Xu, Zhao,
+// arXiv:2204.13595, force steps) on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "irbe_device.hpp"
+#include "irbe_internal.hpp"
+
+using namespace irbe;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kTwo64 = 18446744073709551616.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int64_t kMaxCells = int64_t(1) << 27;
+constexpr int32_t kMaxM = 1 << 16;
+
+irbe_status fail(irbe_ctx* h, irbe_status st, const std::string& msg)
+{
+    if (h) h->last_error = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+irbe_status hip_fail(irbe_ctx* h, hipError_t e, const char* where)
+{
+    const irbe_status st = e == hipErrorOutOfMemory ? IRBE_ENOMEM : IRBE_EHIP;
+    return fail(h, st, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define IRBE_TRY(h, expr, where)                      \
+    do {                                              \
+        const hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return hip_fail(h, e_, where); \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(irbe_ctx* h, T** p, size_t count)
+{
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    h->owned.push_back(q);
+    *p = (T*)q;
+    return hipSuccess;
+}
+
+hipError_t dalloc_bytes(irbe_ctx* h, void** p, size_t bytes)
+{
+    return dalloc(h, (unsigned char**)p, bytes);
+}
+
+void dfree(irbe_ctx* h, void* p)
+{
+    if (!p) return;
+    auto it = std::find(h->owned.begin(), h->owned.end(), p);
+    if (it != h->owned.end()) h->owned.erase(it);
+    hipFree(p);
+}
+
+// Quantized-geometry constants, in the FP64 operation order that fixes them:
+// n_c = floor(L / r_core), R = floor(r_shell n_c / L) + 1,
+// T = floor(t * t) with t = r 2^32 / L.
+void geometry(const irbe_config& c, Geometry& g)
+{
+#pragma clang fp contract(off)
+    const double L = c.box_length;
+    g.n_c = (int32_t)std::floor(L / c.r_core);
+    g.reach = (int32_t)std::floor(c.r_shell * (double)g.n_c / L) + 1;
+    if (2 * g.reach + 1 <= g.n_c) {
+        g.lo = -g.reach;
+        g.hi = g.reach;
+    } else {
+        g.lo = -((g.n_c - 1) / 2);
+        g.hi = g.lo + g.n_c - 1;
+    }
+    const double tc = c.r_core * kTwo32 / L;
+    const double ts = c.r_shell * kTwo32 / L;
+    g.t_core = (uint64_t)std::floor(tc * tc);
+    g.t_shell = (uint64_t)std::floor(ts * ts);
+    g.inv_l = 1.0 / L;
+    g.quantum = L / kTwo32;
+    g.n_cells = (int64_t)g.n_c * g.n_c * g.n_c;
+}
+
+// Per-axis inverse-CDF table of the discrete Gaussian w(m) = exp(-(pi m/(beta L))^2)
+// (Eqs. (2.6)-(2.8)): M = smallest m >= 0 with w(m+1) < 2^-64,
+// H = sum_{m=-M..M} w(m) in ascending m, S = H^3 - 1,
+// U[m+M] = floor(2^64 cdf(m)) with the cdf accumulated in ascending m, U[2M] = 2^64-1.
+int32_t ktable(double beta, double L, std::vector<uint64_t>& U, double& H, double& S)
+{
+#pragma clang fp contract(off)
+    const double a = kPi / (beta * L);
+    auto w = [a](int32_t m) {
+        const double x = a * (double)m;
+        return std::exp(-(x * x));
+    };
+    int32_t M = 0;
+    while (w(M + 1) >= 1.0 / kTwo64) {
+        ++M;
+        if (M > kMaxM) return -1;
+    }
+    H = 0.0;
+    for (int32_t m = -M; m <= M; ++m) H += w(m);
+    U.assign(2 * (size_t)M + 1, 0);
+    double c = 0.0;
+    for (int32_t m = -M; m <= M; ++m) {
+        c += w(m);
+        const double x = (c / H) * kTwo64;
+        U[m + M] = (x >= kTwo64) ? UINT64_MAX : (uint64_t)x;
+    }
+    U[2 * M] = UINT64_MAX;
+    S = H * H * H - 1.0;
+    return M;
+}
+
+int32_t round_up32(double v) { return (int32_t)((std::ceil(v) + 31.0) / 32.0) * 32; }
+
+hipError_t alloc_lists(irbe_ctx* h, int32_t cap_core, int32_t cap_shell)
+{
+    const size_t n = (size_t)h->cfg.n_atoms;
+    dfree(h, h->core);
+    dfree(h, h->shell);
+    h->core = h->shell = nullptr;
+    hipError_t e = dalloc(h, &h->core, n * (size_t)cap_core);
+    if (e != hipSuccess) return e;
+    e = dalloc(h, &h->shell, n * (size_t)cap_shell);
+    if (e != hipSuccess) return e;
+    h->cap_core = cap_core;
+    h->cap_shell = cap_shell;
+    return hipSuccess;
+}
+
+irbe_status check_device_error(irbe_ctx* h)
+{
+    uint32_t err = 0;
+    IRBE_TRY(h, hipMemcpyAsync(&err, h->err, sizeof(err), hipMemcpyDeviceToHost, h->stream), "read error word");
+    IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
+    if (err) {
+        IRBE_TRY(h, launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1), "clear error word");
+        if (err & ERR_NONFINITE) return fail(h, IRBE_ENONFINITE, "non-finite position");
+        return fail(h, IRBE_ECAPACITY, "list capacity exceeded");
+    }
+    return IRBE_OK;
+}
+
+template <typename real>
+void lj_tables(const irbe_ctx* h, std::vector<LJ<real>>& tab, std::vector<real>& raw)
+{
+    const int nt2 = h->cfg.n_types * h->cfg.n_types;
+    tab.resize(nt2);
+    raw.resize(2 * (size_t)nt2);
+    for (int t = 0; t < nt2; ++t) {
+        const double s = h->lj_sigma_host[t], e = h->lj_eps_host[t];
+        const double s6 = s * s * s * s * s * s;
+        const double s12 = s6 * s6;
+        tab[t].a12 = (real)(48.0 * e * s12);
+        tab[t].b6 = (real)(24.0 * e * s6);
+        tab[t].c12 = (real)(4.0 * e * s12);
+        tab[t].c6 = (real)(4.0 * e * s6);
+        raw[t] = (real)s;
+        raw[nt2 + t] = (real)e;
+    }
+}
+
+irbe_status upload_lj(irbe_ctx* h)
+{
+    const int nt2 = h->cfg.n_types * h->cfg.n_types;
+    if (h->fp64) {
+        std::vector<LJ<double>> tab;
+        std::vector<double> raw;
+        lj_tables(h, tab, raw);
+        IRBE_TRY(h, hipMemcpyAsync(h->lj, tab.data(), sizeof(LJ<double>) * nt2, hipMemcpyHostToDevice, h->stream),
+                 "upload LJ");
+        IRBE_TRY(h, hipMemcpyAsync(h->lj_raw, raw.data(), sizeof(double) * 2 * nt2, hipMemcpyHostToDevice, h->stream),
+                 "upload LJ");
+        IRBE_TRY(h, hipStreamSynchronize(h->stream), "upload LJ");
+    } else {
+        std::vector<LJ<float>> tab;
+        std::vector<float> raw;
+        lj_tables(h, tab, raw);
+        IRBE_TRY(h, hipMemcpyAsync(h->lj, tab.data(), sizeof(LJ<float>) * nt2, hipMemcpyHostToDevice, h->stream),
+                 "upload LJ");
+        IRBE_TRY(h, hipMemcpyAsync(h->lj_raw, raw.data(), sizeof(float) * 2 * nt2, hipMemcpyHostToDevice, h->stream),
+                 "upload LJ");
+        IRBE_TRY(h, hipStreamSynchronize(h->stream), "upload LJ");
+    }
+    return IRBE_OK;
+}
+
+bool set_lj_host(irbe_ctx* h, const double* sig, const double* eps, std::string& why)
+{
+    const int nt2 = h->cfg.n_types * h->cfg.n_types;
+    std::vector<double> s(sig, sig + nt2), e(eps, eps + nt2);
+    for (int t = 0; t < nt2; ++t)
+        if (!std::isfinite(s[t]) || !std::isfinite(e[t]) || s[t] < 0.0) {
+            why = "LJ tables must be finite with sigma >= 0";
+            return false;
+        }
+    h->lj_sigma_host = s;
+    h->lj_eps_host = e;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* out)
+{
+    if (!cfg || !out) return fail(nullptr, IRBE_EINVAL, "null argument");
+    *out = nullptr;
+    const irbe_config& c = *cfg;
+    if (c.abi_version != IRBE_ABI_VERSION) return fail(nullptr, IRBE_EINVAL, "abi_version mismatch");
+    if (c.precision != IRBE_MIXED_FP32 && c.precision != IRBE_FP64) return fail(nullptr, IRBE_EINVAL, "bad precision");
+    if (c.n_atoms < 1 || c.n_atoms > (int64_t(1) << 30)) return fail(nullptr, IRBE_EINVAL, "n_atoms out of range");
+    if (!(c.box_length > 0.0) || !std::isfinite(c.box_length)) return fail(nullptr, IRBE_EINVAL, "bad box_length");
+    if (!(c.ewald_beta > 0.0) || !std::isfinite(c.ewald_beta)) return fail(nullptr, IRBE_EINVAL, "bad ewald_beta");
+    if (!std::isfinite(c.coulomb_k)) return fail(nullptr, IRBE_EINVAL, "bad coulomb_k");
+    if (!(c.r_core > 0.0) || !(c.r_shell > c.r_core) || !(c.r_shell < 0.5 * c.box_length))
+        return fail(nullptr, IRBE_EINVAL, "need 0 < r_core < r_shell < L/2");
+    if (c.p_kspace < 1) return fail(nullptr, IRBE_EINVAL, "p_kspace must be >= 1");
+    if (c.n_types < 1 || c.n_types > 16) return fail(nullptr, IRBE_EINVAL, "n_types must be in 1..16");
+    if (!(c.capacity_hint >= 0.0) || !std::isfinite(c.capacity_hint))
+        return fail(nullptr, IRBE_EINVAL, "bad capacity_hint");
+
+    irbe_ctx* h = new (std::nothrow) irbe_ctx();
+    if (!h) return fail(nullptr, IRBE_ENOMEM, "host allocation failed");
+    h->cfg = c;
+    h->stream = (hipStream_t)hip_stream;
+    h->fp64 = c.precision == IRBE_FP64;
+    h->real_size = h->fp64 ? 8 : 4;
+    h->full_list = c.p_shell <= 0;
+    geometry(c, h->geo);
+    if (h->geo.n_c < 3) {
+        delete h;
+        return fail(nullptr, IRBE_EINVAL, "floor(L / r_core) must be >= 3");
+    }
+    if (h->geo.n_cells > kMaxCells) {
+        delete h;
+        return fail(nullptr, IRBE_EUNSUPPORTED, "too many cells");
+    }
+    std::vector<uint64_t> U;
+    h->kM = ktable(c.ewald_beta, c.box_length, U, h->kH, h->kS);
+    if (h->kM < 0) {
+        delete h;
+        return fail(nullptr, IRBE_EUNSUPPORTED, "k table too large (beta L too big)");
+    }
+    hipError_t e = hipGetDevice(&h->device);
+    const size_t n = (size_t)c.n_atoms;
+    const size_t rs = h->real_size;
+    const int64_t nb = blocks_for(c.n_atoms, kBlock);
+    const int64_t nb64 = blocks_for(c.n_atoms, 64);
+    const int64_t nbr = rho_blocks(c.n_atoms);
+    const size_t P = (size_t)c.p_kspace;
+    const int nt2 = c.n_types * c.n_types;
+#define ALLOC(expr)                      \
+    if (e == hipSuccess) e = (expr);
+    ALLOC(dalloc(h, &h->err, 1));
+    ALLOC(dalloc(h, &h->maxcnt, 2));
+    ALLOC(dalloc(h, &h->ktab, U.size()));
+    ALLOC(dalloc_bytes(h, &h->q_orig, n * rs));
+    ALLOC(dalloc(h, &h->type_orig, n));
+    ALLOC(dalloc(h, &h->mol_orig, n));
+    ALLOC(dalloc_bytes(h, &h->lj, (size_t)nt2 * 4 * rs));
+    ALLOC(dalloc_bytes(h, &h->lj_raw, (size_t)nt2 * 2 * rs));
+    ALLOC(dalloc(h, &h->sumq2, 1));
+    ALLOC(dalloc(h, &h->q2part, (size_t)nb));
+    ALLOC(dalloc(h, &h->sq, n));
+    ALLOC(dalloc(h, &h->cell_count, (size_t)h->geo.n_cells));
+    ALLOC(dalloc(h, &h->cell_start, (size_t)h->geo.n_cells + 1));
+    ALLOC(dalloc(h, &h->cursor, (size_t)h->geo.n_cells));
+    {
+        int64_t m = h->geo.n_cells;
+        do {
+            m = blocks_for(m, 1024);
+            int32_t* lv = nullptr;
+            ALLOC(dalloc(h, &lv, (size_t)m + 1));
+            h->scan_levels.push_back(lv);
+        } while (m > 1);
+        int32_t* lv = nullptr;
+        ALLOC(dalloc(h, &lv, 2));
+        h->scan_levels.push_back(lv);
+    }
+    ALLOC(dalloc(h, &h->perm, n));
+    ALLOC(dalloc(h, &h->rank, n));
+    ALLOC(dalloc(h, &h->spos, n));
+    ALLOC(dalloc_bytes(h, &h->sq_r, n * rs));
+    ALLOC(dalloc(h, &h->smol, n));
+    ALLOC(dalloc(h, &h->ncore, n));
+    ALLOC(dalloc(h, &h->nshell, n));
+    ALLOC(dalloc_bytes(h, &h->fsr, 3 * n * rs));
+    ALLOC(dalloc(h, &h->pair_part, (size_t)nb64 * kPairPartials));
+    ALLOC(dalloc(h, &h->fcorr, 3));
+    ALLOC(dalloc(h, &h->ev_pair, kPairPartials));
+    ALLOC(dalloc(h, &h->kvec, P));
+    ALLOC(dalloc(h, &h->kcoef, 4 * P));
+    ALLOC(dalloc(h, &h->rho_part, 4 * P * (size_t)nbr));
+    ALLOC(dalloc(h, &h->rho, 2 * P));
+    ALLOC(dalloc(h, &h->Avec, 2 * P));
+    ALLOC(dalloc_bytes(h, &h->kforce, P * sizeof(KForce<double>)));
+    ALLOC(dalloc_bytes(h, &h->kadj, P * sizeof(KAdj<double>)));
+    ALLOC(dalloc_bytes(h, &h->gs, 3 * n * rs));
+    ALLOC(dalloc(h, &h->gpart, (size_t)nb * 3));
+    ALLOC(dalloc(h, &h->gmean, 3));
+    ALLOC(dalloc_bytes(h, &h->gself, 3 * n * rs));
+    ALLOC(dalloc_bytes(h, &h->gscat, 3 * n * rs));
+    ALLOC(dalloc_bytes(h, &h->gqself, n * rs));
+    ALLOC(dalloc_bytes(h, &h->gqscat, n * rs));
+    ALLOC(dalloc(h, &h->ljpart, (size_t)nb64 * 2 * kMaxTypesGrad * kMaxTypesGrad));
+#undef ALLOC
+    if (e == hipSuccess) {
+        const double L = c.box_length;
+        const double rho_n = (double)c.n_atoms / (L * L * L);
+        const double vc = 4.0 / 3.0 * kPi * c.r_core * c.r_core * c.r_core;
+        const double vs = 4.0 / 3.0 * kPi * c.r_shell * c.r_shell * c.r_shell;
+        int32_t cap_c = round_up32(1.3 * rho_n * vc + 32.0);
+        int32_t cap_s = round_up32(1.3 * rho_n * (h->full_list ? vs : vs - vc) + 32.0);
+        if (c.capacity_hint > 0.0) cap_s = round_up32(c.capacity_hint);
+        if (h->full_list) cap_c = 1;
+        cap_c = (int32_t)std::min<int64_t>(cap_c, c.n_atoms + 32);
+        cap_s = (int32_t)std::min<int64_t>(cap_s, c.n_atoms + 32);
+        e = alloc_lists(h, cap_c, cap_s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->ktab, U.data(), U.size() * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        const irbe_status st = hip_fail(nullptr, e, "irbe_create");
+        irbe_destroy(h);
+        return st;
+    }
+    *out = h;
+    return IRBE_OK;
+}
+
+irbe_status irbe_set_system(irbe_handle h, const int32_t* type, const void* charge, const int32_t* molecule,
+                            const double* lj_sigma_host, const double* lj_eps_host)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!type || !charge || !molecule || !lj_sigma_host || !lj_eps_host)
+        return fail(h, IRBE_EINVAL, "irbe_set_system: null argument");
+    std::string why;
+    std::vector<double> keep_s = h->lj_sigma_host, keep_e = h->lj_eps_host;
+    if (!set_lj_host(h, lj_sigma_host, lj_eps_host, why)) return fail(h, IRBE_EINVAL, why);
+    const size_t n = (size_t)h->cfg.n_atoms;
+    std::vector<int32_t> t(n), mol(n);
+    IRBE_TRY(h, hipMemcpyAsync(t.data(), type, n * 4, hipMemcpyDeviceToHost, h->stream), "read types");
+    IRBE_TRY(h, hipMemcpyAsync(mol.data(), molecule, n * 4, hipMemcpyDeviceToHost, h->stream), "read molecules");
+    IRBE_TRY(h, hipStreamSynchronize(h->stream), "set_system");
+    for (size_t i = 0; i < n; ++i)
+        if (t[i] < 0 || t[i] >= h->cfg.n_types) {
+            h->lj_sigma_host = keep_s;
+            h->lj_eps_host = keep_e;
+            return fail(h, IRBE_EINVAL, "atom type out of range");
+        }
+    // exclusion partners: the other atoms with the same molecule id >= 0, by id
+    std::vector<std::pair<int32_t, int32_t>> order;
+    order.reserve(n);
+    for (size_t i = 0; i < n; ++i)
+        if (mol[i] >= 0) order.emplace_back(mol[i], (int32_t)i);
+    std::sort(order.begin(), order.end());
+    std::vector<int32_t> off(n + 1, 0);
+    for (size_t a = 0; a < order.size();) {
+        size_t b = a;
+        while (b < order.size() && order[b].first == order[a].first) ++b;
+        if (b - a > 4096) return fail(h, IRBE_EUNSUPPORTED, "molecules of more than 4096 atoms");
+        for (size_t k = a; k < b; ++k) off[order[k].second + 1] = (int32_t)(b - a - 1);
+        a = b;
+    }
+    int64_t total = 0;
+    for (size_t i = 0; i < n; ++i) {
+        total += off[i + 1];
+        if (total > INT32_MAX) return fail(h, IRBE_EUNSUPPORTED, "too many excluded pairs");
+        off[i + 1] = (int32_t)total;
+    }
+    std::vector<int32_t> idx((size_t)std::max<int64_t>(total, 1));
+    for (size_t a = 0; a < order.size();) {
+        size_t b = a;
+        while (b < order.size() && order[b].first == order[a].first) ++b;
+        for (size_t k = a; k < b; ++k) {
+            int32_t w = off[order[k].second];
+            for (size_t u = a; u < b; ++u)
+                if (u != k) idx[w++] = order[u].second;
+        }
+        a = b;
+    }
+    dfree(h, h->xoff);
+    dfree(h, h->xidx);
+    h->xoff = h->xidx = nullptr;
+    IRBE_TRY(h, dalloc(h, &h->xoff, n + 1), "alloc exclusions");
+    IRBE_TRY(h, dalloc(h, &h->xidx, idx.size()), "alloc exclusions");
+    h->n_excl = total;
+    IRBE_TRY(h, hipMemcpyAsync(h->xoff, off.data(), (n + 1) * 4, hipMemcpyHostToDevice, h->stream), "upload");
+    IRBE_TRY(h, hipMemcpyAsync(h->xidx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, h->stream), "upload");
+    IRBE_TRY(h, hipMemcpyAsync(h->type_orig, type, n * 4, hipMemcpyDeviceToDevice, h->stream), "copy types");
+    IRBE_TRY(h, hipMemcpyAsync(h->mol_orig, molecule, n * 4, hipMemcpyDeviceToDevice, h->stream), "copy molecules");
+    IRBE_TRY(h, hipMemcpyAsync(h->q_orig, charge, n * h->real_size, hipMemcpyDeviceToDevice, h->stream),
+             "copy charges");
+    IRBE_TRY(h, launch_sum_q2(h), "sum q^2");
+    const irbe_status st = upload_lj(h);
+    if (st != IRBE_OK) return st;
+    h->have_system = true;
+    h->have_lists = false;
+    return IRBE_OK;
+}
+
+irbe_status irbe_update_parameters(irbe_handle h, const void* charge, const double* lj_sigma_host,
+                                   const double* lj_eps_host)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!h->have_system) return fail(h, IRBE_ESTATE, "irbe_update_parameters before irbe_set_system");
+    if ((lj_sigma_host == nullptr) != (lj_eps_host == nullptr))
+        return fail(h, IRBE_EINVAL, "give both LJ tables or neither");
+    if (lj_sigma_host) {
+        std::string why;
+        if (!set_lj_host(h, lj_sigma_host, lj_eps_host, why)) return fail(h, IRBE_EINVAL, why);
+        const irbe_status st = upload_lj(h);
+        if (st != IRBE_OK) return st;
+    }
+    if (charge) {
+        IRBE_TRY(h, hipMemcpyAsync(h->q_orig, charge, (size_t)h->cfg.n_atoms * h->real_size, hipMemcpyDeviceToDevice,
+                                   h->stream),
+                 "copy charges");
+        IRBE_TRY(h, launch_sum_q2(h), "sum q^2");
+    }
+    return IRBE_OK;
+}
+
+irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
+{
+    (void)step;
+    if (!h) return IRBE_EINVAL;
+    if (!pos) return fail(h, IRBE_EINVAL, "irbe_build_lists: null positions");
+    if (!h->have_system) return fail(h, IRBE_ESTATE, "irbe_build_lists before irbe_set_system");
+    h->have_lists = false;
+    IRBE_TRY(h, launch_bin(h, pos), "binning");
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        IRBE_TRY(h, launch_build_lists(h), "list build");
+        int32_t mx[2] = {0, 0};
+        IRBE_TRY(h, hipMemcpyAsync(mx, h->maxcnt, sizeof(mx), hipMemcpyDeviceToHost, h->stream), "read list sizes");
+        const irbe_status st = check_device_error(h);
+        if (st != IRBE_OK) return st;
+        if (mx[0] <= h->cap_core && mx[1] <= h->cap_shell) {
+            h->max_core = mx[0];
+            h->max_shell = mx[1];
+            h->have_lists = true;
+            return IRBE_OK;
+        }
+        const int32_t nc = std::max(h->cap_core, round_up32(1.15 * mx[0] + 32.0));
+        const int32_t ns = std::max(h->cap_shell, round_up32(1.15 * mx[1] + 32.0));
+        IRBE_TRY(h, alloc_lists(h, nc, ns), "grow lists");
+    }
+    return fail(h, IRBE_ECAPACITY, "list capacity did not converge");
+}
+
+irbe_status irbe_compute_forces(irbe_handle h, const void* pos, uint64_t step, void* force, uint32_t flags,
+                                double* energy_virial)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!pos || !force) return fail(h, IRBE_EINVAL, "irbe_compute_forces: null argument");
+    if (flags & ~(uint32_t)(IRBE_ENERGY | IRBE_VIRIAL)) return fail(h, IRBE_EINVAL, "unknown flags");
+    if (flags && !energy_virial) return fail(h, IRBE_EINVAL, "energy/virial requested without a buffer");
+    if (!h->have_lists) return fail(h, IRBE_ESTATE, "irbe_compute_forces before irbe_build_lists");
+    const bool ev = flags != 0;
+    IRBE_TRY(h, launch_requantize(h, pos), "quantize");
+    IRBE_TRY(h, launch_ksample(h, step), "k sampling");
+    IRBE_TRY(h, launch_rho(h, nullptr, false), "structure factor");
+    IRBE_TRY(h, launch_pair_forces(h, step, ev), "pair forces");
+    IRBE_TRY(h, launch_kspace_forces(h, force), "k-space forces");
+    if (ev) IRBE_TRY(h, launch_energy_finalize(h, energy_virial), "energy");
+    h->last_force_step = step;
+    h->have_force_step = true;
+    return IRBE_OK;
+}
+
+irbe_status irbe_compute_forces_backward(irbe_handle h, const void* pos, uint64_t step, const void* grad_force,
+                                         void* grad_pos, void* grad_charge, double* grad_lj)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!pos || !grad_force || !grad_pos) return fail(h, IRBE_EINVAL, "irbe_compute_forces_backward: null argument");
+    if (!h->have_lists) return fail(h, IRBE_ESTATE, "backward before irbe_build_lists");
+    if (grad_lj && h->cfg.n_types > kMaxTypesGrad)
+        return fail(h, IRBE_EUNSUPPORTED, "LJ gradients need n_types <= 4");
+    IRBE_TRY(h, launch_requantize(h, pos), "quantize");
+    IRBE_TRY(h, launch_ksample(h, step), "k sampling");
+    IRBE_TRY(h, launch_gather_grad(h, grad_force), "gather dL/dF");
+    IRBE_TRY(h, launch_rho(h, grad_force, true), "structure factor (adjoint)");
+    IRBE_TRY(h, launch_pair_adjoint(h, step, grad_charge != nullptr, grad_lj != nullptr), "pair adjoint");
+    IRBE_TRY(h, launch_kspace_adjoint(h, grad_force, grad_pos, grad_charge, grad_lj), "k-space adjoint");
+    return IRBE_OK;
+}
+
+irbe_status irbe_sync(irbe_handle h)
+{
+    if (!h) return IRBE_EINVAL;
+    IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
+    return check_device_error(h);
+}
+
+irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!written || capacity < 0 || (capacity > 0 && !dst_host)) return fail(h, IRBE_EINVAL, "bad debug buffer");
+    IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
+    const int64_t n = h->cfg.n_atoms;
+    auto copy_out = [&](const void* src, size_t elem, int64_t count) {
+        *written = count;
+        const int64_t m = std::min(count, capacity);
+        if (m > 0) std::memcpy(dst_host, src, (size_t)m * elem);
+    };
+    auto d2h = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+    };
+    const bool needs_lists = what == IRBE_DBG_CELL_START || what == IRBE_DBG_CELL_ATOMS || what == IRBE_DBG_CORE_OFF ||
+                             what == IRBE_DBG_CORE_IDX || what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_SHELL_IDX ||
+                             what == IRBE_DBG_BATCH_OFF || what == IRBE_DBG_BATCH_RANK;
+    if (needs_lists && !h->have_lists) return fail(h, IRBE_ESTATE, "no lists built");
+    const bool needs_force = what == IRBE_DBG_KVEC || what == IRBE_DBG_RHO || what == IRBE_DBG_FCORR ||
+                             what == IRBE_DBG_BATCH_OFF || what == IRBE_DBG_BATCH_RANK;
+    if (needs_force && !h->have_force_step) return fail(h, IRBE_ESTATE, "no force evaluation yet");
+    switch (what) {
+    case IRBE_DBG_CELL_START: {
+        std::vector<int32_t> v((size_t)h->geo.n_cells + 1);
+        IRBE_TRY(h, d2h(v.data(), h->cell_start, v.size() * 4), "debug");
+        std::vector<int64_t> w(v.begin(), v.end());
+        copy_out(w.data(), 8, (int64_t)w.size());
+        return IRBE_OK;
+    }
+    case IRBE_DBG_CELL_ATOMS: {
+        std::vector<int32_t> v((size_t)n);
+        IRBE_TRY(h, d2h(v.data(), h->perm, v.size() * 4), "debug");
+        std::vector<int64_t> w(v.begin(), v.end());
+        copy_out(w.data(), 8, (int64_t)w.size());
+        return IRBE_OK;
+    }
+    case IRBE_DBG_CORE_OFF:
+    case IRBE_DBG_CORE_IDX:
+    case IRBE_DBG_SHELL_OFF:
+    case IRBE_DBG_SHELL_IDX:
+    case IRBE_DBG_BATCH_OFF:
+    case IRBE_DBG_BATCH_RANK: {
+        const bool is_core = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_CORE_IDX;
+        const bool is_batch = what == IRBE_DBG_BATCH_OFF || what == IRBE_DBG_BATCH_RANK;
+        const bool want_off = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_BATCH_OFF;
+        std::vector<int32_t> perm((size_t)n), rank((size_t)n), cnt((size_t)n);
+        IRBE_TRY(h, d2h(perm.data(), h->perm, (size_t)n * 4), "debug");
+        IRBE_TRY(h, d2h(rank.data(), h->rank, (size_t)n * 4), "debug");
+        IRBE_TRY(h, d2h(cnt.data(), is_core ? h->ncore : h->nshell, (size_t)n * 4), "debug");
+        int32_t stride = is_core ? h->cap_core : h->cap_shell;
+        std::vector<int32_t> rows;
+        if (is_batch) {
+            stride = h->full_list ? h->cap_shell : std::max(1, std::min(h->cfg.p_shell, h->cap_shell));
+            int32_t* dev = nullptr;
+            IRBE_TRY(h, hipMalloc(&dev, (size_t)n * stride * 4), "debug");
+            hipError_t e = launch_batch_debug(h, h->last_force_step, dev, stride);
+            if (e == hipSuccess) {
+                rows.resize((size_t)n * stride);
+                e = d2h(rows.data(), dev, rows.size() * 4);
+            }
+            hipFree(dev);
+            IRBE_TRY(h, e, "debug batches");
+            for (int64_t k = 0; k < n; ++k)
+                if (!h->full_list && cnt[k] > h->cfg.p_shell) cnt[k] = h->cfg.p_shell;
+        } else {
+            rows.resize((size_t)n * stride);
+            IRBE_TRY(h, d2h(rows.data(), is_core ? h->core : h->shell, rows.size() * 4), "debug");
+        }
+        std::vector<int64_t> off((size_t)n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + (is_core && h->full_list ? 0 : cnt[rank[i]]);
+        if (want_off) {
+            copy_out(off.data(), 8, n + 1);
+            return IRBE_OK;
+        }
+        std::vector<int32_t> idx((size_t)off[n]);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t k = rank[i];
+            for (int64_t t = 0; t < off[i + 1] - off[i]; ++t) {
+                const int32_t v = rows[(size_t)k * stride + t];
+                idx[off[i] + t] = is_batch ? v : perm[v];
+            }
+        }
+        copy_out(idx.data(), 4, (int64_t)idx.size());
+        return IRBE_OK;
+    }
+    case IRBE_DBG_KVEC: {
+        std::vector<int4> v((size_t)h->cfg.p_kspace);
+        IRBE_TRY(h, d2h(v.data(), h->kvec, v.size() * sizeof(int4)), "debug");
+        std::vector<int32_t> w;
+        for (auto& m : v) {
+            w.push_back(m.x);
+            w.push_back(m.y);
+            w.push_back(m.z);
+        }
+        copy_out(w.data(), 4, (int64_t)w.size());
+        return IRBE_OK;
+    }
+    case IRBE_DBG_RHO: {
+        std::vector<double> v(2 * (size_t)h->cfg.p_kspace);
+        IRBE_TRY(h, d2h(v.data(), h->rho, v.size() * 8), "debug");
+        copy_out(v.data(), 8, (int64_t)v.size());
+        return IRBE_OK;
+    }
+    case IRBE_DBG_FCORR: {
+        double v[3];
+        IRBE_TRY(h, d2h(v, h->fcorr, sizeof(v)), "debug");
+        copy_out(v, 8, 3);
+        return IRBE_OK;
+    }
+    case IRBE_DBG_SCALARS: {
+        const double v[4] = {h->kS, h->kH, (double)h->geo.n_c, (double)h->geo.reach};
+        copy_out(v, 8, 4);
+        return IRBE_OK;
+    }
+    default:
+        return fail(h, IRBE_EINVAL, "unknown debug selector");
+    }
+}
+
+const char* irbe_last_error(irbe_handle h)
+{
+    return h ? h->last_error.c_str() : g_create_error.c_str();
+}
+
+irbe_status irbe_destroy(irbe_handle h)
+{
+    if (!h) return IRBE_EINVAL;
+    hipStreamSynchronize(h->stream);
+    for (void* p : h->owned) hipFree(p);
+    h->owned.clear();
+    delete h;
+    return IRBE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations of the HIP implementation: the handle, the launch
+// helpers and the kernel entry points shared between the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "irbe.h"
+
+namespace irbe {
+
+// Error-word bits set by kernels and read back at the next waiting call.
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_CORE_CAP = 2u, ERR_SHELL_CAP = 4u };
+
+constexpr int kBlock = 256;          // threads per block of the per-atom kernels
+constexpr int kReduceBlock = 256;    // threads of the deterministic final reductions
+constexpr int kPairPartials = 16;    // FP64 values per block of the pair kernel
+constexpr int kRhoChunk = 16;        // k-vectors per block row of the structure factor
+constexpr int kRhoAtomsPerThread = 8;
+constexpr int kMaxTypesGrad = 4;     // LJ parameter gradients: n_types <= 4
+
+// Per-k constants of the force kernels: k (3), then coefficient products.
+template <typename real>
+struct KForce {
+    real kx, ky, kz;
+    real a;  // ke c_l Im(rho_l)
+    real b;  // ke c_l Re(rho_l)
+    real pad0, pad1, pad2;
+};
+
+template <typename real>
+struct KAdj {
+    real kx, ky, kz;
+    real ar, ai;  // ke c_l A_l
+    real rr, ri;  // ke c_l rho_l
+    real pad;
+};
+
+// LJ pair table entry: force 48 eps s^12, 24 eps s^6; energy 4 eps s^12, 4 eps s^6.
+template <typename real>
+struct LJ {
+    real a12, b6, c12, c6;
+};
+
+struct Geometry {
+    int32_t n_c = 0;
+    int32_t reach = 0;      // R: shell stencil half-width in cells
+    int32_t lo = 0, hi = 0; // shell stencil offsets per axis, inclusive
+    uint64_t t_core = 0, t_shell = 0;
+    double inv_l = 0.0;
+    double quantum = 0.0;   // L / 2^32
+    int64_t n_cells = 0;
+};
+
+}  // namespace irbe
+
+struct irbe_ctx {
+    irbe_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool fp64 = false;
+    bool full_list = false;
+    size_t real_size = 4;
+    irbe::Geometry geo;
+    std::string last_error;
+
+    // k table
+    int32_t kM = 0;
+    double kH = 0.0, kS = 0.0;
+
+    // state
+    bool have_system = false;
+    bool have_lists = false;
+    int32_t cap_core = 0, cap_shell = 0;
+    int32_t max_core = 0, max_shell = 0;
+    uint64_t last_force_step = 0;
+    bool have_force_step = false;
+    std::vector<double> lj_sigma_host, lj_eps_host;
+
+    // device memory, all owned by the handle
+    uint32_t* err = nullptr;          // error word
+    int32_t* maxcnt = nullptr;        // [2] max core / shell count of the last build
+    uint64_t* ktab = nullptr;         // [2M+1]
+    void* q_orig = nullptr;           // real[N]
+    int32_t* type_orig = nullptr;     // [N]
+    int32_t* mol_orig = nullptr;      // [N]
+    void* lj = nullptr;               // LJ<real>[n_t^2]
+    void* lj_raw = nullptr;           // real[2 n_t^2]: sigma, eps
+    int32_t* xoff = nullptr;          // [N+1] exclusion partners per atom (caller ids)
+    int32_t* xidx = nullptr;
+    int64_t n_excl = 0;
+    double* sumq2 = nullptr;          // [1]
+    double* q2part = nullptr;
+
+    uint4* sq = nullptr;              // [N] quantized position + cell, caller order
+    int32_t* cell_count = nullptr;    // [n_cells]
+    int32_t* cell_start = nullptr;    // [n_cells + 1]
+    int32_t* cursor = nullptr;        // [n_cells]
+    std::vector<int32_t*> scan_levels;
+    std::vector<int64_t> scan_sizes;
+    int32_t* perm = nullptr;          // [N] sorted -> caller id
+    int32_t* rank = nullptr;          // [N] caller id -> sorted
+    uint4* spos = nullptr;            // [N] sorted {sx, sy, sz, type}
+    void* sq_r = nullptr;             // real[N] sorted charges
+    int32_t* smol = nullptr;          // [N] sorted molecule ids
+
+    int32_t* core = nullptr;          // [N * cap_core]
+    int32_t* ncore = nullptr;         // [N]
+    int32_t* shell = nullptr;         // [N * cap_shell]
+    int32_t* nshell = nullptr;        // [N]
+
+    void* fsr = nullptr;              // real[3N] sorted short-range (+ excluded-pair) force
+    double* pair_part = nullptr;      // [nb * kPairPartials]
+    double* fcorr = nullptr;          // [3]
+    double* ev_pair = nullptr;        // [kPairPartials] reduced pair partials
+
+    int4* kvec = nullptr;             // [P]
+    double* kcoef = nullptr;          // [4P]: kx, ky, kz, c_l
+    double* rho_part = nullptr;       // [2 * P * nb_rho] (x2 for the adjoint A)
+    double* rho = nullptr;            // [2P]
+    double* Avec = nullptr;           // [2P]
+    void* kforce = nullptr;           // KForce<real>[P]
+    void* kadj = nullptr;             // KAdj<real>[P]
+
+    void* gs = nullptr;               // real[3N] sorted dL/dF
+    double* gpart = nullptr;          // [nb * 3]
+    double* gmean = nullptr;          // [3]
+    void* gself = nullptr;            // real[3N]
+    void* gscat = nullptr;            // real[3N]
+    void* gqself = nullptr;           // real[N]
+    void* gqscat = nullptr;           // real[N]
+    double* ljpart = nullptr;         // [nb * 2 * kMaxTypesGrad^2]
+    int64_t adj_nb = 0;               // blocks of the last pair-adjoint launch
+
+    std::vector<void*> owned;
+};
+
+namespace irbe {
+
+int64_t blocks_for(int64_t n, int block);
+int64_t rho_blocks(int64_t n);
+
+// Launchers (all on the handle's stream). Each returns the HIP status of the launch.
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);
+hipError_t launch_fill_bytes0(hipStream_t s, void* p, size_t bytes);
+hipError_t launch_bin(irbe_ctx* h, const void* pos);
+hipError_t launch_requantize(irbe_ctx* h, const void* pos);
+hipError_t launch_build_lists(irbe_ctx* h);
+hipError_t launch_ksample(irbe_ctx* h, uint64_t step);
+hipError_t launch_rho(irbe_ctx* h, const void* grad, bool with_adjoint);
+hipError_t launch_pair_forces(irbe_ctx* h, uint64_t step, bool ev);
+hipError_t launch_kspace_forces(irbe_ctx* h, void* force);
+hipError_t launch_energy_finalize(irbe_ctx* h, double* ev);
+hipError_t launch_sum_q2(irbe_ctx* h);
+hipError_t launch_gather_grad(irbe_ctx* h, const void* grad);
+hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool want_lj);
+hipError_t launch_kspace_adjoint(irbe_ctx* h, const void* grad, void* grad_pos, void* grad_q, double* grad_lj);
+hipError_t launch_batch_debug(irbe_ctx* h, uint64_t step, int32_t* ranks_dev, int32_t stride);
+
+}  // namespace irbe

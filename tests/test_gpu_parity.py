@@ -1,0 +1,152 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Integer results (cells, lists, batches, k-vectors) must be bit-exact. Forces,
+energies and gradients must agree within tolerances derived from the
+arithmetic: FP64 mode to ~1e-10 relative, mixed mode (FP32 pair and k-space
+arithmetic with FP64 accumulations) to the RMS relative bound 1e-5 for forces.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2204_13595_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rms_rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+def _setup(w, precision, p_shell=100, p_kspace=100, seed=13595, beta=3.0):
+    from paper_2204_13595_amd import irbe
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    dev = torch.device("cuda", 0)
+    h = irbe.Handle(w.n_atoms, w.box, beta=beta, p_shell=p_shell, p_kspace=p_kspace, seed=seed,
+                    precision=precision, device=dev)
+    pos = torch.tensor(w.pos, dtype=dt, device=dev)
+    q = torch.tensor(w.charge, dtype=dt, device=dev)
+    h.set_system(torch.tensor(w.atom_type, device=dev), q, torch.tensor(w.molecule, device=dev), w.lj_sigma, w.lj_eps)
+    # the oracle sees exactly the positions and charges the GPU sees
+    pos_np = pos.double().cpu().numpy()
+    q_np = q.double().cpu().numpy()
+    return h, pos, q, pos_np, q_np
+
+
+def _oracle_params(orc, w, p_shell=100, p_kspace=100, seed=13595, beta=3.0):
+    return orc.Params(box=w.box, beta=beta, p_shell=p_shell, p_kspace=p_kspace, seed=seed)
+
+
+@pytest.mark.parametrize("name,precision,p_shell", [("water512", "fp64", 100), ("water512", "mixed", 100),
+                                                     ("water4k", "mixed", 100), ("water4k", "mixed", 0)])
+def test_cells_and_lists_bit_exact(orc, name, precision, p_shell):
+    w = inputs.workload(name)
+    h, pos, q, pos_np, q_np = _setup(w, precision, p_shell=p_shell)
+    h.build_lists(pos, 0)
+    s = orc.quantize(pos_np, w.box)
+    n_c = orc.n_cells(w.box, 0.5)
+    start, atoms = orc.cell_lists(s, n_c)
+    assert np.array_equal(h.debug("cell_start"), start)
+    assert np.array_equal(h.debug("cell_atoms"), atoms)
+    full = p_shell <= 0
+    lists = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2, full=full)
+    assert np.array_equal(h.debug("shell_off"), lists.shell_off)
+    assert np.array_equal(h.debug("shell_idx"), lists.shell_idx)
+    if not full:
+        assert np.array_equal(h.debug("core_off"), lists.core_off)
+        assert np.array_equal(h.debug("core_idx"), lists.core_idx)
+    h.close()
+
+
+@pytest.mark.parametrize("step", [0, 7, (1 << 33) + 5])
+def test_batches_and_kvectors_bit_exact(orc, step):
+    w = inputs.workload("water512")
+    h, pos, q, pos_np, q_np = _setup(w, "mixed", p_kspace=200)
+    h.build_lists(pos, step)
+    h.compute_forces(pos, step)
+    p = _oracle_params(orc, w, p_kspace=200)
+    s = orc.quantize(pos_np, w.box)
+    lists = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2)
+    b_off, b_rank, _ = orc.shell_batches(p.seed, step, lists, p.p_shell)
+    assert np.array_equal(h.debug("batch_off"), b_off)
+    assert np.array_equal(h.debug("batch_rank"), b_rank)
+    m, _, S = orc.sample_kspace(p, step)
+    assert np.array_equal(h.debug("kvec").reshape(-1, 3), m)
+    sc = h.debug("scalars")
+    assert sc[0] == S and sc[2] == orc.n_cells(w.box, 0.5)
+    h.close()
+
+
+@pytest.mark.parametrize("precision,p_shell,tol_f,tol_e", [("fp64", 100, 1e-11, 1e-10), ("fp64", 0, 1e-11, 1e-10),
+                                                            ("mixed", 100, 1e-5, 2e-5), ("mixed", 0, 1e-5, 2e-5)])
+@pytest.mark.parametrize("name", ["water512", "water4k"])
+def test_forces_energies_parity(orc, name, precision, p_shell, tol_f, tol_e):
+    w = inputs.workload(name)
+    step = 3
+    h, pos, q, pos_np, q_np = _setup(w, precision, p_shell=p_shell)
+    h.build_lists(pos, step)
+    f, ev = h.compute_forces(pos, step, energy=True)
+    f = f.double().cpu().numpy()
+    ev = ev.cpu().numpy()
+    p = _oracle_params(orc, w, p_shell=p_shell)
+    mode = "full" if p_shell <= 0 else "rbl"
+    ref = orc.forward(pos_np, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step, mode=mode)
+    assert _rms_rel(f, ref.force) < tol_f
+    rho = h.debug("rho").reshape(-1, 2)
+    assert np.abs(rho - ref.rho).max() < tol_e * np.abs(ref.rho).max() * 10
+    fc = h.debug("fcorr")
+    assert np.abs(fc - ref.fcorr).max() < tol_f * np.sqrt((ref.force ** 2).mean()) * 10
+    # energies: compare against the sum of absolute pair terms as the scale
+    scale = np.abs(ref.energy[:5]).max()
+    for c in range(11):
+        assert abs(ev[c] - ref.energy[c]) < tol_e * scale, (c, ev[c], ref.energy[c])
+    h.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
+@pytest.mark.parametrize("p_shell", [100, 0])
+def test_backward_parity(orc, precision, tol, p_shell):
+    w = inputs.workload("water512")
+    step = 5
+    h, pos, q, pos_np, q_np = _setup(w, precision, p_shell=p_shell)
+    h.build_lists(pos, step)
+    G = np.random.default_rng(11).standard_normal((w.n_atoms, 3))
+    Gt = torch.tensor(G, dtype=pos.dtype, device=pos.device)
+    gp, gq, gl = h.compute_forces_backward(pos, step, Gt)
+    gp = gp.double().cpu().numpy()
+    gq = gq.double().cpu().numpy()
+    gl = gl.cpu().numpy()
+    p = _oracle_params(orc, w, p_shell=p_shell)
+    mode = "full" if p_shell <= 0 else "rbl"
+    ref = orc.forward(pos_np, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step, mode=mode)
+    G_used = Gt.double().cpu().numpy()
+    r_pos, r_q, r_sig, r_eps = orc.backward(G_used, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, ref,
+                                            mode=mode)
+    assert _rms_rel(gp, r_pos) < tol
+    assert _rms_rel(gq, r_q) < tol
+    assert abs(gl[0] - r_sig[0]) < tol * max(abs(r_sig[0]), 1.0) * 10
+    assert abs(gl[4] - r_eps[0]) < tol * max(abs(r_eps[0]), 1.0) * 10
+    h.close()
+
+
+def test_invalid_arguments_rejected():
+    from paper_2204_13595_amd import irbe
+    with pytest.raises(irbe.IRBEError):
+        irbe.Handle(1000, 2.0, r_core=0.5, r_shell=1.2)  # r_shell >= L/2
+    with pytest.raises(irbe.IRBEError):
+        irbe.Handle(1000, 2.0, r_core=0.9, r_shell=0.95)  # floor(L / r_core) < 3
+    w = inputs.workload("water512")
+    h, pos, q, pos_np, q_np = _setup(w, "mixed")
+    with pytest.raises(irbe.IRBEError):
+        h.compute_forces(pos, 0)  # before build_lists
+    bad = pos.clone()
+    bad[5, 1] = float("nan")
+    with pytest.raises(irbe.IRBEError):
+        h.build_lists(bad, 0)
+    h.build_lists(pos, 0)  # the handle still works afterwards
+    h.compute_forces(pos, 0)
+    h.sync()
+    h.close()
