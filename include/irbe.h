@@ -92,7 +92,7 @@ typedef struct {
     double r_shell;        /* the paper's r_c (erfc and LJ cutoff); r_core < r_shell < L/2 */
     int32_t p_shell;       /* shell batch size p~ (> 0), or <= 0 for the full list   */
     int32_t p_kspace;      /* number of sampled k-vectors p (>= 1)                   */
-    int32_t n_types;       /* LJ atom types, 1..64                                   */
+    int32_t n_types;       /* LJ atom types, 1..16                                   */
     int32_t reserved;      /* 0                                                      */
     uint64_t seed;         /* Philox key                                             */
     double capacity_hint;  /* expected list entries per atom, 0 = from density       */
@@ -115,7 +115,8 @@ irbe_status irbe_set_system(irbe_handle h, const int32_t* type, const void* char
                             const double* lj_sigma_host, const double* lj_eps_host);
 
 /* Replace charges (device, N) and the LJ tables (host, n_types^2) without
- * touching the topology; NULL leaves that part unchanged. Does not wait. */
+ * touching the topology; NULL leaves that part unchanged. Waits only when LJ
+ * tables are given. */
 irbe_status irbe_update_parameters(irbe_handle h, const void* charge, const double* lj_sigma_host,
                                    const double* lj_eps_host);
 
@@ -149,6 +150,30 @@ irbe_status irbe_compute_forces_backward(irbe_handle h, const void* pos, uint64_
 /* Wait for the handle's queued work and report a deferred device error. */
 irbe_status irbe_sync(irbe_handle h);
 
+/* Per-stage timing with HIP events recorded on the handle's stream around each
+ * kernel (or small kernel group) of the listed stages. enable != 0 starts
+ * recording (and clears the totals), 0 stops. irbe_get_timing waits, then
+ * writes for each stage s < capacity/2: ms_host[2s] = total milliseconds,
+ * ms_host[2s+1] = number of launches; *written = 2 * IRBE_N_STAGES. */
+enum {
+    IRBE_STAGE_BIN = 0,        /* quantize, histogram, scan, scatter, in-cell sort, gather */
+    IRBE_STAGE_LISTS = 1,      /* core/shell list build kernel                             */
+    IRBE_STAGE_QUANTIZE = 2,   /* re-quantize positions for a force evaluation             */
+    IRBE_STAGE_KSAMPLE = 3,    /* k-vector draw                                            */
+    IRBE_STAGE_RHO = 4,        /* structure factor (partials + final reduction)            */
+    IRBE_STAGE_PAIR = 5,       /* pair force kernel                                        */
+    IRBE_STAGE_PAIR_REDUCE = 6,/* momentum-correction / energy reduction                   */
+    IRBE_STAGE_KSPACE = 7,     /* k-space force + final force assembly                     */
+    IRBE_STAGE_ENERGY = 8,     /* energy / virial finalisation                             */
+    IRBE_STAGE_GRAD_GATHER = 9,/* dL/dF gather and mean                                    */
+    IRBE_STAGE_RHO_ADJ = 10,   /* structure factor and A_l (adjoint)                       */
+    IRBE_STAGE_PAIR_ADJ = 11,  /* pair adjoint kernel                                      */
+    IRBE_STAGE_KSPACE_ADJ = 12,/* k-space adjoint + gradient assembly                      */
+    IRBE_N_STAGES = 13
+};
+irbe_status irbe_enable_timing(irbe_handle h, int32_t enable);
+irbe_status irbe_get_timing(irbe_handle h, double* ms_host, int64_t capacity, int64_t* written);
+
 /* Debug/parity read-back (waits). `what` selects the array; dst_host receives
  * up to `capacity` elements; *written = the number of elements available.
  *   IRBE_DBG_CELL_START  int64 [n_c^3 + 1]  atoms of cell c are
@@ -162,7 +187,10 @@ irbe_status irbe_sync(irbe_handle h);
  *   IRBE_DBG_KVEC        int32 [3 P]        sampled m (k = 2 pi m / L)
  *   IRBE_DBG_RHO         double [2 P]       rho(k) (re, im)
  *   IRBE_DBG_FCORR       double [3]         F^corr
- *   IRBE_DBG_SCALARS     double [4]         S, H, n_c, R */
+ *   IRBE_DBG_SCALARS     double [4]         S, H, n_c, R
+ *   IRBE_DBG_COUNTS      int64 [4]          total core entries, total shell (or
+ *                                           full-list) entries, row capacities
+ *                                           (core, shell) of the last build */
 enum {
     IRBE_DBG_CELL_START = 1,
     IRBE_DBG_CELL_ATOMS = 2,
@@ -175,7 +203,8 @@ enum {
     IRBE_DBG_KVEC = 9,
     IRBE_DBG_RHO = 10,
     IRBE_DBG_FCORR = 11,
-    IRBE_DBG_SCALARS = 12
+    IRBE_DBG_SCALARS = 12,
+    IRBE_DBG_COUNTS = 13
 };
 irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written);
 

@@ -790,3 +790,55 @@ int orc_kspace_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, const
     free(A);
     return ORC_OK;
 }
+
+/* Batches of a set of rows (Algorithm 1: p~ shell members per atom, or all
+ * when N_S <= p~): ranks per row into batch_rank at batch_off (pass 1 with
+ * batch_rank == NULL writes the counts), weights w = N_S / p~ (1 when all). */
+int orc_shell_batches(uint64_t seed, uint64_t step, const int64_t* rows, int64_t n_rows, const int64_t* shell_off,
+                      int32_t p_s, int64_t* batch_off, int32_t* batch_rank, double* w)
+{
+    if (!batch_rank) {
+        batch_off[0] = 0;
+        for (int64_t r = 0; r < n_rows; ++r) {
+            int64_t n_s = shell_off[r + 1] - shell_off[r];
+            batch_off[r + 1] = batch_off[r] + (n_s <= p_s ? n_s : p_s);
+        }
+        return ORC_OK;
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t id = orc_row_atom(rows, r);
+        int32_t n_s = (int32_t)(shell_off[r + 1] - shell_off[r]);
+        orc_shell_ranks(seed, step, id, n_s, p_s, batch_rank + batch_off[r]);
+        w[r] = n_s > p_s ? (double)n_s / (double)p_s : 1.0;
+    }
+    return ORC_OK;
+}
+
+/* Excluded partners of each row atom: the other atoms with the same molecule
+ * id >= 0, in id order. order[] holds all atoms with mol >= 0 sorted by
+ * (mol, id) and pos_in_order[i] the position of atom i in it (-1 if none).
+ * Pass 1 (idx == NULL) writes the counts into off[r+1]. */
+int orc_exclusion_rows(int64_t n, const int32_t* mol, const int64_t* order, int64_t n_order,
+                       const int64_t* pos_in_order, const int64_t* rows, int64_t n_rows, int64_t* off, int64_t* idx)
+{
+    (void)n;
+    if (!idx) off[0] = 0;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t i = orc_row_atom(rows, r);
+        int64_t p = pos_in_order[i];
+        int64_t cnt = 0;
+        if (p >= 0) {
+            int64_t a = p, b = p;
+            while (a > 0 && mol[order[a - 1]] == mol[i]) --a;
+            while (b + 1 < n_order && mol[order[b + 1]] == mol[i]) ++b;
+            for (int64_t t = a; t <= b; ++t) {
+                if (order[t] == i) continue;
+                if (idx) idx[off[r] + cnt] = order[t];
+                ++cnt;
+            }
+        }
+        if (!idx) off[r + 1] = off[r] + cnt;
+    }
+    return ORC_OK;
+}

@@ -74,6 +74,10 @@ def lib():
         L.orc_ktable.restype = ctypes.c_int32
         L.orc_ktable.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, _u64p, _f64p, _f64p]
         L.orc_kdraw.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, _u64p, _i32p]
+        L.orc_shell_batches.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _i64p, ctypes.c_int64, _i64p,
+                                        ctypes.c_int32, _i64p, _i32p, _f64p]
+        L.orc_exclusion_rows.argtypes = [ctypes.c_int64, _i32p, _i64p, ctypes.c_int64, _i64p, _i64p, ctypes.c_int64,
+                                         _i64p, _i64p]
         L.orc_short_range.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i32p, _f64p, _f64p,
                                       _i64p, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _i64p, _i32p, _f64p,
                                       _f64p, _f64p]
@@ -190,31 +194,23 @@ def build_lists(s, mol, box, r_core, r_shell, full=False, rows=None) -> Lists:
 
 def exclusion_lists(mol: np.ndarray, rows=None):
     """Partners of each (row) atom: the other atoms with the same molecule id >= 0, in id order."""
-    mol = np.asarray(mol)
+    mol = _c(mol, np.int32)
     n = mol.shape[0]
-    ids = np.arange(n)
+    ids = np.arange(n, dtype=np.int64)
     valid = ids[mol >= 0]
-    order = valid[np.lexsort((valid, mol[valid]))]
-    groups = {}
-    if order.size:
-        m_sorted = mol[order]
-        cuts = np.flatnonzero(np.diff(m_sorted)) + 1
-        for g in np.split(order, cuts):
-            groups[int(mol[g[0]])] = g
-    row_ids = ids if rows is None else np.asarray(rows)
-    off = np.zeros(row_ids.shape[0] + 1, dtype=np.int64)
-    parts = []
-    for k, i in enumerate(row_ids):
-        m = int(mol[i])
-        if m < 0:
-            partners = np.empty(0, dtype=np.int64)
-        else:
-            g = groups[m]
-            partners = g[g != i]
-        parts.append(partners)
-        off[k + 1] = off[k] + partners.shape[0]
-    idx = np.concatenate(parts).astype(np.int64) if parts else np.empty(0, dtype=np.int64)
-    return off, idx
+    order = _c(valid[np.lexsort((valid, mol[valid]))], np.int64)
+    pos_in = np.full(n, -1, dtype=np.int64)
+    pos_in[order] = np.arange(order.shape[0])
+    rows_a = None if rows is None else _c(rows, np.int64)
+    nr = n if rows is None else rows_a.shape[0]
+    off = np.zeros(nr + 1, dtype=np.int64)
+    L = lib()
+    L.orc_exclusion_rows(n, _p(mol, _i32p), _p(order, _i64p), order.shape[0], _p(pos_in, _i64p), _p(rows_a, _i64p),
+                         nr, _p(off, _i64p), None)
+    idx = np.empty(max(int(off[-1]), 1), dtype=np.int64)
+    L.orc_exclusion_rows(n, _p(mol, _i32p), _p(order, _i64p), order.shape[0], _p(pos_in, _i64p), _p(rows_a, _i64p),
+                         nr, _p(off, _i64p), _p(idx, _i64p))
+    return off, idx[:off[-1]]
 
 
 # --------------------------------------------------------------------------- randomness
@@ -236,19 +232,16 @@ def shell_ranks(seed: int, step: int, atom_id: int, n_s: int, p_s: int) -> np.nd
 def shell_batches(seed: int, step: int, lists: Lists, p_s: int):
     """Per-row batch ranks (CSR) and weights N_S / p_s (1 when N_S <= p_s)."""
     n_rows = lists.shell_off.shape[0] - 1
-    ids = np.arange(n_rows) if lists.rows is None else lists.rows
-    n_s = np.diff(lists.shell_off)
+    rows = None if lists.rows is None else _c(lists.rows, np.int64)
     off = np.zeros(n_rows + 1, dtype=np.int64)
-    parts = []
+    L = lib()
+    L.orc_shell_batches(seed, step, _p(rows, _i64p), n_rows, _p(lists.shell_off, _i64p), p_s, _p(off, _i64p), None,
+                        None)
+    rank = np.empty(max(int(off[-1]), 1), dtype=np.int32)
     w = np.ones(n_rows)
-    for r in range(n_rows):
-        ranks = shell_ranks(seed, step, int(ids[r]), int(n_s[r]), p_s)
-        parts.append(ranks)
-        off[r + 1] = off[r] + ranks.shape[0]
-        if n_s[r] > p_s:
-            w[r] = n_s[r] / p_s
-    rank = np.concatenate(parts).astype(np.int32) if parts else np.empty(0, dtype=np.int32)
-    return off, rank, w
+    L.orc_shell_batches(seed, step, _p(rows, _i64p), n_rows, _p(lists.shell_off, _i64p), p_s, _p(off, _i64p),
+                        _p(rank, _i32p), _p(w, _f64p))
+    return off, rank[:off[-1]], w
 
 
 def ktable(beta: float, box: float, max_m: int = 1 << 16):

@@ -46,6 +46,14 @@ irbe_status hip_fail(irbe_ctx* h, hipError_t e, const char* where)
         if (e_ != hipSuccess) return hip_fail(h, e_, where); \
     } while (0)
 
+// A launcher bracketed by timing events when timing is on.
+#define IRBE_STAGE(h, stage, expr, where) \
+    do {                                  \
+        stage_begin(h);                   \
+        IRBE_TRY(h, expr, where);         \
+        stage_end(h, stage);              \
+    } while (0)
+
 template <typename T>
 hipError_t dalloc(irbe_ctx* h, T** p, size_t count)
 {
@@ -157,6 +165,37 @@ irbe_status check_device_error(irbe_ctx* h)
         return fail(h, IRBE_ECAPACITY, "list capacity exceeded");
     }
     return IRBE_OK;
+}
+
+void stage_begin(irbe_ctx* h)
+{
+    if (!h->timing) return;
+    hipEventCreate(&h->open_start);
+    hipEventRecord(h->open_start, h->stream);
+}
+
+void stage_end(irbe_ctx* h, int stage)
+{
+    if (!h->timing || !h->open_start) return;
+    hipEvent_t stop;
+    hipEventCreate(&stop);
+    hipEventRecord(stop, h->stream);
+    h->pending.push_back({stage, h->open_start, stop});
+    h->open_start = nullptr;
+}
+
+void drain_timing(irbe_ctx* h)
+{
+    for (auto& p : h->pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.stop) == hipSuccess && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+            h->stage_ms[p.stage] += ms;
+            h->stage_n[p.stage] += 1;
+        }
+        hipEventDestroy(p.start);
+        hipEventDestroy(p.stop);
+    }
+    h->pending.clear();
 }
 
 template <typename real>
@@ -450,9 +489,10 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
     if (!pos) return fail(h, IRBE_EINVAL, "irbe_build_lists: null positions");
     if (!h->have_system) return fail(h, IRBE_ESTATE, "irbe_build_lists before irbe_set_system");
     h->have_lists = false;
-    IRBE_TRY(h, launch_bin(h, pos), "binning");
+    IRBE_STAGE(h, IRBE_STAGE_BIN, launch_bin(h, pos), "binning");
     for (int attempt = 0; attempt < 3; ++attempt) {
-        IRBE_TRY(h, launch_build_lists(h), "list build");
+        IRBE_TRY(h, launch_fill_i32(h->stream, h->maxcnt, 0, 2), "list build");
+        IRBE_STAGE(h, IRBE_STAGE_LISTS, launch_build_lists(h), "list build");
         int32_t mx[2] = {0, 0};
         IRBE_TRY(h, hipMemcpyAsync(mx, h->maxcnt, sizeof(mx), hipMemcpyDeviceToHost, h->stream), "read list sizes");
         const irbe_status st = check_device_error(h);
@@ -479,12 +519,13 @@ irbe_status irbe_compute_forces(irbe_handle h, const void* pos, uint64_t step, v
     if (flags && !energy_virial) return fail(h, IRBE_EINVAL, "energy/virial requested without a buffer");
     if (!h->have_lists) return fail(h, IRBE_ESTATE, "irbe_compute_forces before irbe_build_lists");
     const bool ev = flags != 0;
-    IRBE_TRY(h, launch_requantize(h, pos), "quantize");
-    IRBE_TRY(h, launch_ksample(h, step), "k sampling");
-    IRBE_TRY(h, launch_rho(h, nullptr, false), "structure factor");
-    IRBE_TRY(h, launch_pair_forces(h, step, ev), "pair forces");
-    IRBE_TRY(h, launch_kspace_forces(h, force), "k-space forces");
-    if (ev) IRBE_TRY(h, launch_energy_finalize(h, energy_virial), "energy");
+    IRBE_STAGE(h, IRBE_STAGE_QUANTIZE, launch_requantize(h, pos), "quantize");
+    IRBE_STAGE(h, IRBE_STAGE_KSAMPLE, launch_ksample(h, step), "k sampling");
+    IRBE_STAGE(h, IRBE_STAGE_RHO, launch_rho(h, nullptr, false), "structure factor");
+    IRBE_STAGE(h, IRBE_STAGE_PAIR, launch_pair_forces(h, step, ev), "pair forces");
+    IRBE_STAGE(h, IRBE_STAGE_PAIR_REDUCE, launch_pair_reduce(h), "pair reduction");
+    IRBE_STAGE(h, IRBE_STAGE_KSPACE, launch_kspace_forces(h, force), "k-space forces");
+    if (ev) IRBE_STAGE(h, IRBE_STAGE_ENERGY, launch_energy_finalize(h, energy_virial), "energy");
     h->last_force_step = step;
     h->have_force_step = true;
     return IRBE_OK;
@@ -498,12 +539,14 @@ irbe_status irbe_compute_forces_backward(irbe_handle h, const void* pos, uint64_
     if (!h->have_lists) return fail(h, IRBE_ESTATE, "backward before irbe_build_lists");
     if (grad_lj && h->cfg.n_types > kMaxTypesGrad)
         return fail(h, IRBE_EUNSUPPORTED, "LJ gradients need n_types <= 4");
-    IRBE_TRY(h, launch_requantize(h, pos), "quantize");
-    IRBE_TRY(h, launch_ksample(h, step), "k sampling");
-    IRBE_TRY(h, launch_gather_grad(h, grad_force), "gather dL/dF");
-    IRBE_TRY(h, launch_rho(h, grad_force, true), "structure factor (adjoint)");
-    IRBE_TRY(h, launch_pair_adjoint(h, step, grad_charge != nullptr, grad_lj != nullptr), "pair adjoint");
-    IRBE_TRY(h, launch_kspace_adjoint(h, grad_force, grad_pos, grad_charge, grad_lj), "k-space adjoint");
+    IRBE_STAGE(h, IRBE_STAGE_QUANTIZE, launch_requantize(h, pos), "quantize");
+    IRBE_STAGE(h, IRBE_STAGE_KSAMPLE, launch_ksample(h, step), "k sampling");
+    IRBE_STAGE(h, IRBE_STAGE_GRAD_GATHER, launch_gather_grad(h, grad_force), "gather dL/dF");
+    IRBE_STAGE(h, IRBE_STAGE_RHO_ADJ, launch_rho(h, grad_force, true), "structure factor (adjoint)");
+    IRBE_STAGE(h, IRBE_STAGE_PAIR_ADJ, launch_pair_adjoint(h, step, grad_charge != nullptr, grad_lj != nullptr),
+               "pair adjoint");
+    IRBE_STAGE(h, IRBE_STAGE_KSPACE_ADJ, launch_kspace_adjoint(h, grad_force, grad_pos, grad_charge, grad_lj),
+               "k-space adjoint");
     return IRBE_OK;
 }
 
@@ -623,6 +666,19 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
         copy_out(v, 8, 3);
         return IRBE_OK;
     }
+    case IRBE_DBG_COUNTS: {
+        if (!h->have_lists) return fail(h, IRBE_ESTATE, "no lists built");
+        std::vector<int32_t> a((size_t)n), b((size_t)n);
+        IRBE_TRY(h, d2h(a.data(), h->ncore, (size_t)n * 4), "debug");
+        IRBE_TRY(h, d2h(b.data(), h->nshell, (size_t)n * 4), "debug");
+        int64_t v[4] = {0, 0, h->full_list ? 0 : h->cap_core, h->cap_shell};
+        for (int64_t i = 0; i < n; ++i) {
+            v[0] += h->full_list ? 0 : a[i];
+            v[1] += b[i];
+        }
+        copy_out(v, 8, 4);
+        return IRBE_OK;
+    }
     case IRBE_DBG_SCALARS: {
         const double v[4] = {h->kS, h->kH, (double)h->geo.n_c, (double)h->geo.reach};
         copy_out(v, 8, 4);
@@ -631,6 +687,33 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
     default:
         return fail(h, IRBE_EINVAL, "unknown debug selector");
     }
+}
+
+irbe_status irbe_enable_timing(irbe_handle h, int32_t enable)
+{
+    if (!h) return IRBE_EINVAL;
+    IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
+    drain_timing(h);
+    for (int s = 0; s < IRBE_N_STAGES; ++s) {
+        h->stage_ms[s] = 0.0;
+        h->stage_n[s] = 0;
+    }
+    h->timing = enable != 0;
+    return IRBE_OK;
+}
+
+irbe_status irbe_get_timing(irbe_handle h, double* ms_host, int64_t capacity, int64_t* written)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!written || capacity < 0 || (capacity > 0 && !ms_host)) return fail(h, IRBE_EINVAL, "bad timing buffer");
+    IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
+    drain_timing(h);
+    *written = 2 * IRBE_N_STAGES;
+    for (int s = 0; s < IRBE_N_STAGES; ++s) {
+        if (2 * s < capacity) ms_host[2 * s] = h->stage_ms[s];
+        if (2 * s + 1 < capacity) ms_host[2 * s + 1] = (double)h->stage_n[s];
+    }
+    return IRBE_OK;
 }
 
 const char* irbe_last_error(irbe_handle h)
@@ -642,6 +725,7 @@ irbe_status irbe_destroy(irbe_handle h)
 {
     if (!h) return IRBE_EINVAL;
     hipStreamSynchronize(h->stream);
+    drain_timing(h);
     for (void* p : h->owned) hipFree(p);
     h->owned.clear();
     delete h;

@@ -134,6 +134,18 @@ struct irbe_ctx {
     void* gqscat = nullptr;           // real[N]
     double* ljpart = nullptr;         // [nb * 2 * kMaxTypesGrad^2]
     int64_t adj_nb = 0;               // blocks of the last pair-adjoint launch
+    int64_t pair_nb = 0;              // blocks of the last pair-force launch
+
+    // per-stage event timing (irbe_enable_timing)
+    bool timing = false;
+    struct Pending {
+        int stage;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> pending;
+    hipEvent_t open_start = nullptr;
+    double stage_ms[IRBE_N_STAGES] = {};
+    int64_t stage_n[IRBE_N_STAGES] = {};
 
     std::vector<void*> owned;
 };
@@ -152,6 +164,7 @@ hipError_t launch_build_lists(irbe_ctx* h);
 hipError_t launch_ksample(irbe_ctx* h, uint64_t step);
 hipError_t launch_rho(irbe_ctx* h, const void* grad, bool with_adjoint);
 hipError_t launch_pair_forces(irbe_ctx* h, uint64_t step, bool ev);
+hipError_t launch_pair_reduce(irbe_ctx* h);
 hipError_t launch_kspace_forces(irbe_ctx* h, void* force);
 hipError_t launch_energy_finalize(irbe_ctx* h, double* ev);
 hipError_t launch_sum_q2(irbe_ctx* h);

@@ -84,8 +84,6 @@ hipError_t launch_build_lists(irbe_ctx* h)
 {
     const int64_t n = h->cfg.n_atoms;
     const unsigned nb = (unsigned)blocks_for(n, kBlock);
-    hipError_t e = launch_fill_i32(h->stream, h->maxcnt, 0, 2);
-    if (e != hipSuccess) return e;
     const Geometry& g = h->geo;
     if (h->full_list)
         k_build_lists<true><<<nb, kBlock, 0, h->stream>>>(n, g.n_c, g.lo, g.hi, g.t_core, g.t_shell, h->spos, h->smol,

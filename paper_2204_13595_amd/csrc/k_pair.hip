@@ -229,8 +229,14 @@ static void launch_pair_t(irbe_ctx* h, uint64_t step, int bm_words, size_t lds)
         n, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core, h->shell, h->nshell,
         h->cap_shell, h->xoff, h->xidx, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->cfg.seed, step,
         bm_words, (real*)h->fsr, h->pair_part);
-    k_pair_reduce<<<1, kReduceBlock, 0, h->stream>>>(nb, h->pair_part, n, h->full_list ? 0 : 1, h->ev_pair,
-                                                     h->fcorr);
+    h->pair_nb = nb;
+}
+
+hipError_t launch_pair_reduce(irbe_ctx* h)
+{
+    k_pair_reduce<<<1, kReduceBlock, 0, h->stream>>>(h->pair_nb, h->pair_part, h->cfg.n_atoms, h->full_list ? 0 : 1,
+                                                     h->ev_pair, h->fcorr);
+    return hipGetLastError();
 }
 
 template <typename real>

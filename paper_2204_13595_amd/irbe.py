@@ -24,16 +24,20 @@ IRBE_VIRIAL = 2
 
 DBG = {
     "cell_start": 1, "cell_atoms": 2, "core_off": 3, "core_idx": 4, "shell_off": 5, "shell_idx": 6,
-    "batch_off": 7, "batch_rank": 8, "kvec": 9, "rho": 10, "fcorr": 11, "scalars": 12,
+    "batch_off": 7, "batch_rank": 8, "kvec": 9, "rho": 10, "fcorr": 11, "scalars": 12, "counts": 13,
 }
 _DBG_DTYPE = {1: np.int64, 2: np.int64, 3: np.int64, 4: np.int32, 5: np.int64, 6: np.int32, 7: np.int64,
-              8: np.int32, 9: np.int32, 10: np.float64, 11: np.float64, 12: np.float64}
+              8: np.int32, 9: np.int32, 10: np.float64, 11: np.float64, 12: np.float64, 13: np.int64}
 
 STATUS = {0: "IRBE_OK", -1: "IRBE_EINVAL", -2: "IRBE_ENOMEM", -3: "IRBE_EHIP", -4: "IRBE_ECAPACITY",
           -5: "IRBE_ESTATE", -6: "IRBE_EUNSUPPORTED", -7: "IRBE_ENONFINITE"}
 
 EXPORTED = ("irbe_create", "irbe_set_system", "irbe_update_parameters", "irbe_build_lists", "irbe_compute_forces",
-            "irbe_compute_forces_backward", "irbe_sync", "irbe_get_debug", "irbe_last_error", "irbe_destroy")
+            "irbe_compute_forces_backward", "irbe_sync", "irbe_enable_timing", "irbe_get_timing", "irbe_get_debug",
+            "irbe_last_error", "irbe_destroy")
+
+STAGES = ("bin", "lists", "quantize", "ksample", "rho", "pair", "pair_reduce", "kspace", "energy", "grad_gather",
+          "rho_adj", "pair_adj", "kspace_adj")
 
 
 class IRBEError(RuntimeError):
@@ -71,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.irbe_compute_forces.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_uint32, vp]
     L.irbe_compute_forces_backward.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, vp]
     L.irbe_sync.argtypes = [vp]
+    L.irbe_enable_timing.argtypes = [vp, ctypes.c_int32]
+    L.irbe_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.irbe_get_debug.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.irbe_last_error.argtypes = [vp]
     L.irbe_last_error.restype = ctypes.c_char_p
@@ -178,6 +184,16 @@ class Handle:
 
     def sync(self):
         self._check(self.lib.irbe_sync(self.h))
+
+    def enable_timing(self, on: bool = True):
+        self._check(self.lib.irbe_enable_timing(self.h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        """{stage: (total ms, launches)} since timing was enabled."""
+        buf = (ctypes.c_double * (2 * len(STAGES)))()
+        written = ctypes.c_int64()
+        self._check(self.lib.irbe_get_timing(self.h, buf, len(buf), ctypes.byref(written)))
+        return {name: (buf[2 * s], int(buf[2 * s + 1])) for s, name in enumerate(STAGES)}
 
     def debug(self, what: str) -> np.ndarray:
         sel = DBG[what]
