@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline forward figure")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (reference for the HBM byte counters of a profile)")
     return ap.parse_args()
 
 
@@ -128,6 +130,12 @@ def main():
         h.set_system(at, q, mol, w.lj_sigma, w.lj_eps)
         return h
 
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = make(args.p_shell, args.p_kspace)
     F = torch.empty((n, 3), dtype=dt, device=dev)
     G = torch.randn((n, 3), dtype=dt, device=dev, generator=torch.Generator(device=dev).manual_seed(5))

@@ -208,6 +208,14 @@ enum {
 };
 irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written);
 
+/* The same read-back restricted to the atoms rows_host[0..n_rows) (caller ids,
+ * host int64), for the per-atom selectors CORE_*, SHELL_* and BATCH_*: the
+ * *_OFF selectors give n_rows + 1 offsets, the *_IDX / BATCH_RANK selectors the
+ * concatenated rows. Meant for spot checks on systems too large to copy whole.
+ * Waits. IRBE_EINVAL for an id outside [0, N). */
+irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows_host, int64_t n_rows, void* dst_host,
+                                int64_t capacity, int64_t* written);
+
 /* Message of the last failure on h (or of the last failed irbe_create when h is
  * NULL). The string stays valid until the next call on h. */
 const char* irbe_last_error(irbe_handle h);

@@ -305,10 +305,26 @@ def sample_kspace(params: Params, step: int):
     return m, np.full(params.p_kspace, S / params.p_kspace), S
 
 
+def structure_factor(s, q, kvec, rows=None) -> np.ndarray:
+    """rho(k_l) = sum_j q_j e^{i k_l.r_j} (Eq. 2.4) over all atoms (or the rows): [n_k, 2]."""
+    s = _c(s, np.uint32)
+    q = _c(q, np.float64)
+    m = _c(kvec, np.int32)
+    rows_a = None if rows is None else _c(rows, np.int64)
+    n_rows = s.shape[0] if rows is None else rows_a.shape[0]
+    rho = np.zeros((m.shape[0], 2))
+    lib().orc_structure_factor(_p(s, _u32p), _p(q, _f64p), _p(rows_a, _i64p), n_rows, m.shape[0], _p(m, _i32p),
+                               _p(rho, _f64p))
+    return rho
+
+
 def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int = 0, mode: str = "rbl",
-            rows=None, s=None, lists: Lists | None = None, batches=None, kspace=None) -> Result:
+            rows=None, s=None, lists: Lists | None = None, batches=None, kspace=None, rho=None) -> Result:
     """One force evaluation. ``s`` (quantized positions), ``lists``, ``batches``
-    ((off, rank, w)) and ``kspace`` ((m, W, S)) may be given to freeze them."""
+    ((off, rank, w)) and ``kspace`` ((m, W, S)) may be given to freeze them.
+    With ``rows`` only those atoms are evaluated; ``rho`` (from
+    :func:`structure_factor` over all atoms) then gives their exact long-range
+    force, otherwise rho is summed over the rows only."""
     q = _c(q, np.float64)
     atom_type = _c(atom_type, np.int32)
     mol = _c(mol, np.int32)
@@ -355,9 +371,12 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
     L.orc_exclusions(ctypes.byref(sy), _p(s, _u32p), _p(q, _f64p), _p(rows_a, _i64p), n_rows, _p(x_off, _i64p),
                      _p(x_idx, _i64p), _p(f_x, _f64p), _p(e7x, _f64p))
     n_k = m.shape[0]
-    rho = np.zeros((n_k, 2))
-    L.orc_structure_factor(_p(s, _u32p), _p(q, _f64p), _p(rows_a, _i64p), n_rows, n_k, _p(m, _i32p),
-                           _p(rho, _f64p))
+    if rho is None:
+        rho = np.zeros((n_k, 2))
+        L.orc_structure_factor(_p(s, _u32p), _p(q, _f64p), _p(rows_a, _i64p), n_rows, n_k, _p(m, _i32p),
+                               _p(rho, _f64p))
+    else:
+        rho = _c(rho, np.float64)
     f_long = np.zeros((n_rows, 3))
     L.orc_kspace_force(ctypes.byref(sy), _p(s, _u32p), _p(q, _f64p), _p(rows_a, _i64p), n_rows, n_k,
                        _p(m, _i32p), _p(W, _f64p), _p(rho, _f64p), _p(f_long, _f64p))

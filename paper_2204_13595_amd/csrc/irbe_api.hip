@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -290,7 +291,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
         delete h;
         return fail(nullptr, IRBE_EINVAL, "floor(L / r_core) must be >= 3");
     }
-    if (h->geo.n_cells > kMaxCells) {
+    if (h->geo.n_cells > kMaxCells || h->geo.n_c > 1000) {
         delete h;
         return fail(nullptr, IRBE_EUNSUPPORTED, "too many cells");
     }
@@ -304,7 +305,10 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     const size_t n = (size_t)c.n_atoms;
     const size_t rs = h->real_size;
     const int64_t nb = blocks_for(c.n_atoms, kBlock);
-    const int64_t nb64 = blocks_for(c.n_atoms, 64);
+    // per-block partial buffers must cover the largest grid of any pair kernel:
+    // 64-thread blocks of the thread-per-atom kernels and the cooperative kernel's
+    // blocks of four wavefronts with kAtomsPerWave atoms each
+    const int64_t nb64 = std::max(blocks_for(c.n_atoms, 64), blocks_for(c.n_atoms, 4 * kAtomsPerWave));
     const int64_t nbr = rho_blocks(c.n_atoms);
     const size_t P = (size_t)c.p_kspace;
     const int nt2 = c.n_types * c.n_types;
@@ -324,6 +328,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc(h, &h->cell_count, (size_t)h->geo.n_cells));
     ALLOC(dalloc(h, &h->cell_start, (size_t)h->geo.n_cells + 1));
     ALLOC(dalloc(h, &h->cursor, (size_t)h->geo.n_cells));
+    ALLOC(dalloc(h, &h->cell_bound, (size_t)h->geo.n_c + 1));
     {
         int64_t m = h->geo.n_cells;
         do {
@@ -342,10 +347,14 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc_bytes(h, &h->sq_r, n * rs));
     ALLOC(dalloc(h, &h->smol, n));
     ALLOC(dalloc(h, &h->ncore, n));
+    h->p_stride = c.p_shell > 0 ? (c.p_shell + 3) / 4 * 4 : 0;
+    if (h->p_stride > 0) ALLOC(dalloc(h, &h->ranks, n * (size_t)h->p_stride));
     ALLOC(dalloc(h, &h->nshell, n));
     ALLOC(dalloc_bytes(h, &h->fsr, 3 * n * rs));
     ALLOC(dalloc(h, &h->pair_part, (size_t)nb64 * kPairPartials));
+    h->part_blocks = nb64;
     ALLOC(dalloc(h, &h->fcorr, 3));
+    ALLOC(dalloc(h, &h->pair_slices, 256 * 12));
     ALLOC(dalloc(h, &h->ev_pair, kPairPartials));
     ALLOC(dalloc(h, &h->kvec, P));
     ALLOC(dalloc(h, &h->kcoef, 4 * P));
@@ -362,6 +371,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc_bytes(h, &h->gqself, n * rs));
     ALLOC(dalloc_bytes(h, &h->gqscat, n * rs));
     ALLOC(dalloc(h, &h->ljpart, (size_t)nb64 * 2 * kMaxTypesGrad * kMaxTypesGrad));
+    ALLOC(dalloc(h, &h->lj_slices, 256 * 2 * kMaxTypesGrad * kMaxTypesGrad));
 #undef ALLOC
     if (e == hipSuccess) {
         const double L = c.box_length;
@@ -378,6 +388,11 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->ktab, U.data(), U.size() * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream);
+    std::vector<uint32_t> bound((size_t)h->geo.n_c + 1);
+    for (int32_t c = 0; c <= h->geo.n_c; ++c)
+        bound[c] = (uint32_t)((((uint64_t)c << 32) + (uint64_t)h->geo.n_c - 1) / (uint64_t)h->geo.n_c);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->cell_bound, bound.data(), bound.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -489,6 +504,7 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
     if (!pos) return fail(h, IRBE_EINVAL, "irbe_build_lists: null positions");
     if (!h->have_system) return fail(h, IRBE_ESTATE, "irbe_build_lists before irbe_set_system");
     h->have_lists = false;
+    h->ranks_valid = false;
     IRBE_STAGE(h, IRBE_STAGE_BIN, launch_bin(h, pos), "binning");
     for (int attempt = 0; attempt < 3; ++attempt) {
         IRBE_TRY(h, launch_fill_i32(h->stream, h->maxcnt, 0, 2), "list build");
@@ -505,6 +521,7 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
         }
         const int32_t nc = std::max(h->cap_core, round_up32(1.15 * mx[0] + 32.0));
         const int32_t ns = std::max(h->cap_shell, round_up32(1.15 * mx[1] + 32.0));
+        if (ns > 65535) return fail(h, IRBE_ECAPACITY, "more than 65535 list entries per atom");
         IRBE_TRY(h, alloc_lists(h, nc, ns), "grow lists");
     }
     return fail(h, IRBE_ECAPACITY, "list capacity did not converge");
@@ -608,25 +625,26 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
         IRBE_TRY(h, d2h(cnt.data(), is_core ? h->ncore : h->nshell, (size_t)n * 4), "debug");
         int32_t stride = is_core ? h->cap_core : h->cap_shell;
         std::vector<int32_t> rows;
+        std::vector<uint16_t> rk;
         if (is_batch) {
-            stride = h->full_list ? h->cap_shell : std::max(1, std::min(h->cfg.p_shell, h->cap_shell));
-            int32_t* dev = nullptr;
-            IRBE_TRY(h, hipMalloc(&dev, (size_t)n * stride * 4), "debug");
-            hipError_t e = launch_batch_debug(h, h->last_force_step, dev, stride);
-            if (e == hipSuccess) {
-                rows.resize((size_t)n * stride);
-                e = d2h(rows.data(), dev, rows.size() * 4);
+            // the ranks the pair kernel used for the step of the last force evaluation
+            if (!h->full_list && !(h->ranks_valid && h->ranks_step == h->last_force_step))
+                return fail(h, IRBE_ESTATE, "batch ranks of the last force step are not available");
+            if (!h->full_list) {
+                rk.resize((size_t)n * h->p_stride);
+                IRBE_TRY(h, d2h(rk.data(), h->ranks, rk.size() * 2), "debug");
             }
-            hipFree(dev);
-            IRBE_TRY(h, e, "debug batches");
-            for (int64_t k = 0; k < n; ++k)
-                if (!h->full_list && cnt[k] > h->cfg.p_shell) cnt[k] = h->cfg.p_shell;
         } else {
             rows.resize((size_t)n * stride);
             IRBE_TRY(h, d2h(rows.data(), is_core ? h->core : h->shell, rows.size() * 4), "debug");
         }
+        auto row_len = [&](int64_t k) -> int64_t {
+            if (is_core && h->full_list) return 0;
+            if (is_batch && !h->full_list) return std::min<int64_t>(cnt[k], h->cfg.p_shell);
+            return cnt[k];
+        };
         std::vector<int64_t> off((size_t)n + 1, 0);
-        for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + (is_core && h->full_list ? 0 : cnt[rank[i]]);
+        for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + row_len(rank[i]);
         if (want_off) {
             copy_out(off.data(), 8, n + 1);
             return IRBE_OK;
@@ -634,9 +652,10 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
         std::vector<int32_t> idx((size_t)off[n]);
         for (int64_t i = 0; i < n; ++i) {
             const int64_t k = rank[i];
+            const bool sampled = is_batch && !h->full_list && cnt[k] > h->cfg.p_shell;
             for (int64_t t = 0; t < off[i + 1] - off[i]; ++t) {
-                const int32_t v = rows[(size_t)k * stride + t];
-                idx[off[i] + t] = is_batch ? v : perm[v];
+                if (is_batch) idx[off[i] + t] = sampled ? (int32_t)rk[(size_t)k * h->p_stride + t] : (int32_t)t;
+                else idx[off[i] + t] = perm[rows[(size_t)k * stride + t]];
             }
         }
         copy_out(idx.data(), 4, (int64_t)idx.size());
@@ -687,6 +706,67 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
     default:
         return fail(h, IRBE_EINVAL, "unknown debug selector");
     }
+}
+
+irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows_host, int64_t n_rows, void* dst_host,
+                                int64_t capacity, int64_t* written)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!written || capacity < 0 || (capacity > 0 && !dst_host) || n_rows < 0 || (n_rows > 0 && !rows_host))
+        return fail(h, IRBE_EINVAL, "bad debug buffer");
+    const bool is_core = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_CORE_IDX;
+    const bool is_shell = what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_SHELL_IDX;
+    const bool is_batch = what == IRBE_DBG_BATCH_OFF || what == IRBE_DBG_BATCH_RANK;
+    if (!is_core && !is_shell && !is_batch) return fail(h, IRBE_EINVAL, "selector is not per atom");
+    if (!h->have_lists) return fail(h, IRBE_ESTATE, "no lists built");
+    if (is_batch && !h->full_list && !(h->have_force_step && h->ranks_valid && h->ranks_step == h->last_force_step))
+        return fail(h, IRBE_ESTATE, "batch ranks of the last force step are not available");
+    const int64_t n = h->cfg.n_atoms;
+    for (int64_t r = 0; r < n_rows; ++r)
+        if (rows_host[r] < 0 || rows_host[r] >= n) return fail(h, IRBE_EINVAL, "row id out of range");
+    IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
+    const bool want_off = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_BATCH_OFF;
+    std::vector<int32_t> perm;
+    if (!want_off && !is_batch) {
+        perm.resize((size_t)n);
+        IRBE_TRY(h, hipMemcpy(perm.data(), h->perm, (size_t)n * 4, hipMemcpyDeviceToHost), "debug");
+    }
+    std::vector<int64_t> off((size_t)n_rows + 1, 0);
+    std::vector<int32_t> idx;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int32_t k = 0, cnt = 0;
+        IRBE_TRY(h, hipMemcpy(&k, h->rank + rows_host[r], 4, hipMemcpyDeviceToHost), "debug");
+        IRBE_TRY(h, hipMemcpy(&cnt, (is_core ? h->ncore : h->nshell) + k, 4, hipMemcpyDeviceToHost), "debug");
+        int64_t len = (is_core && h->full_list) ? 0 : cnt;
+        const bool sampled = is_batch && !h->full_list && cnt > h->cfg.p_shell;
+        if (is_batch && !h->full_list) len = std::min<int64_t>(cnt, h->cfg.p_shell);
+        off[r + 1] = off[r] + len;
+        if (want_off || len == 0) continue;
+        if (is_batch) {
+            if (sampled) {
+                std::vector<uint16_t> rk((size_t)len);
+                IRBE_TRY(h, hipMemcpy(rk.data(), h->ranks + (int64_t)k * h->p_stride, (size_t)len * 2,
+                                      hipMemcpyDeviceToHost),
+                         "debug");
+                for (auto v : rk) idx.push_back((int32_t)v);
+            } else {
+                for (int64_t t = 0; t < len; ++t) idx.push_back((int32_t)t);
+            }
+        } else {
+            std::vector<int32_t> row((size_t)len);
+            const int32_t* src = is_core ? h->core + (int64_t)k * h->cap_core : h->shell + (int64_t)k * h->cap_shell;
+            IRBE_TRY(h, hipMemcpy(row.data(), src, (size_t)len * 4, hipMemcpyDeviceToHost), "debug");
+            for (auto v : row) idx.push_back(perm[v]);
+        }
+    }
+    if (want_off) {
+        *written = n_rows + 1;
+        std::memcpy(dst_host, off.data(), (size_t)std::min<int64_t>(capacity, n_rows + 1) * 8);
+    } else {
+        *written = (int64_t)idx.size();
+        if (capacity > 0) std::memcpy(dst_host, idx.data(), (size_t)std::min<int64_t>(capacity, *written) * 4);
+    }
+    return IRBE_OK;
 }
 
 irbe_status irbe_enable_timing(irbe_handle h, int32_t enable)

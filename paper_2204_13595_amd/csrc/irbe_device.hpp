@@ -21,10 +21,10 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -125,6 +125,24 @@ struct Math;
 template <>
 struct Math<float> {
     static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
+    // erfc(x) for x >= 0 given ex = exp(-x^2): the Chebyshev-fitted form of
+    // Numerical Recipes (Press et al., Sec. 6.2, "erfcc"), fractional error
+    // below 1.2e-7: erfc(x) = t exp(-x^2 + P(t)), t = 1/(1 + x/2).
+    static __device__ __forceinline__ float erfc_ex(float x, float ex)
+    {
+        const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+        float p = 0.17087277f;
+        p = fmaf(p, t, -0.82215223f);
+        p = fmaf(p, t, 1.48851587f);
+        p = fmaf(p, t, -1.13520398f);
+        p = fmaf(p, t, 0.27886807f);
+        p = fmaf(p, t, -0.18628806f);
+        p = fmaf(p, t, 0.09678418f);
+        p = fmaf(p, t, 0.37409196f);
+        p = fmaf(p, t, 1.00002368f);
+        p = fmaf(p, t, -1.26551223f);
+        return t * ex * __expf(p);
+    }
     static __device__ __forceinline__ float erf_(float x) { return erff(x); }
     static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
     static __device__ __forceinline__ float rsqrt_(float x) { return rsqrtf(x); }
@@ -140,6 +158,7 @@ struct Math<float> {
 template <>
 struct Math<double> {
     static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
+    static __device__ __forceinline__ double erfc_ex(double x, double) { return erfc(x); }
     static __device__ __forceinline__ double erf_(double x) { return erf(x); }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
     static __device__ __forceinline__ double rsqrt_(double x) { return rsqrt(x); }

@@ -21,6 +21,7 @@ constexpr int kPairPartials = 16;    // FP64 values per block of the pair kernel
 constexpr int kRhoChunk = 16;        // k-vectors per block row of the structure factor
 constexpr int kRhoAtomsPerThread = 8;
 constexpr int kMaxTypesGrad = 4;     // LJ parameter gradients: n_types <= 4
+constexpr int kAtomsPerWave = 8;     // atoms per wavefront in the cooperative pair kernels
 
 // Per-k constants of the force kernels: k (3), then coefficient products.
 template <typename real>
@@ -98,6 +99,7 @@ struct irbe_ctx {
     uint4* sq = nullptr;              // [N] quantized position + cell, caller order
     int32_t* cell_count = nullptr;    // [n_cells]
     int32_t* cell_start = nullptr;    // [n_cells + 1]
+    uint32_t* cell_bound = nullptr;   // [n_c + 1] first fixed-point coordinate of each cell row/column
     int32_t* cursor = nullptr;        // [n_cells]
     std::vector<int32_t*> scan_levels;
     std::vector<int64_t> scan_sizes;
@@ -115,6 +117,7 @@ struct irbe_ctx {
     void* fsr = nullptr;              // real[3N] sorted short-range (+ excluded-pair) force
     double* pair_part = nullptr;      // [nb * kPairPartials]
     double* fcorr = nullptr;          // [3]
+    double* pair_slices = nullptr;    // [256 * 12] first-stage sums of pair_part
     double* ev_pair = nullptr;        // [kPairPartials] reduced pair partials
 
     int4* kvec = nullptr;             // [P]
@@ -133,8 +136,14 @@ struct irbe_ctx {
     void* gqself = nullptr;           // real[N]
     void* gqscat = nullptr;           // real[N]
     double* ljpart = nullptr;         // [nb * 2 * kMaxTypesGrad^2]
+    double* lj_slices = nullptr;      // [256 * 2 * kMaxTypesGrad^2] first-stage sums of ljpart
     int64_t adj_nb = 0;               // blocks of the last pair-adjoint launch
     int64_t pair_nb = 0;              // blocks of the last pair-force launch
+    int64_t part_blocks = 0;          // capacity (blocks) of pair_part and ljpart
+    uint16_t* ranks = nullptr;        // [N * p_stride] shell batch ranks of the current step
+    int32_t p_stride = 0;
+    bool ranks_valid = false;         // ranks hold the draw of ranks_step for the current lists
+    uint64_t ranks_step = 0;
 
     // per-stage event timing (irbe_enable_timing)
     bool timing = false;
@@ -171,6 +180,5 @@ hipError_t launch_sum_q2(irbe_ctx* h);
 hipError_t launch_gather_grad(irbe_ctx* h, const void* grad);
 hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool want_lj);
 hipError_t launch_kspace_adjoint(irbe_ctx* h, const void* grad, void* grad_pos, void* grad_q, double* grad_lj);
-hipError_t launch_batch_debug(irbe_ctx* h, uint64_t step, int32_t* ranks_dev, int32_t stride);
 
 }  // namespace irbe

@@ -403,15 +403,35 @@ __global__ __launch_bounds__(kBlock) void k_kspace_adjoint(int64_t n, int P, con
     if (gq) gq[i] = gqself[k] + gqscat[k] - pq;
 }
 
-__global__ __launch_bounds__(kReduceBlock) void k_lj_reduce(int64_t nb, const double* __restrict__ part, int n_types,
-                                                            double* __restrict__ out)
+// LJ table gradients: fixed-order two-stage sum of the per-block partials
+// (slices of contiguous blocks, then the slices).
+constexpr int kLjSlices = 256;
+
+__global__ __launch_bounds__(kReduceBlock) void k_lj_reduce1(int64_t nb, const double* __restrict__ part,
+                                                             double* __restrict__ slices)
+{
+    constexpr int NLJ = 2 * kMaxTypesGrad * kMaxTypesGrad;
+    __shared__ double lds[NLJ * (kReduceBlock / 64)];
+    const int64_t per = (nb + kLjSlices - 1) / kLjSlices;
+    const int64_t b0 = blockIdx.x * per, b1 = min(nb, b0 + per);
+    double vals[NLJ];
+    for (int v = 0; v < NLJ; ++v) vals[v] = 0.0;
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += kReduceBlock)
+        for (int v = 0; v < NLJ; ++v) vals[v] += part[b * NLJ + v];
+    double o;
+    block_sum_vec<NLJ, kReduceBlock>(vals, lds, threadIdx.x, o);
+    if (threadIdx.x < NLJ) slices[blockIdx.x * NLJ + threadIdx.x] = o;
+}
+
+__global__ __launch_bounds__(kReduceBlock) void k_lj_reduce2(const double* __restrict__ slices, int n_types,
+                                                             double* __restrict__ out)
 {
     constexpr int NLJ = 2 * kMaxTypesGrad * kMaxTypesGrad;
     __shared__ double lds[NLJ * (kReduceBlock / 64)];
     double vals[NLJ];
     for (int v = 0; v < NLJ; ++v) vals[v] = 0.0;
-    for (int64_t b = threadIdx.x; b < nb; b += kReduceBlock)
-        for (int v = 0; v < NLJ; ++v) vals[v] += part[b * NLJ + v];
+    for (int b = threadIdx.x; b < kLjSlices; b += kReduceBlock)
+        for (int v = 0; v < NLJ; ++v) vals[v] += slices[b * NLJ + v];
     double o;
     block_sum_vec<NLJ, kReduceBlock>(vals, lds, threadIdx.x, o);
     if (threadIdx.x < NLJ) {
@@ -438,7 +458,8 @@ hipError_t launch_kspace_adjoint(irbe_ctx* h, const void* grad, void* grad_pos, 
             (const KAdj<float>*)h->kadj, (const float*)h->gself, (const float*)h->gscat, (const float*)h->gqself,
             (const float*)h->gqscat, (float*)grad_pos, (float*)grad_q);
     if (grad_lj) {
-        k_lj_reduce<<<1, kReduceBlock, 0, h->stream>>>(h->adj_nb, h->ljpart, h->cfg.n_types, grad_lj);
+        k_lj_reduce1<<<kLjSlices, kReduceBlock, 0, h->stream>>>(h->adj_nb, h->ljpart, h->lj_slices);
+        k_lj_reduce2<<<1, kReduceBlock, 0, h->stream>>>(h->lj_slices, h->cfg.n_types, grad_lj);
     }
     return hipGetLastError();
 }

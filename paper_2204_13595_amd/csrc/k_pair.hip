@@ -38,7 +38,7 @@ __device__ __forceinline__ real pair_phi(real r2, real qq, const LJ<real>& lj, c
     const real r = r2 * rinv;
     const real br = pp.beta * r;
     const real ex = M::exp_(-br * br);
-    const real ec = M::erfc_(br);
+    const real ec = M::erfc_ex(br, ex);
     const real rinv2 = rinv * rinv;
     const real r6 = rinv2 * rinv2 * rinv2;
     real phi = -qq * rinv2 * (ec * rinv + pp.cgauss * ex);
@@ -65,158 +65,227 @@ __device__ __forceinline__ real excl_psi(real r2, real qq, const PairParams<real
     return -qq * rinv2 * (pp.cgauss * ex - ef * rinv);
 }
 
+// Force, energy and virial sums of one list (core or shell batch).
 template <typename real>
-struct Acc3 {
-    real x = 0, y = 0, z = 0;
+struct PairSum {
+    real fx = 0, fy = 0, fz = 0;
+    real uc = 0, ul = 0;
+    real v[6] = {0, 0, 0, 0, 0, 0};
 };
 
-template <typename real, bool FULL, bool EV, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_pair_forces(
-    int64_t n, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
+template <typename real, bool EV>
+__device__ __forceinline__ void add_pair(PairSum<real>& a, uint4 si, real qi, uint4 sj, real qj, const LJ<real>* lrow,
+                                         const PairParams<real>& pp)
+{
+    real dx, dy, dz;
+    separation(si, sj, pp.quantum, dx, dy, dz);
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    real uc, ul;
+    const real phi = pair_phi<real, EV>(r2, qi * qj, lrow[sj.w], pp, uc, ul);
+    a.fx += phi * dx;
+    a.fy += phi * dy;
+    a.fz += phi * dz;
+    if (EV) {
+        a.uc += uc;
+        a.ul += ul;
+        a.v[0] += phi * dx * dx; a.v[1] += phi * dy * dy; a.v[2] += phi * dz * dz;
+        a.v[3] += phi * dx * dy; a.v[4] += phi * dx * dz; a.v[5] += phi * dy * dz;
+    }
+}
+
+// One Floyd step: draw r in [0, t], insert r or (if taken) t into the bitmap.
+template <int BLOCK>
+__device__ __forceinline__ int floyd_step(WordStream& st, uint32_t* bitmap, int t)
+{
+    const int r = (int)st.below((uint32_t)t + 1u);
+    const bool taken = (bitmap[(r >> 5) * BLOCK + threadIdx.x] >> (r & 31)) & 1u;
+    const int v = taken ? t : r;
+    bitmap[(v >> 5) * BLOCK + threadIdx.x] |= 1u << (v & 31);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Forward, cooperative form: the shell batch ranks are drawn first (one thread
+// per atom, Floyd's algorithm into a row of 16-bit ranks), then one wavefront
+// evaluates one atom at a time with its lanes spread over the atom's core
+// list, its batch and its excluded pairs. Each atom's list rows are then read
+// by one wavefront at one time (coalesced for the core and full lists, one
+// short burst of lines for the sampled shell ranks) instead of entry by entry
+// over the whole kernel.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_draw_batches(int64_t n, const int32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ nshell, int p_shell, int p_stride,
+                                                        uint64_t seed, uint64_t step, uint16_t* __restrict__ ranks)
+{
+    extern __shared__ uint32_t bitmap[];
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= n) return;
+    const int ns = nshell[k];
+    if (ns <= p_shell) return;
+    const int words = (ns + 31) >> 5;
+    for (int t = 0; t < words; ++t) bitmap[t * BLOCK + threadIdx.x] = 0u;
+    WordStream st(seed, step, (uint32_t)perm[k], kTagShell);
+    uint16_t* out = ranks + k * (int64_t)p_stride;
+    const int t0 = ns - p_shell;
+    int c = 0;
+    for (; c + 4 <= p_shell; c += 4) {
+        const uint32_t v0 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c);
+        const uint32_t v1 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c + 1);
+        const uint32_t v2 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c + 2);
+        const uint32_t v3 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c + 3);
+        *(uint2*)(out + c) = make_uint2(v0 | (v1 << 16), v2 | (v3 << 16));
+    }
+    for (; c < p_shell; ++c) out[c] = (uint16_t)floyd_step<BLOCK>(st, bitmap, t0 + c);
+}
+
+template <typename real>
+__device__ __forceinline__ real wave_sum_r(real v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+constexpr int kCoopBlock = 256;
+
+template <typename real, bool FULL, bool EV>
+__global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
+    int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const int32_t* __restrict__ xoff,
-    const int32_t* __restrict__ xidx, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, uint64_t seed,
-    uint64_t step, int bm_words, real* __restrict__ fsr, double* __restrict__ part)
+    const int32_t* __restrict__ xidx, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, int p_stride,
+    const uint16_t* __restrict__ ranks, real* __restrict__ fsr, double* __restrict__ part)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    LJ<real>* lj = (LJ<real>*)smem_raw;
+    __shared__ LJ<real> lj[256];
+    __shared__ double red[kPairPartials * (kCoopBlock / 64)];
     const int nt2 = n_types * n_types;
-    uint32_t* bitmap = (uint32_t*)(smem_raw + ((sizeof(LJ<real>) * nt2 + 15) / 16) * 16);
-    __shared__ double red[kPairPartials * (BLOCK / 64)];
-    for (int t = threadIdx.x; t < nt2; t += BLOCK) lj[t] = lj_g[t];
+    for (int t = threadIdx.x; t < nt2; t += kCoopBlock) lj[t] = lj_g[t];
     __syncthreads();
-
-    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    Acc3<real> fc, fs, fx;
-    real uc_c = 0, ul_c = 0, uc_s = 0, ul_s = 0, ux = 0;
-    real vc[6] = {0, 0, 0, 0, 0, 0}, vs[6] = {0, 0, 0, 0, 0, 0}, vx[6] = {0, 0, 0, 0, 0, 0};
-    real w = 1;
-    if (k < n) {
-        const uint4 si = spos[k];
-        const real qi = sqr[k] * pp.ke;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (kCoopBlock / 64) + (threadIdx.x >> 6);
+    const int64_t a0 = gw * apw;
+    const int64_t a1 = min(n, a0 + apw);
+    double fc_sum[3] = {0.0, 0.0, 0.0};
+    PairSum<real> ev;  // per-lane energy/virial totals (forces unused)
+    for (int64_t a = a0; a < a1; ++a) {
+        const uint4 si = spos[a];
+        const real qi = sqr[a] * pp.ke;
         const LJ<real>* lrow = lj + (int)si.w * n_types;
-        // core pairs
-        const int nc = ncore[k];
-        const int32_t* crow = core + k * (int64_t)cap_core;
-        for (int c = 0; c < nc; ++c) {
+        PairSum<real> pc, ps, px;
+        const int nc = ncore[a];
+        const int32_t* crow = core + a * (int64_t)cap_core;
+        for (int c = lane; c < nc; c += 64) {
             const int j = crow[c];
-            const uint4 sj = spos[j];
-            real dx, dy, dz;
-            separation(si, sj, pp.quantum, dx, dy, dz);
-            const real r2 = dx * dx + dy * dy + dz * dz;
-            real uc, ul;
-            const real phi = pair_phi<real, EV>(r2, qi * sqr[j], lrow[sj.w], pp, uc, ul);
-            fc.x += phi * dx;
-            fc.y += phi * dy;
-            fc.z += phi * dz;
-            if (EV) {
-                uc_c += uc;
-                ul_c += ul;
-                vc[0] += phi * dx * dx; vc[1] += phi * dy * dy; vc[2] += phi * dz * dz;
-                vc[3] += phi * dx * dy; vc[4] += phi * dx * dz; vc[5] += phi * dy * dz;
-            }
+            add_pair<real, EV>(pc, si, qi, spos[j], sqr[j], lrow, pp);
         }
-        // shell: every member, or the Floyd batch
-        const int ns = nshell[k];
-        const int32_t* srow = shell + k * (int64_t)cap_shell;
+        const int ns = nshell[a];
+        const int32_t* srow = shell + a * (int64_t)cap_shell;
         const bool sample = !FULL && ns > p_shell;
-        const int cnt = sample ? p_shell : ns;
-        WordStream st(seed, step, (uint32_t)perm[k], kTagShell);
+        real w = 1;
         if (sample) {
             w = (real)((double)ns / (double)p_shell);
-            const int words = (ns + 31) >> 5;
-            for (int t = 0; t < words; ++t) bitmap[t * BLOCK + threadIdx.x] = 0u;
-        }
-        for (int c = 0; c < cnt; ++c) {
-            int v = c;
-            if (sample) {
-                const int t = ns - p_shell + c;
-                const int r = (int)st.below((uint32_t)t + 1u);
-                uint32_t* wr = &bitmap[(r >> 5) * BLOCK + threadIdx.x];
-                const bool taken = (*wr >> (r & 31)) & 1u;
-                v = taken ? t : r;
-                bitmap[(v >> 5) * BLOCK + threadIdx.x] |= 1u << (v & 31);
+            const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+            for (int c = lane; c < p_shell; c += 64) {
+                const int j = srow[rrow[c]];
+                add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
             }
-            const int j = srow[v];
-            const uint4 sj = spos[j];
-            real dx, dy, dz;
-            separation(si, sj, pp.quantum, dx, dy, dz);
-            const real r2 = dx * dx + dy * dy + dz * dz;
-            real uc, ul;
-            const real phi = pair_phi<real, EV>(r2, qi * sqr[j], lrow[sj.w], pp, uc, ul);
-            fs.x += phi * dx;
-            fs.y += phi * dy;
-            fs.z += phi * dz;
-            if (EV) {
-                uc_s += uc;
-                ul_s += ul;
-                vs[0] += phi * dx * dx; vs[1] += phi * dy * dy; vs[2] += phi * dz * dz;
-                vs[3] += phi * dx * dy; vs[4] += phi * dx * dz; vs[5] += phi * dy * dz;
+        } else {
+            for (int c = lane; c < ns; c += 64) {
+                const int j = srow[c];
+                add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
             }
         }
-        // excluded pairs: remove their reciprocal-space erf(beta r)/r interaction
-        const int ic = perm[k];
-        for (int x = xoff[ic]; x < xoff[ic + 1]; ++x) {
-            const int j = rank[xidx[x]];
+        const int ia = perm[a];
+        const int xb = xoff[ia], nx = xoff[ia + 1] - xb;
+        for (int c = lane; c < nx; c += 64) {
+            const int j = rank[xidx[xb + c]];
             const uint4 sj = spos[j];
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
             const real r2 = dx * dx + dy * dy + dz * dz;
             real u;
             const real psi = excl_psi<real, EV>(r2, qi * sqr[j], pp, u);
-            fx.x += psi * dx;
-            fx.y += psi * dy;
-            fx.z += psi * dz;
+            px.fx += psi * dx;
+            px.fy += psi * dy;
+            px.fz += psi * dz;
             if (EV) {
-                ux += u;
-                vx[0] += psi * dx * dx; vx[1] += psi * dy * dy; vx[2] += psi * dz * dz;
-                vx[3] += psi * dx * dy; vx[4] += psi * dx * dz; vx[5] += psi * dy * dz;
+                px.uc += u;
+                px.v[0] += psi * dx * dx; px.v[1] += psi * dy * dy; px.v[2] += psi * dz * dz;
+                px.v[3] += psi * dx * dy; px.v[4] += psi * dx * dz; px.v[5] += psi * dy * dz;
             }
         }
-        const real px = fc.x + w * fs.x, py = fc.y + w * fs.y, pz = fc.z + w * fs.z;
-        fsr[3 * k + 0] = px + fx.x;
-        fsr[3 * k + 1] = py + fx.y;
-        fsr[3 * k + 2] = pz + fx.z;
-        fc.x = px; fc.y = py; fc.z = pz;
+        const real fx = wave_sum_r(pc.fx + w * ps.fx);
+        const real fy = wave_sum_r(pc.fy + w * ps.fy);
+        const real fz = wave_sum_r(pc.fz + w * ps.fz);
+        const real ex = wave_sum_r(px.fx);
+        const real ey = wave_sum_r(px.fy);
+        const real ez = wave_sum_r(px.fz);
+        if (lane == 0) {
+            fsr[3 * a + 0] = fx + ex;
+            fsr[3 * a + 1] = fy + ey;
+            fsr[3 * a + 2] = fz + ez;
+            fc_sum[0] += (double)fx;
+            fc_sum[1] += (double)fy;
+            fc_sum[2] += (double)fz;
+        }
+        if (EV) {
+            ev.uc += pc.uc + w * ps.uc;
+            ev.ul += pc.ul + w * ps.ul;
+            ev.fx += px.uc;  // excluded-pair energy
+#pragma unroll
+            for (int c = 0; c < 6; ++c) ev.v[c] += pc.v[c] + w * ps.v[c] + px.v[c];
+        }
     }
     double vals[kPairPartials];
-    vals[0] = (double)fc.x;
-    vals[1] = (double)fc.y;
-    vals[2] = (double)fc.z;
+    vals[0] = fc_sum[0];
+    vals[1] = fc_sum[1];
+    vals[2] = fc_sum[2];
     if (EV) {
-        vals[3] = 0.5 * ((double)uc_c + (double)w * (double)uc_s);
-        vals[4] = 0.5 * ((double)ul_c + (double)w * (double)ul_s);
-        vals[5] = 0.5 * (double)ux;
-        for (int c = 0; c < 6; ++c) vals[6 + c] = -0.5 * ((double)vc[c] + (double)w * (double)vs[c] + (double)vx[c]);
+        vals[3] = 0.5 * (double)ev.uc;
+        vals[4] = 0.5 * (double)ev.ul;
+        vals[5] = 0.5 * (double)ev.fx;
+        for (int c = 0; c < 6; ++c) vals[6 + c] = -0.5 * (double)ev.v[c];
     } else {
         for (int c = 3; c < 12; ++c) vals[c] = 0.0;
     }
     for (int c = 12; c < kPairPartials; ++c) vals[c] = 0.0;
     double out;
-    block_sum_vec<12, BLOCK>(vals, red, threadIdx.x, out);
+    block_sum_vec<12, kCoopBlock>(vals, red, threadIdx.x, out);
     if (threadIdx.x < 12) part[blockIdx.x * (int64_t)kPairPartials + threadIdx.x] = out;
 }
 
-// Reduce the per-block partials in a fixed order: ev_pair[0..11] = totals,
-// fcorr = (sum of the uncorrected short-range force) / N when rbl.
-__global__ __launch_bounds__(kReduceBlock) void k_pair_reduce(int64_t nb, const double* __restrict__ part, int64_t n,
-                                                              int rbl, double* __restrict__ ev_pair,
-                                                              double* __restrict__ fcorr)
+// Batch ranks of every atom for `step` (kept until the lists or the step change).
+static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
 {
-    __shared__ double lds[12 * (kReduceBlock / 64)];
-    double vals[12];
-    for (int c = 0; c < 12; ++c) vals[c] = 0.0;
-    for (int64_t b = threadIdx.x; b < nb; b += kReduceBlock)
-        for (int c = 0; c < 12; ++c) vals[c] += part[b * kPairPartials + c];
-    double out;
-    block_sum_vec<12, kReduceBlock>(vals, lds, threadIdx.x, out);
-    if (threadIdx.x < 12) ev_pair[threadIdx.x] = out;
-    if (threadIdx.x < 3) fcorr[threadIdx.x] = rbl ? out / (double)n : 0.0;
+    if (h->full_list || (h->ranks_valid && h->ranks_step == step)) return hipSuccess;
+    const int64_t n = h->cfg.n_atoms;
+    const int words = (h->max_shell + 31) / 32;
+    int block = 256;
+    while (block > 64 && (size_t)words * block * 4 > 32 * 1024) block /= 2;
+    const size_t lds = (size_t)words * block * 4;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)blocks_for(n, block);
+    if (block == 256)
+        k_draw_batches<256><<<nb, 256, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
+                                                         h->cfg.seed, step, h->ranks);
+    else if (block == 128)
+        k_draw_batches<128><<<nb, 128, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
+                                                         h->cfg.seed, step, h->ranks);
+    else
+        k_draw_batches<64><<<nb, 64, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
+                                                       h->cfg.seed, step, h->ranks);
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        h->ranks_valid = true;
+        h->ranks_step = step;
+    }
+    return e;
 }
 
-template <typename real, bool FULL, bool EV, int BLOCK>
-static void launch_pair_t(irbe_ctx* h, uint64_t step, int bm_words, size_t lds)
+template <typename real, bool FULL, bool EV>
+static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
 {
     const int64_t n = h->cfg.n_atoms;
     PairParams<real> pp;
@@ -224,88 +293,73 @@ static void launch_pair_t(irbe_ctx* h, uint64_t step, int bm_words, size_t lds)
     pp.beta = (real)h->cfg.ewald_beta;
     pp.cgauss = (real)(2.0 * h->cfg.ewald_beta / 1.7724538509055160273);
     pp.ke = (real)h->cfg.coulomb_k;
-    const unsigned nb = (unsigned)blocks_for(n, BLOCK);
-    k_pair_forces<real, FULL, EV, BLOCK><<<nb, BLOCK, lds, h->stream>>>(
-        n, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core, h->shell, h->nshell,
-        h->cap_shell, h->xoff, h->xidx, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->cfg.seed, step,
-        bm_words, (real*)h->fsr, h->pair_part);
+    hipError_t e = launch_draw(h, step);
+    if (e != hipSuccess) return e;
+    const int64_t waves = blocks_for(n, kAtomsPerWave);
+    const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
+    if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
+    k_pair_coop<real, FULL, EV><<<nb, kCoopBlock, 0, h->stream>>>(
+        n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core,
+        h->shell, h->nshell, h->cap_shell, h->xoff, h->xidx, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell,
+        h->p_stride, h->ranks, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
-}
-
-hipError_t launch_pair_reduce(irbe_ctx* h)
-{
-    k_pair_reduce<<<1, kReduceBlock, 0, h->stream>>>(h->pair_nb, h->pair_part, h->cfg.n_atoms, h->full_list ? 0 : 1,
-                                                     h->ev_pair, h->fcorr);
     return hipGetLastError();
 }
 
 template <typename real>
-static hipError_t launch_pair_r(irbe_ctx* h, uint64_t step, bool ev)
+static hipError_t launch_coop_r(irbe_ctx* h, uint64_t step, bool ev)
 {
-    const int words = h->full_list ? 0 : (h->max_shell + 31) / 32;
-    const size_t lj_bytes = ((sizeof(LJ<real>) * h->cfg.n_types * h->cfg.n_types + 15) / 16) * 16;
-    const size_t lds256 = lj_bytes + (size_t)words * 256 * 4;
-    const size_t lds64 = lj_bytes + (size_t)words * 64 * 4;
-    const bool big = lds256 > 48 * 1024;
-    if (big && lds64 > 64 * 1024) return hipErrorInvalidValue;
-    if (h->full_list) {
-        if (ev) launch_pair_t<real, true, true, 256>(h, step, words, lds256);
-        else launch_pair_t<real, true, false, 256>(h, step, words, lds256);
-    } else if (!big) {
-        if (ev) launch_pair_t<real, false, true, 256>(h, step, words, lds256);
-        else launch_pair_t<real, false, false, 256>(h, step, words, lds256);
-    } else {
-        if (ev) launch_pair_t<real, false, true, 64>(h, step, words, lds64);
-        else launch_pair_t<real, false, false, 64>(h, step, words, lds64);
-    }
+    if (h->full_list) return ev ? launch_coop_t<real, true, true>(h, step) : launch_coop_t<real, true, false>(h, step);
+    return ev ? launch_coop_t<real, false, true>(h, step) : launch_coop_t<real, false, false>(h, step);
+}
+
+// Reduce the per-block partials in a fixed order, in two stages: stage 1 sums
+// contiguous ranges of blocks into kReduceSlices slices, stage 2 sums the
+// slices: ev_pair[0..11] = totals, fcorr = (sum of the uncorrected short-range
+// force) / N when rbl.
+constexpr int kReduceSlices = 256;
+
+__global__ __launch_bounds__(kReduceBlock) void k_pair_reduce1(int64_t nb, const double* __restrict__ part,
+                                                               double* __restrict__ slices)
+{
+    __shared__ double lds[12 * (kReduceBlock / 64)];
+    const int64_t per = (nb + kReduceSlices - 1) / kReduceSlices;
+    const int64_t b0 = blockIdx.x * per, b1 = min(nb, b0 + per);
+    double vals[12];
+    for (int c = 0; c < 12; ++c) vals[c] = 0.0;
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += kReduceBlock)
+        for (int c = 0; c < 12; ++c) vals[c] += part[b * kPairPartials + c];
+    double out;
+    block_sum_vec<12, kReduceBlock>(vals, lds, threadIdx.x, out);
+    if (threadIdx.x < 12) slices[blockIdx.x * 12 + threadIdx.x] = out;
+}
+
+__global__ __launch_bounds__(kReduceBlock) void k_pair_reduce2(const double* __restrict__ slices, int64_t n, int rbl,
+                                                               double* __restrict__ ev_pair,
+                                                               double* __restrict__ fcorr)
+{
+    __shared__ double lds[12 * (kReduceBlock / 64)];
+    double vals[12];
+    for (int c = 0; c < 12; ++c) vals[c] = 0.0;
+    for (int b = threadIdx.x; b < kReduceSlices; b += kReduceBlock)
+        for (int c = 0; c < 12; ++c) vals[c] += slices[b * 12 + c];
+    double out;
+    block_sum_vec<12, kReduceBlock>(vals, lds, threadIdx.x, out);
+    if (threadIdx.x < 12) ev_pair[threadIdx.x] = out;
+    if (threadIdx.x < 3) fcorr[threadIdx.x] = rbl ? out / (double)n : 0.0;
+}
+
+hipError_t launch_pair_reduce(irbe_ctx* h)
+{
+    k_pair_reduce1<<<kReduceSlices, kReduceBlock, 0, h->stream>>>(h->pair_nb, h->pair_part, h->pair_slices);
+    k_pair_reduce2<<<1, kReduceBlock, 0, h->stream>>>(h->pair_slices, h->cfg.n_atoms, h->full_list ? 0 : 1,
+                                                      h->ev_pair, h->fcorr);
     return hipGetLastError();
 }
 
 hipError_t launch_pair_forces(irbe_ctx* h, uint64_t step, bool ev)
 {
-    return h->fp64 ? launch_pair_r<double>(h, step, ev) : launch_pair_r<float>(h, step, ev);
-}
-
-// Batch ranks of every atom (debug read-back): ranks_dev[k * stride + t] for
-// the atom in cell-order slot k, in draw order.
-__global__ __launch_bounds__(kBlock) void k_batch_debug(int64_t n, const int32_t* __restrict__ perm,
-                                                        const int32_t* __restrict__ nshell, int p_shell, uint64_t seed,
-                                                        uint64_t step, int32_t* __restrict__ ranks, int stride,
-                                                        uint32_t* __restrict__ bits, int words)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int ns = nshell[k];
-    int32_t* out = ranks + k * (int64_t)stride;
-    if (p_shell <= 0 || ns <= p_shell) {
-        for (int t = 0; t < ns; ++t) out[t] = t;
-        return;
-    }
-    uint32_t* bm = bits + k * (int64_t)words;
-    for (int t = 0; t < words; ++t) bm[t] = 0u;
-    WordStream st(seed, step, (uint32_t)perm[k], kTagShell);
-    for (int c = 0; c < p_shell; ++c) {
-        const int t = ns - p_shell + c;
-        const int r = (int)st.below((uint32_t)t + 1u);
-        const bool taken = (bm[r >> 5] >> (r & 31)) & 1u;
-        const int v = taken ? t : r;
-        bm[v >> 5] |= 1u << (v & 31);
-        out[c] = v;
-    }
-}
-
-hipError_t launch_batch_debug(irbe_ctx* h, uint64_t step, int32_t* ranks_dev, int32_t stride)
-{
-    const int64_t n = h->cfg.n_atoms;
-    const int words = (h->max_shell + 31) / 32 + 1;
-    uint32_t* bits = nullptr;
-    hipError_t e = hipMalloc(&bits, (size_t)n * words * 4);
-    if (e != hipSuccess) return e;
-    k_batch_debug<<<(unsigned)blocks_for(n, kBlock), kBlock, 0, h->stream>>>(
-        n, h->perm, h->nshell, h->cfg.p_shell, h->cfg.seed, step, ranks_dev, stride, bits, words);
-    e = hipStreamSynchronize(h->stream);
-    hipFree(bits);
-    return e;
+    return h->fp64 ? launch_coop_r<double>(h, step, ev) : launch_coop_r<float>(h, step, ev);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,100 +442,85 @@ __device__ __forceinline__ void load3(const real* p, int64_t k, real& x, real& y
     z = p[3 * k + 2];
 }
 
-template <typename real, bool FULL, bool WANT_LJ, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_pair_adjoint(
-    int64_t n, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
+// One wavefront per atom (cell order), lanes over the atom's lists.
+template <typename real, bool FULL, bool WANT_LJ>
+__global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
+    int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const int32_t* __restrict__ xoff,
-    const int32_t* __restrict__ xidx, const real* __restrict__ ljraw_g, int n_types, int p_shell, uint64_t seed,
-    uint64_t step, const real* __restrict__ gs, const double* __restrict__ gmean_d, real* __restrict__ gself,
-    real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat, double* __restrict__ ljpart)
+    const int32_t* __restrict__ xidx, const real* __restrict__ ljraw_g, int n_types, int p_shell, int p_stride,
+    const uint16_t* __restrict__ ranks, const real* __restrict__ gs, const double* __restrict__ gmean_d,
+    real* __restrict__ gself, real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat,
+    double* __restrict__ ljpart)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    real* ljraw = (real*)smem_raw;  // sigma[nt2], eps[nt2]
-    const int nt2 = n_types * n_types;
-    uint32_t* bitmap = (uint32_t*)(smem_raw + ((sizeof(real) * 2 * nt2 + 15) / 16) * 16);
     constexpr int NLJ = 2 * kMaxTypesGrad * kMaxTypesGrad;
-    __shared__ double red[NLJ * (BLOCK / 64)];
-    for (int t = threadIdx.x; t < 2 * nt2; t += BLOCK) ljraw[t] = ljraw_g[t];
+    constexpr int NW = kCoopBlock / 64;
+    __shared__ real ljraw[2 * 256];  // sigma[nt2], eps[nt2]
+    __shared__ double ljacc[NW][NLJ];
+    const int nt2 = n_types * n_types;
+    for (int t = threadIdx.x; t < 2 * nt2; t += kCoopBlock) ljraw[t] = ljraw_g[t];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (WANT_LJ)
+        for (int t = lane; t < NLJ; t += 64) ljacc[wave][t] = 0.0;
     __syncthreads();
-
     const real mx = FULL ? (real)0 : (real)gmean_d[0];
     const real my = FULL ? (real)0 : (real)gmean_d[1];
     const real mz = FULL ? (real)0 : (real)gmean_d[2];
-    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    double acc_sig[kMaxTypesGrad], acc_eps[kMaxTypesGrad];
-#pragma unroll
-    for (int t = 0; t < kMaxTypesGrad; ++t) acc_sig[t] = acc_eps[t] = 0.0;
-    int ti = 0;
-    if (k < n) {
-        const uint4 si = spos[k];
-        ti = (int)si.w;
-        const real qi = sqr[k];
-        const real ke = pp.ke;
-        real gx, gy, gz;
-        load3(gs, k, gx, gy, gz);
+    const real ke = pp.ke;
+    const int64_t gw = (int64_t)blockIdx.x * NW + wave;
+    const int64_t a0 = gw * apw;
+    const int64_t a1 = min(n, a0 + apw);
+    for (int64_t a = a0; a < a1; ++a) {
+        const uint4 si = spos[a];
+        const int ti = (int)si.w;
+        const real qi = sqr[a];
+        const real gx = gs[3 * a], gy = gs[3 * a + 1], gz = gs[3 * a + 2];
         const real pgx = gx - mx, pgy = gy - my, pgz = gz - mz;  // G'_i
         real rx = 0, ry = 0, rz = 0, rq = 0;
-        // symmetric part: core pairs (RBL) or the whole list (full-list mode)
-        for (int list = 0; list < 2; ++list) {
-            const bool sym = list == 0 || FULL;
-            const int nc = list == 0 ? ncore[k] : nshell[k];
-            if (!sym) break;
-            const int32_t* row = list == 0 ? core + k * (int64_t)cap_core : shell + k * (int64_t)cap_shell;
-            for (int c = 0; c < nc; ++c) {
-                const int j = row[c];
-                const uint4 sj = spos[j];
-                real dx, dy, dz;
-                separation(si, sj, pp.quantum, dx, dy, dz);
-                const real r2 = dx * dx + dy * dy + dz * dz;
-                const int tp = ti * n_types + (int)sj.w;
-                const real sig = ljraw[tp], eps = ljraw[nt2 + tp];
-                const real qj = sqr[j];
-                const PairGrad<real> g = pair_grad(r2, ke * qi * qj, sig, eps, pp);
-                real hx, hy, hz;
-                load3(gs, (int64_t)j, hx, hy, hz);
-                const real ex_ = hx - mx - pgx, ey_ = hy - my - pgy, ez_ = hz - mz - pgz;  // G'_j - G'_i
-                const real gd = dx * ex_ + dy * ey_ + dz * ez_;
-                rx += g.phi * ex_ + g.dphi_r * dx * gd;
-                ry += g.phi * ey_ + g.dphi_r * dy * gd;
-                rz += g.phi * ez_ + g.dphi_r * dz * gd;
-                rq += ke * qj * g.a_coul * gd;
-                if (WANT_LJ) {
-                    const real gdi = dx * pgx + dy * pgy + dz * pgz;
-                    const int tj = (int)sj.w;
+        real acc_sig[kMaxTypesGrad], acc_eps[kMaxTypesGrad];
 #pragma unroll
-                    for (int t = 0; t < kMaxTypesGrad; ++t)
-                        if (t == tj) {
-                            acc_sig[t] += (double)(-eps * g.dc_dsig * gdi);
-                            acc_eps[t] += (double)(-g.c_lj * gdi);
-                        }
-                }
+        for (int t = 0; t < kMaxTypesGrad; ++t) acc_sig[t] = acc_eps[t] = 0;
+        // symmetric lists: core pairs (RBL) or the whole list (full-list mode)
+        const int nsym = FULL ? nshell[a] : ncore[a];
+        const int32_t* srow_sym = FULL ? shell + a * (int64_t)cap_shell : core + a * (int64_t)cap_core;
+        for (int c = lane; c < nsym; c += 64) {
+            const int j = srow_sym[c];
+            const uint4 sj = spos[j];
+            real dx, dy, dz;
+            separation(si, sj, pp.quantum, dx, dy, dz);
+            const real r2 = dx * dx + dy * dy + dz * dz;
+            const int tp = ti * n_types + (int)sj.w;
+            const real sig = ljraw[tp], eps = ljraw[nt2 + tp];
+            const real qj = sqr[j];
+            const PairGrad<real> g = pair_grad(r2, ke * qi * qj, sig, eps, pp);
+            const real ex_ = gs[3 * j] - mx - pgx, ey_ = gs[3 * j + 1] - my - pgy, ez_ = gs[3 * j + 2] - mz - pgz;
+            const real gd = dx * ex_ + dy * ey_ + dz * ez_;
+            rx += g.phi * ex_ + g.dphi_r * dx * gd;
+            ry += g.phi * ey_ + g.dphi_r * dy * gd;
+            rz += g.phi * ez_ + g.dphi_r * dz * gd;
+            rq += ke * qj * g.a_coul * gd;
+            if (WANT_LJ) {
+                const real gdi = dx * pgx + dy * pgy + dz * pgz;
+                const int tj = (int)sj.w;
+#pragma unroll
+                for (int t = 0; t < kMaxTypesGrad; ++t)
+                    if (t == tj) {
+                        acc_sig[t] += -eps * g.dc_dsig * gdi;
+                        acc_eps[t] += -g.c_lj * gdi;
+                    }
             }
         }
         if (!FULL) {
-            // sampled shell pairs, one-sided
-            const int ns = nshell[k];
-            const int32_t* srow = shell + k * (int64_t)cap_shell;
+            // sampled shell pairs, one-sided: gather for i, scatter (atomics) for j
+            const int ns = nshell[a];
+            const int32_t* srow = shell + a * (int64_t)cap_shell;
             const bool sample = ns > p_shell;
             const int cnt = sample ? p_shell : ns;
             const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
-            WordStream st(seed, step, (uint32_t)perm[k], kTagShell);
-            if (sample) {
-                const int words = (ns + 31) >> 5;
-                for (int t = 0; t < words; ++t) bitmap[t * BLOCK + threadIdx.x] = 0u;
-            }
-            for (int c = 0; c < cnt; ++c) {
-                int v = c;
-                if (sample) {
-                    const int t = ns - p_shell + c;
-                    const int r = (int)st.below((uint32_t)t + 1u);
-                    const bool taken = (bitmap[(r >> 5) * BLOCK + threadIdx.x] >> (r & 31)) & 1u;
-                    v = taken ? t : r;
-                    bitmap[(v >> 5) * BLOCK + threadIdx.x] |= 1u << (v & 31);
-                }
-                const int j = srow[v];
+            const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+            for (int c = lane; c < cnt; c += 64) {
+                const int j = srow[sample ? (int)rrow[c] : c];
                 const uint4 sj = spos[j];
                 real dx, dy, dz;
                 separation(si, sj, pp.quantum, dx, dy, dz);
@@ -507,16 +546,17 @@ __global__ __launch_bounds__(BLOCK) void k_pair_adjoint(
 #pragma unroll
                     for (int t = 0; t < kMaxTypesGrad; ++t)
                         if (t == tj) {
-                            acc_sig[t] += (double)(w * (-eps * g.dc_dsig * gdi));
-                            acc_eps[t] += (double)(w * (-g.c_lj * gdi));
+                            acc_sig[t] += w * (-eps * g.dc_dsig * gdi);
+                            acc_eps[t] += w * (-g.c_lj * gdi);
                         }
                 }
             }
         }
         // excluded pairs (symmetric; G itself)
-        const int ic = perm[k];
-        for (int x = xoff[ic]; x < xoff[ic + 1]; ++x) {
-            const int j = rank[xidx[x]];
+        const int ia = perm[a];
+        const int xb = xoff[ia], nx = xoff[ia + 1] - xb;
+        for (int c = lane; c < nx; c += 64) {
+            const int j = rank[xidx[xb + c]];
             const uint4 sj = spos[j];
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
@@ -524,39 +564,48 @@ __global__ __launch_bounds__(BLOCK) void k_pair_adjoint(
             const real qj = sqr[j];
             real psi, dpsi_r, a_x;
             excl_grad(r2, ke * qi * qj, pp, psi, dpsi_r, a_x);
-            real hx, hy, hz;
-            load3(gs, (int64_t)j, hx, hy, hz);
-            const real ex_ = hx - gx, ey_ = hy - gy, ez_ = hz - gz;
+            const real ex_ = gs[3 * j] - gx, ey_ = gs[3 * j + 1] - gy, ez_ = gs[3 * j + 2] - gz;
             const real gd = dx * ex_ + dy * ey_ + dz * ez_;
             rx += psi * ex_ + dpsi_r * dx * gd;
             ry += psi * ey_ + dpsi_r * dy * gd;
             rz += psi * ez_ + dpsi_r * dz * gd;
             rq += ke * qj * a_x * gd;
         }
-        gself[3 * k + 0] = rx;
-        gself[3 * k + 1] = ry;
-        gself[3 * k + 2] = rz;
-        gqself[k] = rq;
-    }
-    if (WANT_LJ) {
-        // per-block sums of the table entries [t_i][t], sigma then eps
-        double vals[NLJ];
-#pragma unroll
-        for (int a = 0; a < kMaxTypesGrad; ++a)
+        rx = wave_sum_r(rx);
+        ry = wave_sum_r(ry);
+        rz = wave_sum_r(rz);
+        rq = wave_sum_r(rq);
+        if (lane == 0) {
+            gself[3 * a + 0] = rx;
+            gself[3 * a + 1] = ry;
+            gself[3 * a + 2] = rz;
+            gqself[a] = rq;
+        }
+        if (WANT_LJ && ti < kMaxTypesGrad) {
 #pragma unroll
             for (int t = 0; t < kMaxTypesGrad; ++t) {
-                const bool mine = (k < n) && (ti == a);
-                vals[a * kMaxTypesGrad + t] = mine ? acc_sig[t] : 0.0;
-                vals[kMaxTypesGrad * kMaxTypesGrad + a * kMaxTypesGrad + t] = mine ? acc_eps[t] : 0.0;
+                const real s_sig = wave_sum_r(acc_sig[t]);
+                const real s_eps = wave_sum_r(acc_eps[t]);
+                if (lane == 0) {
+                    ljacc[wave][ti * kMaxTypesGrad + t] += (double)s_sig;
+                    ljacc[wave][kMaxTypesGrad * kMaxTypesGrad + ti * kMaxTypesGrad + t] += (double)s_eps;
+                }
             }
-        double out;
-        block_sum_vec<NLJ, BLOCK>(vals, red, threadIdx.x, out);
-        if (threadIdx.x < NLJ) ljpart[blockIdx.x * (int64_t)NLJ + threadIdx.x] = out;
+        }
+    }
+    if (WANT_LJ) {
+        __syncthreads();
+        if (threadIdx.x < NLJ) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += ljacc[w][threadIdx.x];
+            ljpart[blockIdx.x * (int64_t)NLJ + threadIdx.x] = t;
+        }
     }
 }
 
-template <typename real, bool FULL, bool WANT_LJ, int BLOCK>
-static void launch_adj_t(irbe_ctx* h, uint64_t step, size_t lds)
+template <typename real, bool FULL, bool WANT_LJ>
+static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step)
 {
     const int64_t n = h->cfg.n_atoms;
     PairParams<real> pp;
@@ -564,35 +613,26 @@ static void launch_adj_t(irbe_ctx* h, uint64_t step, size_t lds)
     pp.beta = (real)h->cfg.ewald_beta;
     pp.cgauss = (real)(2.0 * h->cfg.ewald_beta / 1.7724538509055160273);
     pp.ke = (real)h->cfg.coulomb_k;
-    const unsigned nb = (unsigned)blocks_for(n, BLOCK);
+    hipError_t e = launch_draw(h, step);
+    if (e != hipSuccess) return e;
+    const int64_t waves = blocks_for(n, kAtomsPerWave);
+    const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
+    if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     h->adj_nb = nb;
-    k_pair_adjoint<real, FULL, WANT_LJ, BLOCK><<<nb, BLOCK, lds, h->stream>>>(
-        n, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core, h->shell, h->nshell,
-        h->cap_shell, h->xoff, h->xidx, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell, h->cfg.seed, step,
-        (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself, (real*)h->gqscat,
-        h->ljpart);
+    k_pair_adjoint<real, FULL, WANT_LJ><<<nb, kCoopBlock, 0, h->stream>>>(
+        n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core,
+        h->shell, h->nshell, h->cap_shell, h->xoff, h->xidx, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
+        h->p_stride, h->ranks, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
+        (real*)h->gqscat, h->ljpart);
+    return hipGetLastError();
 }
 
 template <typename real>
 static hipError_t launch_adj_r(irbe_ctx* h, uint64_t step, bool want_lj)
 {
-    const int words = h->full_list ? 0 : (h->max_shell + 31) / 32;
-    const size_t raw_bytes = ((sizeof(real) * 2 * h->cfg.n_types * h->cfg.n_types + 15) / 16) * 16;
-    const size_t lds256 = raw_bytes + (size_t)words * 256 * 4;
-    const size_t lds64 = raw_bytes + (size_t)words * 64 * 4;
-    const bool big = lds256 > 48 * 1024;
-    if (big && lds64 > 64 * 1024) return hipErrorInvalidValue;
-    if (h->full_list) {
-        if (want_lj) launch_adj_t<real, true, true, 256>(h, step, lds256);
-        else launch_adj_t<real, true, false, 256>(h, step, lds256);
-    } else if (!big) {
-        if (want_lj) launch_adj_t<real, false, true, 256>(h, step, lds256);
-        else launch_adj_t<real, false, false, 256>(h, step, lds256);
-    } else {
-        if (want_lj) launch_adj_t<real, false, true, 64>(h, step, lds64);
-        else launch_adj_t<real, false, false, 64>(h, step, lds64);
-    }
-    return hipGetLastError();
+    if (h->full_list)
+        return want_lj ? launch_adj_t<real, true, true>(h, step) : launch_adj_t<real, true, false>(h, step);
+    return want_lj ? launch_adj_t<real, false, true>(h, step) : launch_adj_t<real, false, false>(h, step);
 }
 
 hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool want_lj)

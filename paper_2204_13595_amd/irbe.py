@@ -34,7 +34,7 @@ STATUS = {0: "IRBE_OK", -1: "IRBE_EINVAL", -2: "IRBE_ENOMEM", -3: "IRBE_EHIP", -
 
 EXPORTED = ("irbe_create", "irbe_set_system", "irbe_update_parameters", "irbe_build_lists", "irbe_compute_forces",
             "irbe_compute_forces_backward", "irbe_sync", "irbe_enable_timing", "irbe_get_timing", "irbe_get_debug",
-            "irbe_last_error", "irbe_destroy")
+            "irbe_get_debug_rows", "irbe_last_error", "irbe_destroy")
 
 STAGES = ("bin", "lists", "quantize", "ksample", "rho", "pair", "pair_reduce", "kspace", "energy", "grad_gather",
           "rho_adj", "pair_adj", "kspace_adj")
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.irbe_enable_timing.argtypes = [vp, ctypes.c_int32]
     L.irbe_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.irbe_get_debug.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    L.irbe_get_debug_rows.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, vp,
+                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.irbe_last_error.argtypes = [vp]
     L.irbe_last_error.restype = ctypes.c_char_p
     L.irbe_destroy.argtypes = [vp]
@@ -202,6 +204,18 @@ class Handle:
         out = np.empty(max(written.value, 1), dtype=_DBG_DTYPE[sel])
         self._check(self.lib.irbe_get_debug(self.h, sel, out.ctypes.data_as(ctypes.c_void_p), written.value,
                                             ctypes.byref(written)))
+        return out[:written.value]
+
+    def debug_rows(self, what: str, rows) -> np.ndarray:
+        """Per-atom read-back (core/shell lists, batch ranks) of the caller ids in rows."""
+        sel = DBG[what]
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        rp = rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        written = ctypes.c_int64()
+        self._check(self.lib.irbe_get_debug_rows(self.h, sel, rp, rows.size, None, 0, ctypes.byref(written)))
+        out = np.empty(max(written.value, 1), dtype=_DBG_DTYPE[sel])
+        self._check(self.lib.irbe_get_debug_rows(self.h, sel, rp, rows.size, out.ctypes.data_as(ctypes.c_void_p),
+                                                 written.value, ctypes.byref(written)))
         return out[:written.value]
 
     def close(self):

@@ -1,0 +1,72 @@
+"""Parity at the full benchmark sizes, on sampled atoms.
+
+The 3,145,728-atom water box runs in the benchmark's launch configuration
+(mixed precision, p_shell = 100, p = 100); the 6,291,456-atom box in FP64 with
+p = 500. The oracle recomputes, for a random sample of atoms, their core and
+shell lists, batch ranks and uncorrected short-range, excluded-pair and
+long-range forces (the structure factor over every atom). The momentum
+correction is checked through a property that holds at any size: the total
+force vanishes.
+"""
+import numpy as np
+import pytest
+
+from paper_2204_13595_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("name,precision,p_kspace,tol", [("water1M", "mixed", 100, 1e-5),
+                                                          ("water2M", "fp64", 500, 1e-11)])
+def test_fullsize_sampled_parity(orc, name, precision, p_kspace, tol):
+    from paper_2204_13595_amd import irbe
+    w = inputs.workload(name)
+    dev = torch.device("cuda", 0)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    step = 11
+    h = irbe.Handle(w.n_atoms, w.box, p_shell=100, p_kspace=p_kspace, precision=precision, device=dev)
+    pos = torch.tensor(w.pos, dtype=dt, device=dev)
+    q = torch.tensor(w.charge, dtype=dt, device=dev)
+    h.set_system(torch.tensor(w.atom_type, device=dev), q, torch.tensor(w.molecule, device=dev), w.lj_sigma,
+                 w.lj_eps)
+    h.build_lists(pos, step)
+    F = h.compute_forces(pos, step)
+    fcorr = h.debug("fcorr")
+    rho_gpu = h.debug("rho").reshape(-1, 2)
+    kvec = h.debug("kvec").reshape(-1, 3)
+    Fsum = F.double().sum(dim=0).cpu().numpy()
+    Fabs = F.double().abs().sum().item()
+    rows = np.sort(np.random.default_rng(42).choice(w.n_atoms, size=48, replace=False))
+    Fr = F[torch.tensor(rows, device=dev)].double().cpu().numpy()
+    core_off = h.debug_rows("core_off", rows)
+    core_idx = h.debug_rows("core_idx", rows)
+    shell_off = h.debug_rows("shell_off", rows)
+    shell_idx = h.debug_rows("shell_idx", rows)
+    b_off = h.debug_rows("batch_off", rows)
+    b_rank = h.debug_rows("batch_rank", rows)
+    h.close()
+    del F, pos
+    torch.cuda.empty_cache()
+
+    pos_np = torch.tensor(w.pos, dtype=dt).double().numpy()
+    q_np = torch.tensor(w.charge, dtype=dt).double().numpy()
+    p = orc.Params(box=w.box, p_shell=100, p_kspace=p_kspace)
+    s = orc.quantize(pos_np, w.box)
+    lists = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2, rows=rows)
+    assert np.array_equal(core_off, lists.core_off) and np.array_equal(core_idx, lists.core_idx)
+    assert np.array_equal(shell_off, lists.shell_off) and np.array_equal(shell_idx, lists.shell_idx)
+    batches = orc.shell_batches(p.seed, step, lists, p.p_shell)
+    assert np.array_equal(b_off, batches[0]) and np.array_equal(b_rank, batches[1])
+    m, W, S = orc.sample_kspace(p, step)
+    assert np.array_equal(kvec, m)
+    rho = orc.structure_factor(s, q_np, m)
+    assert np.abs(rho_gpu - rho).max() < 100 * tol * np.abs(rho).max()
+    ref = orc.forward(None, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step, mode="rbl",
+                      rows=rows, s=s, lists=lists, batches=batches, kspace=(m, W, S), rho=rho)
+    uncorrected = ref.f_short + ref.f_excl + ref.f_long
+    err = np.sqrt(((Fr + fcorr - uncorrected) ** 2).sum() / (uncorrected ** 2).sum())
+    assert err < tol, err
+    # momentum: sum_i F_i = 0 (Eq. 2.12 for the short range, Im|rho|^2 = 0 for RBE)
+    assert np.abs(Fsum).max() < (1e-6 if precision == "mixed" else 1e-12) * Fabs

@@ -150,3 +150,126 @@ def test_invalid_arguments_rejected():
     h.compute_forces(pos, 0)
     h.sync()
     h.close()
+
+
+def test_water32k_parity_p200(orc):
+    """The 98,304-atom box (P = 200) against the oracle, every atom."""
+    w = inputs.workload("water32k")
+    step = 2
+    h, pos, q, pos_np, q_np = _setup(w, "mixed", p_kspace=200)
+    h.build_lists(pos, step)
+    f, ev = h.compute_forces(pos, step, energy=True)
+    f = f.double().cpu().numpy()
+    ev = ev.cpu().numpy()
+    p = _oracle_params(orc, w, p_kspace=200)
+    ref = orc.forward(pos_np, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step, mode="rbl")
+    assert _rms_rel(f, ref.force) < 1e-5
+    scale = np.abs(ref.energy[:5]).max()
+    assert np.all(np.abs(ev - ref.energy) < 2e-5 * scale)
+    h.close()
+
+
+def test_forward_is_deterministic():
+    w = inputs.workload("water4k")
+    h, pos, q, pos_np, q_np = _setup(w, "mixed")
+    h.build_lists(pos, 4)
+    a, ea = h.compute_forces(pos, 4, energy=True)
+    b, eb = h.compute_forces(pos, 4, energy=True)
+    h.build_lists(pos, 4)
+    c, ec = h.compute_forces(pos, 4, energy=True)
+    assert torch.equal(a, b) and torch.equal(a, c)
+    assert torch.equal(ea, eb) and torch.equal(ea, ec)
+    d = h.compute_forces(pos, 5)
+    assert not torch.equal(a, d)  # another step draws other samples
+    h.close()
+
+
+@pytest.mark.slow
+def test_gpu_estimator_is_unbiased(orc):
+    """Mean of the GPU RBL+RBE force over many steps (independent samples) tends
+    to the deterministic Ewald force (Sec. 2.4), per component as z-scores."""
+    w = inputs.workload("water512")
+    h, pos, q, pos_np, q_np = _setup(w, "fp64")
+    h.build_lists(pos, 0)
+    n_draw = 400
+    acc = torch.zeros_like(pos)
+    acc2 = torch.zeros_like(pos)
+    for t in range(n_draw):
+        f = h.compute_forces(pos, t)
+        acc += f
+        acc2 += f * f
+    mean = (acc / n_draw).cpu().numpy()
+    var = (acc2 / n_draw).cpu().numpy() - mean ** 2
+    h.close()
+    ref = orc.forward(pos_np, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, orc.Params(box=w.box),
+                      mode="ewald")
+    z = (mean - ref.force) / np.sqrt(var * n_draw / (n_draw - 1) / n_draw)
+    assert abs((z ** 2).mean() - 1.0) < 0.12
+    assert np.abs(z).max() < 5.5
+
+
+@pytest.mark.parametrize("p_shell,p_kspace", [(1, 1), (7, 3), (100000, 50)])
+def test_small_batches_and_all_members(orc, p_shell, p_kspace):
+    w = inputs.workload("water512")
+    h, pos, q, pos_np, q_np = _setup(w, "fp64", p_shell=p_shell, p_kspace=p_kspace)
+    h.build_lists(pos, 9)
+    f = h.compute_forces(pos, 9).cpu().numpy()
+    p = _oracle_params(orc, w, p_shell=p_shell, p_kspace=p_kspace)
+    ref = orc.forward(pos_np, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=9, mode="rbl")
+    assert _rms_rel(f, ref.force) < 1e-11
+    h.close()
+
+
+def test_ionic_crystal_without_exclusions(orc):
+    """Rock salt (no molecules, one LJ-free type, Gaussian units): GPU against oracle."""
+    from paper_2204_13595_amd import irbe
+    pos, qv, box = inputs.nacl_crystal(3, d=0.45)
+    pos = pos + np.random.default_rng(2).uniform(-0.05, 0.05, pos.shape)
+    n = qv.shape[0]
+    dev = torch.device("cuda", 0)
+    h = irbe.Handle(n, box, beta=4.0, r_core=0.55, r_shell=1.1, p_shell=20, p_kspace=64, n_types=1,
+                    precision="fp64", coulomb_k=1.0, device=dev)
+    pt = torch.tensor(pos, device=dev)
+    qt = torch.tensor(qv, device=dev)
+    h.set_system(torch.zeros(n, dtype=torch.int32, device=dev), qt, -torch.ones(n, dtype=torch.int32, device=dev),
+                 [0.0], [0.0])
+    h.build_lists(pt, 1)
+    f = h.compute_forces(pt, 1).cpu().numpy()
+    h.close()
+    p = orc.Params(box=box, beta=4.0, r_core=0.55, r_shell=1.1, p_shell=20, p_kspace=64, ke=1.0, n_types=1)
+    ref = orc.forward(pos, qv, np.zeros(n, np.int32), -np.ones(n, np.int32), np.zeros(1), np.zeros(1), p, step=1,
+                      mode="rbl")
+    assert _rms_rel(f, ref.force) < 1e-11
+
+
+def test_single_atom_and_small_box(orc):
+    from paper_2204_13595_amd import irbe
+    dev = torch.device("cuda", 0)
+    # one charged atom: no pairs, and its k-space self force vanishes
+    h = irbe.Handle(1, 3.0, r_core=0.6, r_shell=1.2, p_shell=4, p_kspace=8, n_types=1, precision="fp64",
+                    device=dev)
+    h.set_system(torch.zeros(1, dtype=torch.int32, device=dev), torch.ones(1, dtype=torch.float64, device=dev),
+                 -torch.ones(1, dtype=torch.int32, device=dev), [0.3], [0.5])
+    x = torch.tensor([[0.3, 2.9, -1.0]], dtype=torch.float64, device=dev)
+    h.build_lists(x, 0)
+    f = h.compute_forces(x, 0)
+    assert torch.all(f.abs() < 1e-12)
+    h.close()
+    # three cells per axis, random atoms, some cells empty
+    rng = np.random.default_rng(5)
+    n = 40
+    box = 1.8
+    pos = rng.uniform(0, box, (n, 3))
+    qv = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    h = irbe.Handle(n, box, r_core=0.6, r_shell=0.85, p_shell=3, p_kspace=16, n_types=1, precision="fp64",
+                    coulomb_k=1.0, device=dev)
+    h.set_system(torch.zeros(n, dtype=torch.int32, device=dev), torch.tensor(qv, device=dev),
+                 torch.tensor(np.arange(n) // 2, dtype=torch.int32, device=dev), [0.2], [0.1])
+    pt = torch.tensor(pos, device=dev)
+    h.build_lists(pt, 3)
+    f = h.compute_forces(pt, 3).cpu().numpy()
+    h.close()
+    p = orc.Params(box=box, r_core=0.6, r_shell=0.85, p_shell=3, p_kspace=16, ke=1.0, n_types=1)
+    ref = orc.forward(pos, qv, np.zeros(n, np.int32), (np.arange(n) // 2).astype(np.int32), np.array([0.2]),
+                      np.array([0.1]), p, step=3, mode="rbl")
+    assert _rms_rel(f, ref.force) < 1e-11
