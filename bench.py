@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline forward figure")
+    ap.add_argument("--with-backward", action="store_true",
+                    help="with --no-extras: also run the forward+backward steps once (for profiles)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (reference for the HBM byte counters of a profile)")
     return ap.parse_args()
@@ -72,6 +74,20 @@ def stage_times(h, fn, steps: int, first_step: int):
     t = h.timing()
     h.enable_timing(False)
     return {k: (ms / n if n else 0.0, n) for k, (ms, n) in t.items()}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE profile of
+    this kernel and workload, or None when absent or taken on another version
+    of the kernel's source."""
+    from paper_2204_13595_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("source_sha") != profiling.source_hash(kernel):
+        return None
+    return t["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(w, args):
@@ -183,7 +199,8 @@ def main():
         lists_ms = st["lists"][0]
         roof = {
             "kernel": "k_build_lists", "bound": "hbm", "achieved": list_bytes / (lists_ms * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": measured_traffic("k_build_lists", args.workload),
+            "algorithmic_bytes": list_bytes, "avg_launch_ms": lists_ms,
         }
         roof["frac"] = roof["achieved"] / roof["peak"]
         extras = {
@@ -198,6 +215,10 @@ def main():
             "roofline": roof,
         }
     else:
+        if args.with_backward:
+            for s in range(args.steps):
+                fwd_bwd(9000 + s)
+            torch.cuda.synchronize()
         h.close()
     out = {
         "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,

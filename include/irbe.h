@@ -176,10 +176,11 @@ irbe_status irbe_get_timing(irbe_handle h, double* ms_host, int64_t capacity, in
 
 /* Debug/parity read-back (waits). `what` selects the array; dst_host receives
  * up to `capacity` elements; *written = the number of elements available.
- *   IRBE_DBG_CELL_START  int64 [n_c^3 + 1]  atoms of cell c are
- *   IRBE_DBG_CELL_ATOMS  int64 [N]          cell_atoms[cell_start[c] .. cell_start[c+1])
+ *   IRBE_DBG_CELL_START  int64 [n_c^3 + 1]  atoms of cell c are cell_atoms[cell_start[c]
+ *   IRBE_DBG_CELL_ATOMS  int64 [N]          .. cell_start[c+1]), by (fixed-point x, id)
  *   IRBE_DBG_CORE_OFF    int64 [N + 1]      C(i) of atom i (caller order) at
- *   IRBE_DBG_CORE_IDX    int32 [..]         core_idx[core_off[i] .. core_off[i+1]) (atom ids)
+ *   IRBE_DBG_CORE_IDX    int32 [..]         core_idx[core_off[i] .. core_off[i+1]) (atom ids),
+ *                                           in stencil-offset order, then cell order
  *   IRBE_DBG_SHELL_OFF   int64 [N + 1]      S(i) (or the full list), same layout
  *   IRBE_DBG_SHELL_IDX   int32 [..]
  *   IRBE_DBG_BATCH_OFF   int64 [N + 1]      batch ranks into S(i), draw order, for

@@ -89,8 +89,9 @@ void orc_cell_ids(int64_t n, int32_t n_c, const uint32_t* s, int64_t* cell)
     }
 }
 
-/* Per-cell atom lists ordered by (cell id, atom id): cell_start[n_c^3 + 1],
- * cell_atoms[n]. Counting sort, stable because atoms are visited in id order. */
+/* Per-cell atom lists: cell_start[n_c^3 + 1], cell_atoms[n], ordered by cell
+ * id and, inside a cell, by (fixed-point x coordinate, atom id). A counting
+ * sort by cell, then an insertion sort of each cell by (s_x, id). */
 int orc_cell_lists(int64_t n, int32_t n_c, const uint32_t* s, int64_t* cell_start, int64_t* cell_atoms)
 {
     int64_t n_cells = (int64_t)n_c * n_c * n_c;
@@ -103,6 +104,16 @@ int orc_cell_lists(int64_t n, int32_t n_c, const uint32_t* s, int64_t* cell_star
     for (int64_t c = 0; c < n_cells; ++c) cell_start[c + 1] += cell_start[c];
     for (int64_t c = 0; c < n_cells; ++c) cursor[c] = cell_start[c];
     for (int64_t i = 0; i < n; ++i) cell_atoms[cursor[cell[i]]++] = i;
+    for (int64_t c = 0; c < n_cells; ++c)
+        for (int64_t k = cell_start[c] + 1; k < cell_start[c + 1]; ++k) {
+            int64_t v = cell_atoms[k], t = k - 1;
+            while (t >= cell_start[c] && (s[3 * cell_atoms[t]] > s[3 * v] ||
+                                          (s[3 * cell_atoms[t]] == s[3 * v] && cell_atoms[t] > v))) {
+                cell_atoms[t + 1] = cell_atoms[t];
+                --t;
+            }
+            cell_atoms[t + 1] = v;
+        }
     free(cell);
     free(cursor);
     return ORC_OK;
@@ -127,7 +138,7 @@ static inline int orc_excluded(const int32_t* mol, int64_t i, int64_t j)
  * Core set C(i) = {j != i : r_ij <= r_core} and shell set
  * S(i) = {j : r_core < r_ij <= r_shell} (Sec. 2.3), intramolecular pairs
  * removed. Canonical order: cell offsets (dz, dy, dx) in lexicographic order,
- * then the atoms of each cell in id order. Core offsets are -1..1 on each axis;
+ * then the atoms of each cell in their cell order (by x coordinate, then id). Core offsets are -1..1 on each axis;
  * shell offsets are -R..R when 2R+1 <= n_c, else -h..n_c-1-h with
  * h = floor((n_c-1)/2) (each cell once, and the 27 core cells keep their
  * relative order).

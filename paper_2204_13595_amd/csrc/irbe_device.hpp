@@ -77,6 +77,20 @@ struct WordStream {
     }
 };
 
+// Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each with
+// its own L2. Mapping hardware block b to logical block xcd_block(b) gives every
+// XCD one contiguous range of logical blocks, i.e. one compact region of the
+// cell-sorted atoms, so the neighbour data an XCD reads stays in its own L2. A
+// bijection of [0, nb) for any nb.
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t x = b % kNumXcd, i = b / kNumXcd;
+    const int64_t q = nb / kNumXcd, r = nb % kNumXcd;
+    return x * q + (x < r ? x : r) + i;
+}
+
 constexpr uint32_t kTagShell = 0u;
 constexpr uint32_t kTagKspace = 1u;
 

@@ -1,6 +1,7 @@
 // Binning (Sec. 2.3: cells of edge >= r_core): fixed-point quantization of the
-// positions, cell histogram, exclusive scan, scatter, in-cell ordering by atom
-// id, and the gather of a cell-sorted structure-of-arrays copy of the system.
+// positions, cell histogram, exclusive scan, scatter, in-cell ordering by
+// (x coordinate, atom id), and the gather of a cell-sorted structure-of-arrays
+// copy of the system.
 #include "irbe_device.hpp"
 #include "irbe_internal.hpp"
 
@@ -168,18 +169,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const uint4* __re
     perm[slot] = (int32_t)i;
 }
 
-// Order each cell's atoms by id (insertion sort; a cell holds a few tens).
+// Order each cell's atoms by (fixed-point x coordinate, atom id): insertion
+// sort (a cell holds a few tens of atoms). Sorting by x lets the list build
+// trim each atom's candidate range to its exact x extent.
 __global__ __launch_bounds__(kBlock) void k_cell_sort(int64_t n_cells, const int32_t* __restrict__ cell_start,
-                                                      int32_t* __restrict__ perm)
+                                                      const uint4* __restrict__ sq, int32_t* __restrict__ perm)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     const int32_t b = cell_start[c], e = cell_start[c + 1];
     for (int32_t k = b + 1; k < e; ++k) {
         const int32_t v = perm[k];
+        const uint32_t xv = sq[v].x;
         int32_t t = k - 1;
-        while (t >= b && perm[t] > v) {
-            perm[t + 1] = perm[t];
+        while (t >= b) {
+            const int32_t u = perm[t];
+            const uint32_t xu = sq[u].x;
+            if (xu < xv || (xu == xv && u < v)) break;
+            perm[t + 1] = u;
             --t;
         }
         perm[t + 1] = v;
@@ -223,7 +230,7 @@ hipError_t launch_bin(irbe_ctx* h, const void* pos)
     k_scan_total<<<1, 64, 0, h->stream>>>(h->cell_count, h->cell_start, h->geo.n_cells);
     k_scatter<<<nb, kBlock, 0, h->stream>>>(n, h->sq, h->cell_start, h->cursor, h->perm);
     k_cell_sort<<<(unsigned)blocks_for(h->geo.n_cells, kBlock), kBlock, 0, h->stream>>>(h->geo.n_cells,
-                                                                                         h->cell_start, h->perm);
+                                                                                         h->cell_start, h->sq, h->perm);
     if (h->fp64)
         k_gather_sorted<double><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const double*)h->q_orig,
                                                               h->mol_orig, h->spos, (double*)h->sq_r, h->smol,

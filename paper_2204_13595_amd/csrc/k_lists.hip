@@ -1,7 +1,7 @@
 // Core and shell lists (Sec. 2.3): C(i) = {j != i : r_ij <= r_core} and
 // S(i) = {j : r_core < r_ij <= r_shell}, same-molecule pairs removed, in the
 // canonical order "stencil cell offset (dz, dy, dx) lexicographic, then the
-// atoms of each cell by id". One traversal of the shell stencil yields both
+// atoms of each cell in cell order (by fixed-point x coordinate, then id)". One traversal of the shell stencil yields both
 // lists: the 27 core cells are visited in their own lexicographic order
 // inside it. Membership is exact: uint64 squared separations in quanta of
 // L / 2^32 against integer thresholds (an FP32 estimate settles every
@@ -12,7 +12,9 @@
 // lane per atom). For every stencil row (dz, dy) the union of the lanes' x
 // ranges is staged in LDS; each lane scans only the cells its own sphere can
 // reach (per-atom pruning of rows and of the x range from exact cell-boundary
-// distances), which leaves the member order unchanged.
+// distances; inside the first and last cell of the range, a binary search on
+// the x-sorted cell trims the range to the atom's exact x extent), which
+// leaves the member order unchanged.
 //
 // Layout: fixed-capacity rows (row k of atom k in cell order), entries are
 // cell-sorted atom indices, written four at a time. Counts beyond the capacity
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     const uint32_t* bound = bound_g;  // indexed by wave-uniform cell coordinates
     const int lane = threadIdx.x;
     const int groups_per_row = (n_c + G - 1) / G;
-    const int g = blockIdx.x;
+    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
     const int rowid = g / groups_per_row;
     const int cz = rowid / n_c, cy = rowid % n_c;
     const int x0 = (g % groups_per_row) * G;
@@ -119,6 +121,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                 // lane's candidate cells in this row: tile cells [u_lo, u_hi]
                 int u_lo = ti, u_hi = ti + span_c - 1;
                 bool need = act;
+                int32_t ext_i = 0x7fffffff;  // x half-extent (quanta) of the lane's sphere in this row
                 if (prune && act) {
                     const float gy = (float)slab_gap(si.y, dy, y, bound);
                     const float rem = tfs_hi - gy * gy - gz * gz;
@@ -126,6 +129,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         need = false;
                     } else {
                         const uint32_t ext = (uint32_t)(sqrtf(rem) * 1.000002f) + 2u;
+                        ext_i = (int32_t)ext;
                         const int cl = (int)(((uint64_t)(uint32_t)(si.x - ext) * (uint32_t)n_c) >> 32);
                         const int ch = (int)(((uint64_t)(uint32_t)(si.x + ext) * (uint32_t)n_c) >> 32);
                         int ol = cl - cx, oh = ch - cx;
@@ -146,13 +150,16 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                 const int eB = lenB > 0 ? cell_start[row + lenB] : jB;
                 const int nA = eA - jA;
                 const int total = nA + (eB - jB);
-                // lane's range in tile positions
-                int p_lo = 0, p_hi = 0;
+                // lane's range in tile positions; tpos(u) = position of the first atom of tile cell u
+                auto tpos = [&](int u) {
+                    return u < lenA ? cell_start[row + xu0 + u] - jA : nA + cell_start[row + u - lenA] - jB;
+                };
+                int p_lo = 0, p_hi = 0, pc1 = 0, pc2 = 0;
                 if (need) {
-                    const int ua = u_lo, ub = u_hi + 1;
-                    p_lo = ua < lenA ? cell_start[row + xu0 + ua] - jA : nA + cell_start[row + ua - lenA] - jB;
-                    p_hi = ub < lenA ? cell_start[row + xu0 + ub] - jA
-                                     : (ub == lenA ? nA : nA + cell_start[row + ub - lenA] - jB);
+                    p_lo = tpos(u_lo);
+                    p_hi = tpos(u_hi + 1);
+                    pc1 = u_lo < u_hi ? tpos(u_lo + 1) : p_hi;  // end of the first cell
+                    pc2 = u_lo < u_hi ? tpos(u_hi) : p_lo;      // start of the last cell
                 }
                 for (int base = 0; base < total; base += kTileCap) {
                     const int cnt = min(kTileCap, total - base);
@@ -164,6 +171,24 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         tmol[t] = smol[j];
                     }
                     __syncthreads();
+                    if (prune && need && total <= kTileCap) {
+                        // the cells are x-sorted: trim the first and the last cell of the range
+                        int a = p_lo, b = pc1;
+                        while (a < b) {
+                            const int m = (a + b) >> 1;
+                            if ((int32_t)(tile[m].x - si.x) < -ext_i) a = m + 1;
+                            else b = m;
+                        }
+                        p_lo = a;
+                        a = max(pc2, p_lo);
+                        b = p_hi;
+                        while (a < b) {
+                            const int m = (a + b) >> 1;
+                            if ((int32_t)(tile[m].x - si.x) <= ext_i) a = m + 1;
+                            else b = m;
+                        }
+                        p_hi = a;
+                    }
                     const int s0 = max(p_lo, base), s1 = min(p_hi, base + cnt);
                     // classify one staged candidate (FP32 estimate, exact test near a threshold)
                     auto visit = [&](int p, uint4 sj) {

@@ -164,7 +164,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     for (int t = threadIdx.x; t < nt2; t += kCoopBlock) lj[t] = lj_g[t];
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t gw = (int64_t)blockIdx.x * (kCoopBlock / 64) + (threadIdx.x >> 6);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t gw = blk * (kCoopBlock / 64) + (threadIdx.x >> 6);
     const int64_t a0 = gw * apw;
     const int64_t a1 = min(n, a0 + apw);
     double fc_sum[3] = {0.0, 0.0, 0.0};
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     for (int c = 12; c < kPairPartials; ++c) vals[c] = 0.0;
     double out;
     block_sum_vec<12, kCoopBlock>(vals, red, threadIdx.x, out);
-    if (threadIdx.x < 12) part[blockIdx.x * (int64_t)kPairPartials + threadIdx.x] = out;
+    if (threadIdx.x < 12) part[blk * (int64_t)kPairPartials + threadIdx.x] = out;
 }
 
 // Batch ranks of every atom for `step` (kept until the lists or the step change).
@@ -468,7 +469,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const real my = FULL ? (real)0 : (real)gmean_d[1];
     const real mz = FULL ? (real)0 : (real)gmean_d[2];
     const real ke = pp.ke;
-    const int64_t gw = (int64_t)blockIdx.x * NW + wave;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t gw = blk * NW + wave;
     const int64_t a0 = gw * apw;
     const int64_t a1 = min(n, a0 + apw);
     for (int64_t a = a0; a < a1; ++a) {
@@ -599,7 +601,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             double t = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) t += ljacc[w][threadIdx.x];
-            ljpart[blockIdx.x * (int64_t)NLJ + threadIdx.x] = t;
+            ljpart[blk * (int64_t)NLJ + threadIdx.x] = t;
         }
     }
 }

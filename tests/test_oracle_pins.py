@@ -148,7 +148,7 @@ def _brute_lists(s, mol, box, r_core, r_shell, rows, full=False):
             else:
                 h = (n_c - 1) // 2
                 off = (off + h) % n_c - h
-            key = np.lexsort((js, off[:, 0], off[:, 1], off[:, 2]))
+            key = np.lexsort((js, s[js, 0], off[:, 0], off[:, 1], off[:, 2]))
             return js[key]
 
         out.append((order(core, 1), order(shell, R)))
