@@ -82,6 +82,30 @@ void dfree(irbe_ctx* h, void* p)
     hipFree(p);
 }
 
+}  // namespace
+
+namespace irbe {
+
+hipError_t ensure_buckets(irbe_ctx* h, int64_t records)
+{
+    hipError_t e = hipSuccess;
+    if (!h->bk_cursor) e = dalloc(h, &h->bk_cursor, (size_t)h->geo.n_c * (size_t)h->geo.n_c);
+    if (e != hipSuccess || records <= h->bk_total) return e;
+    dfree(h, h->bk_c);
+    dfree(h, h->bk_j);
+    h->bk_c = nullptr;
+    h->bk_j = nullptr;
+    h->bk_total = 0;
+    e = dalloc_bytes(h, &h->bk_c, 4 * (size_t)records * h->real_size);
+    if (e == hipSuccess) e = dalloc(h, &h->bk_j, (size_t)records);
+    if (e == hipSuccess) h->bk_total = records;
+    return e;
+}
+
+}  // namespace irbe
+
+namespace {
+
 // Quantized-geometry constants, in the FP64 operation order that fixes them:
 // n_c = floor(L / r_core), R = floor(r_shell n_c / L) + 1,
 // T = floor(t * t) with t = r 2^32 / L.
@@ -306,9 +330,10 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     const size_t rs = h->real_size;
     const int64_t nb = blocks_for(c.n_atoms, kBlock);
     // per-block partial buffers must cover the largest grid of any pair kernel:
-    // 64-thread blocks of the thread-per-atom kernels and the cooperative kernel's
-    // blocks of four wavefronts with kAtomsPerWave atoms each
-    const int64_t nb64 = std::max(blocks_for(c.n_atoms, 64), blocks_for(c.n_atoms, 4 * kAtomsPerWave));
+    // 64-thread blocks of the thread-per-atom kernels and the cooperative kernels'
+    // blocks of four wavefronts with two or more atoms each
+    // (the bucketed pair adjoint runs blocks of as few as 8 atoms)
+    const int64_t nb64 = std::max(blocks_for(c.n_atoms, 64), blocks_for(c.n_atoms, 8));
     const int64_t nbr = rho_blocks(c.n_atoms);
     const size_t P = (size_t)c.p_kspace;
     const int nt2 = c.n_types * c.n_types;

@@ -22,6 +22,13 @@ constexpr int kRhoChunk = 16;        // k-vectors per block row of the structure
 constexpr int kRhoAtomsPerThread = 8;
 constexpr int kMaxTypesGrad = 4;     // LJ parameter gradients: n_types <= 4
 constexpr int kAtomsPerWave = 8;     // atoms per wavefront in the cooperative pair kernels
+// Shell-adjoint transpose: scatter records staged per block in LDS, then
+// bucketed by destination cell row (y, z) and reduced per row.
+constexpr int kBucketRowLds = 2048;  // atoms of a row accumulated in LDS (the rest: device atomics)
+constexpr int kBucketRecF = 2048;    // staged records per block, FP32
+constexpr int kBucketRecD = 1024;    // staged records per block, FP64
+constexpr int kBucketMaxKeys = 256;  // (source row, destination row) keys per block
+constexpr int kBucketSlack = 64;     // records of spare capacity per destination row
 
 // Per-k constants of the force kernels: k (3), then coefficient products.
 template <typename real>
@@ -140,6 +147,10 @@ struct irbe_ctx {
     int64_t adj_nb = 0;               // blocks of the last pair-adjoint launch
     int64_t pair_nb = 0;              // blocks of the last pair-force launch
     int64_t part_blocks = 0;          // capacity (blocks) of pair_part and ljpart
+    unsigned long long* bk_cursor = nullptr;  // [n_c^2] records reserved per destination row
+    void* bk_c = nullptr;             // real[4 * bk_total] shell-adjoint records: dL/dr_j (3), dL/dq_j
+    uint16_t* bk_j = nullptr;         // [bk_total] record's atom, relative to its row's first atom
+    int64_t bk_total = 0;             // allocated records
     uint16_t* ranks = nullptr;        // [N * p_stride] shell batch ranks of the current step
     int32_t p_stride = 0;
     bool ranks_valid = false;         // ranks hold the draw of ranks_step for the current lists
@@ -179,6 +190,8 @@ hipError_t launch_energy_finalize(irbe_ctx* h, double* ev);
 hipError_t launch_sum_q2(irbe_ctx* h);
 hipError_t launch_gather_grad(irbe_ctx* h, const void* grad);
 hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool want_lj);
+// Grow the shell-adjoint record buckets to hold `records` records (and create the row cursors).
+hipError_t ensure_buckets(irbe_ctx* h, int64_t records);
 hipError_t launch_kspace_adjoint(irbe_ctx* h, const void* grad, void* grad_pos, void* grad_q, double* grad_lj);
 
 }  // namespace irbe

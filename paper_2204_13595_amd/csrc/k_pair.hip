@@ -7,6 +7,8 @@
 // i), w_i = N_S / p_shell (all members and w_i = 1 when N_S <= p_shell). The
 // per-block FP64 sums of the uncorrected short-range force give F^corr.
 // Full-list mode: one list of every pair within r_shell, weight 1.
+#include <algorithm>
+
 #include "irbe_device.hpp"
 #include "irbe_internal.hpp"
 
@@ -370,10 +372,21 @@ hipError_t launch_pair_forces(irbe_ctx* h, uint64_t step, bool ev)
 // the excluded pairs) the gradient is gathered per atom:
 //   dL/dr_i += sum_j J (G'_j - G'_i),  dL/dq_i += sum_j (ke q_j a(r)) r_ij.(G'_j - G'_i)
 // where a(r) is the Coulomb factor of phi / (-ke q_i q_j). The sampled shell
-// terms are one-sided: dL/dr_i -= w J G'_i and dL/dr_j += w J G'_i (scattered
-// with atomics), and likewise for the charges. G' = G - mean(G) for the pair
-// terms when the momentum correction is applied; excluded pairs use G.
-// LJ table gradients are accumulated per (t_i, t_j) entry in FP64.
+// terms are one-sided: dL/dr_i -= w J G'_i and dL/dr_j += w J G'_i, and likewise
+// for the charges. G' = G - mean(G) for the pair terms when the momentum
+// correction is applied; excluded pairs use G. LJ table gradients are
+// accumulated per (t_i, t_j) entry in FP64.
+//
+// The scatter onto j is a transpose. Device-scope atomics on this chip are
+// executed at the memory side, one transaction per lane, so instead each block
+// (a run of consecutive cell-ordered atoms, which lie in one or two cell rows)
+// stages its records (j, w J G'_i, charge term) in LDS, counts them per
+// (source row, destination row) key, reserves one contiguous range per key in
+// the destination row's bucket with a single atomic, and writes the records
+// there. A second kernel reduces each row's bucket in LDS and adds the row's
+// gradients with plain stores. Records that do not fit (a third source row in
+// one block, a full bucket, an atom beyond the LDS row window) fall back to
+// device atomics, so the result never depends on the capacities.
 // ---------------------------------------------------------------------------
 template <typename real>
 struct PairGrad {
@@ -443,8 +456,54 @@ __device__ __forceinline__ void load3(const real* p, int64_t k, real& x, real& y
     z = p[3 * k + 2];
 }
 
-// One wavefront per atom (cell order), lanes over the atom's lists.
-template <typename real, bool FULL, bool WANT_LJ>
+// Geometry of the shell-adjoint buckets. Row R = cz n_c + cy holds the atoms of
+// cells [R n_c, (R + 1) n_c); its bucket starts at
+// floor(cell_start[R n_c] p9 / 8) + kBucketSlack R records (9/8 of the expected
+// p_eff records per atom, plus slack).
+struct BucketArgs {
+    int n_c, lo, span;            // shell stencil offsets lo .. lo + span - 1 per axis
+    int64_t p9;                   // 9 * p_eff
+    const int32_t* cell_start;
+    unsigned long long* cursor;   // [n_c^2] records reserved per destination row
+    void* rec_c;                  // real[4 * total]
+    uint16_t* rec_j;              // [total]
+};
+
+__device__ __forceinline__ int64_t bucket_start(const BucketArgs& bk, int row)
+{
+    const int64_t a = bk.cell_start[(int64_t)row * bk.n_c];
+    return ((a * bk.p9) >> 3) + (int64_t)kBucketSlack * row;
+}
+
+__device__ __forceinline__ int cell_row(uint4 s, int n_c)
+{
+    const int cz = (int)(((uint64_t)s.z * (uint32_t)n_c) >> 32);
+    const int cy = (int)(((uint64_t)s.y * (uint32_t)n_c) >> 32);
+    return cz * n_c + cy;
+}
+
+// Offset d = c_j - c_i of a stencil cell mapped into [lo, lo + span).
+__device__ __forceinline__ int stencil_offset(int cj, int ci, int lo, int span, int n_c)
+{
+    int d = cj - ci;
+    if (d < lo) d += n_c;
+    if (d >= lo + span) d -= n_c;
+    return d;
+}
+
+template <typename real>
+__device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_t j, real x, real y, real z, real q)
+{
+    atomicAdd(&gscat[3 * j + 0], x);
+    atomicAdd(&gscat[3 * j + 1], y);
+    atomicAdd(&gscat[3 * j + 2], z);
+    atomicAdd(&gqscat[j], q);
+}
+
+// One wavefront per atom (cell order), lanes over the atom's lists. BK: the
+// shell scatter goes through the LDS-staged buckets (dynamic LDS: rec_cap
+// records of 4 reals + j + key, then 7 ints per key).
+template <typename real, bool FULL, bool WANT_LJ, bool BK>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, const int32_t* __restrict__ core,
@@ -453,17 +512,35 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const int32_t* __restrict__ xidx, const real* __restrict__ ljraw_g, int n_types, int p_shell, int p_stride,
     const uint16_t* __restrict__ ranks, const real* __restrict__ gs, const double* __restrict__ gmean_d,
     real* __restrict__ gself, real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat,
-    double* __restrict__ ljpart)
+    double* __restrict__ ljpart, BucketArgs bk, int rec_cap)
 {
     constexpr int NLJ = 2 * kMaxTypesGrad * kMaxTypesGrad;
     constexpr int NW = kCoopBlock / 64;
     __shared__ real ljraw[2 * 256];  // sigma[nt2], eps[nt2]
     __shared__ double ljacc[NW][NLJ];
+    __shared__ int nrec;
+    extern __shared__ __align__(16) unsigned char bk_lds[];
+    real* rc = (real*)bk_lds;                              // [rec_cap][4]
+    int32_t* rj = (int32_t*)(rc + 4 * (size_t)rec_cap);    // [rec_cap] sorted index of j
+    uint16_t* rk = (uint16_t*)(rj + rec_cap);              // [rec_cap] key
+    const int span2 = bk.span * bk.span;
+    const int nkeys = 2 * span2;
+    int32_t* kcnt = (int32_t*)(rk + ((rec_cap + 1) & ~1));  // [nkeys] records per key
+    int32_t* kcur = kcnt + nkeys;                           // [nkeys] write cursor
+    int32_t* kbase = kcur + nkeys;                          // [nkeys] reserved offset in the bucket
+    int32_t* kdst = kbase + nkeys;                          // [nkeys] destination row
+    int32_t* kfirst = kdst + nkeys;                         // [nkeys] first atom of the row
+    int32_t* kcap = kfirst + nkeys;                         // [nkeys] bucket capacity
+    int32_t* kcount = kcap + nkeys;                         // [nkeys] atoms of the row in the LDS window
     const int nt2 = n_types * n_types;
     for (int t = threadIdx.x; t < 2 * nt2; t += kCoopBlock) ljraw[t] = ljraw_g[t];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (WANT_LJ)
         for (int t = lane; t < NLJ; t += 64) ljacc[wave][t] = 0.0;
+    if (BK) {
+        for (int t = threadIdx.x; t < nkeys; t += kCoopBlock) kcnt[t] = 0;
+        if (threadIdx.x == 0) nrec = 0;
+    }
     __syncthreads();
     const real mx = FULL ? (real)0 : (real)gmean_d[0];
     const real my = FULL ? (real)0 : (real)gmean_d[1];
@@ -473,6 +550,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const int64_t gw = blk * NW + wave;
     const int64_t a0 = gw * apw;
     const int64_t a1 = min(n, a0 + apw);
+    // cell row of the block's first atom: the block's atoms lie in rows row0, row0 + 1, ...
+    const int row0 = BK ? cell_row(spos[min(blk * NW * apw, n - 1)], bk.n_c) : 0;
     for (int64_t a = a0; a < a1; ++a) {
         const uint4 si = spos[a];
         const int ti = (int)si.w;
@@ -538,11 +617,44 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                 rx -= jx;
                 ry -= jy;
                 rz -= jz;
-                atomicAdd(&gscat[3 * (int64_t)j + 0], jx);
-                atomicAdd(&gscat[3 * (int64_t)j + 1], jy);
-                atomicAdd(&gscat[3 * (int64_t)j + 2], jz);
                 rq += w * (-ke * qj * g.a_coul) * gdi;
-                atomicAdd(&gqscat[j], w * (-ke * qi * g.a_coul) * gdi);
+                const real jq = w * (-ke * qi * g.a_coul) * gdi;
+                if (BK) {
+                    // key: (source row - row0, row offset of j); positions moved since the
+                    // lists were built can leave the window, and then take the atomics
+                    const int nc_ = bk.n_c;
+                    const int src = cell_row(si, nc_) - row0;  // wave-uniform
+                    const int dz = stencil_offset((int)(((uint64_t)sj.z * (uint32_t)nc_) >> 32),
+                                                  (int)(((uint64_t)si.z * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
+                                   bk.lo;
+                    const int dy = stencil_offset((int)(((uint64_t)sj.y * (uint32_t)nc_) >> 32),
+                                                  (int)(((uint64_t)si.y * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
+                                   bk.lo;
+                    if (src >= 0 && src < 2 && dz >= 0 && dz < bk.span && dy >= 0 && dy < bk.span) {
+                        const int key = src * span2 + dz * bk.span + dy;
+                        const uint64_t m = __ballot(1);
+                        const int leader = __ffsll((unsigned long long)m) - 1;
+                        int base = 0;
+                        if (lane == leader) base = atomicAdd(&nrec, __popcll(m));
+                        base = __shfl(base, leader, 64);
+                        const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                        if (slot < rec_cap) {
+                            rc[4 * slot + 0] = jx;
+                            rc[4 * slot + 1] = jy;
+                            rc[4 * slot + 2] = jz;
+                            rc[4 * slot + 3] = jq;
+                            rj[slot] = j;
+                            rk[slot] = (uint16_t)key;
+                            atomicAdd(&kcnt[key], 1);
+                        } else {
+                            scatter_atomic(gscat, gqscat, j, jx, jy, jz, jq);
+                        }
+                    } else {
+                        scatter_atomic(gscat, gqscat, j, jx, jy, jz, jq);
+                    }
+                } else {
+                    scatter_atomic(gscat, gqscat, j, jx, jy, jz, jq);
+                }
                 if (WANT_LJ) {
                     const int tj = (int)sj.w;
 #pragma unroll
@@ -604,10 +716,94 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             ljpart[blk * (int64_t)NLJ + threadIdx.x] = t;
         }
     }
+    if (BK) {
+        // reserve one range per key in its destination row's bucket
+        __syncthreads();
+        for (int t = threadIdx.x; t < nkeys; t += kCoopBlock) {
+            const int c = kcnt[t];
+            kcur[t] = 0;
+            if (c == 0) continue;
+            const int src = row0 + t / span2;
+            const int rem = t % span2;
+            const int dz = rem / bk.span + bk.lo, dy = rem % bk.span + bk.lo;
+            int z = src / bk.n_c + dz, y = src % bk.n_c + dy;
+            z = z < 0 ? z + bk.n_c : (z >= bk.n_c ? z - bk.n_c : z);
+            y = y < 0 ? y + bk.n_c : (y >= bk.n_c ? y - bk.n_c : y);
+            const int dst = z * bk.n_c + y;
+            const int64_t b0 = bucket_start(bk, dst);
+            const int64_t cap = bucket_start(bk, dst + 1) - b0;
+            kdst[t] = dst;
+            kfirst[t] = bk.cell_start[(int64_t)dst * bk.n_c];
+            kcount[t] = min(bk.cell_start[(int64_t)(dst + 1) * bk.n_c] - kfirst[t], kBucketRowLds);
+            kcap[t] = (int32_t)min(cap, (int64_t)INT32_MAX);
+            const unsigned long long old = atomicAdd(&bk.cursor[dst], (unsigned long long)c);
+            kbase[t] = (int32_t)min(old, (unsigned long long)INT32_MAX);
+        }
+        __syncthreads();
+        const int nr = min(nrec, rec_cap);
+        real* out_c = (real*)bk.rec_c;
+        for (int s = threadIdx.x; s < nr; s += kCoopBlock) {
+            const int key = rk[s];
+            const int64_t pos = (int64_t)kbase[key] + atomicAdd(&kcur[key], 1);
+            const int j = rj[s];
+            const int jrel = j - kfirst[key];
+            const int dst = kdst[key];
+            if (pos < kcap[key]) {
+                const int64_t at = bucket_start(bk, dst) + pos;
+                if (jrel >= 0 && jrel < kcount[key]) {
+                    out_c[4 * at + 0] = rc[4 * s + 0];
+                    out_c[4 * at + 1] = rc[4 * s + 1];
+                    out_c[4 * at + 2] = rc[4 * s + 2];
+                    out_c[4 * at + 3] = rc[4 * s + 3];
+                    bk.rec_j[at] = (uint16_t)jrel;
+                    continue;
+                }
+                bk.rec_j[at] = (uint16_t)0xffffu;  // reserved slot left empty
+            }
+            scatter_atomic(gscat, gqscat, (int64_t)j, rc[4 * s + 0], rc[4 * s + 1], rc[4 * s + 2], rc[4 * s + 3]);
+        }
+    }
 }
 
-template <typename real, bool FULL, bool WANT_LJ>
-static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step)
+// Reduce one destination row's bucket: LDS sums over its records, then added
+// to the row's scatter gradients (the atomics of the fallback paths already in
+// place). One block per row.
+template <typename real>
+__global__ __launch_bounds__(512) void k_bucket_reduce(BucketArgs bk, real* __restrict__ gscat,
+                                                       real* __restrict__ gqscat)
+{
+    __shared__ real acc[4 * kBucketRowLds];
+    const int row = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int first = bk.cell_start[(int64_t)row * bk.n_c];
+    const int count = bk.cell_start[(int64_t)(row + 1) * bk.n_c] - first;
+    const int nl = min(count, kBucketRowLds);
+    for (int t = threadIdx.x; t < 4 * nl; t += 512) acc[t] = (real)0;
+    const int64_t b0 = bucket_start(bk, row);
+    const int64_t cap = bucket_start(bk, row + 1) - b0;
+    const int64_t nr = (int64_t)min(bk.cursor[row], (unsigned long long)cap);
+    __syncthreads();
+    const real* rcg = (const real*)bk.rec_c + 4 * b0;
+    const uint16_t* rjg = bk.rec_j + b0;
+    for (int64_t s = threadIdx.x; s < nr; s += 512) {
+        const int jr = rjg[s];
+        if (jr >= nl) continue;
+        atomicAdd(&acc[4 * jr + 0], rcg[4 * s + 0]);
+        atomicAdd(&acc[4 * jr + 1], rcg[4 * s + 1]);
+        atomicAdd(&acc[4 * jr + 2], rcg[4 * s + 2]);
+        atomicAdd(&acc[4 * jr + 3], rcg[4 * s + 3]);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nl; k += 512) {
+        const int64_t j = first + k;
+        gscat[3 * j + 0] += acc[4 * k + 0];
+        gscat[3 * j + 1] += acc[4 * k + 1];
+        gscat[3 * j + 2] += acc[4 * k + 2];
+        gqscat[j] += acc[4 * k + 3];
+    }
+}
+
+template <typename real, bool FULL, bool WANT_LJ, bool BK>
+static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const BucketArgs& bk, int rec_cap, size_t lds)
 {
     const int64_t n = h->cfg.n_atoms;
     PairParams<real> pp;
@@ -617,34 +813,72 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step)
     pp.ke = (real)h->cfg.coulomb_k;
     hipError_t e = launch_draw(h, step);
     if (e != hipSuccess) return e;
-    const int64_t waves = blocks_for(n, kAtomsPerWave);
+    const int64_t waves = blocks_for(n, apw);
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     h->adj_nb = nb;
-    k_pair_adjoint<real, FULL, WANT_LJ><<<nb, kCoopBlock, 0, h->stream>>>(
-        n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core,
+    k_pair_adjoint<real, FULL, WANT_LJ, BK><<<nb, kCoopBlock, lds, h->stream>>>(
+        n, apw, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, h->xoff, h->xidx, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
         h->p_stride, h->ranks, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
-        (real*)h->gqscat, h->ljpart);
+        (real*)h->gqscat, h->ljpart, bk, rec_cap);
+    e = hipGetLastError();
+    if (e != hipSuccess || !BK) return e;
+    const unsigned rows = (unsigned)((int64_t)bk.n_c * bk.n_c);
+    k_bucket_reduce<real><<<rows, 512, 0, h->stream>>>(bk, (real*)h->gscat, (real*)h->gqscat);
     return hipGetLastError();
 }
 
-template <typename real>
-static hipError_t launch_adj_r(irbe_ctx* h, uint64_t step, bool want_lj)
+template <typename real, bool BK>
+static hipError_t launch_adj_r(irbe_ctx* h, uint64_t step, bool want_lj, int apw, const BucketArgs& bk, int rec_cap,
+                               size_t lds)
 {
     if (h->full_list)
-        return want_lj ? launch_adj_t<real, true, true>(h, step) : launch_adj_t<real, true, false>(h, step);
-    return want_lj ? launch_adj_t<real, false, true>(h, step) : launch_adj_t<real, false, false>(h, step);
+        return want_lj ? launch_adj_t<real, true, true, false>(h, step, apw, bk, 0, 0)
+                       : launch_adj_t<real, true, false, false>(h, step, apw, bk, 0, 0);
+    return want_lj ? launch_adj_t<real, false, true, BK>(h, step, apw, bk, rec_cap, lds)
+                   : launch_adj_t<real, false, false, BK>(h, step, apw, bk, rec_cap, lds);
 }
 
 hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool want_lj)
 {
     (void)want_q;
-    hipError_t e = launch_fill_bytes0(h->stream, h->gscat, 3 * (size_t)h->cfg.n_atoms * h->real_size);
+    const int64_t n = h->cfg.n_atoms;
+    hipError_t e = launch_fill_bytes0(h->stream, h->gscat, 3 * (size_t)n * h->real_size);
     if (e != hipSuccess) return e;
-    e = launch_fill_bytes0(h->stream, h->gqscat, (size_t)h->cfg.n_atoms * h->real_size);
+    e = launch_fill_bytes0(h->stream, h->gqscat, (size_t)n * h->real_size);
     if (e != hipSuccess) return e;
-    return h->fp64 ? launch_adj_r<double>(h, step, want_lj) : launch_adj_r<float>(h, step, want_lj);
+    // bucketed transpose of the shell scatter when a block of >= 8 atoms' records
+    // fits the LDS staging area and the keys fit their table
+    BucketArgs bk{};
+    bk.n_c = h->geo.n_c;
+    bk.lo = h->geo.lo;
+    bk.span = h->geo.hi - h->geo.lo + 1;
+    const int p_eff = std::max(1, std::min(h->cfg.p_shell, std::max(h->max_shell, 1)));
+    const int rec_cap = h->fp64 ? kBucketRecD : kBucketRecF;
+    const int apw = std::min(kAtomsPerWave, rec_cap / (4 * p_eff));
+    const int nkeys = 2 * bk.span * bk.span;
+    const bool use_bk = !h->full_list && apw >= 2 && nkeys <= kBucketMaxKeys;
+    size_t lds = 0;
+    if (use_bk) {
+        bk.p9 = 9 * (int64_t)p_eff;
+        const int64_t rows = (int64_t)bk.n_c * bk.n_c;
+        const int64_t total = ((int64_t)n * bk.p9 >> 3) + (int64_t)kBucketSlack * (rows + 1);
+        e = ensure_buckets(h, total);
+        if (e != hipSuccess) return e;
+        e = launch_fill_i32(h->stream, (int32_t*)h->bk_cursor, 0, 2 * rows);
+        if (e != hipSuccess) return e;
+        bk.cell_start = h->cell_start;
+        bk.cursor = h->bk_cursor;
+        bk.rec_c = h->bk_c;
+        bk.rec_j = h->bk_j;
+        lds = (size_t)rec_cap * (4 * h->real_size + 4) + (size_t)((rec_cap + 1) & ~1) * 2 + (size_t)nkeys * 7 * 4;
+    }
+    if (h->fp64)
+        return use_bk ? launch_adj_r<double, true>(h, step, want_lj, apw, bk, rec_cap, lds)
+                      : launch_adj_r<double, false>(h, step, want_lj, kAtomsPerWave, bk, 0, 0);
+    return use_bk ? launch_adj_r<float, true>(h, step, want_lj, apw, bk, rec_cap, lds)
+                  : launch_adj_r<float, false>(h, step, want_lj, kAtomsPerWave, bk, 0, 0);
 }
 
 }  // namespace irbe

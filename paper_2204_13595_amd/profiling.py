@@ -23,7 +23,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 KERNEL_SOURCES = {"k_build_lists": "k_lists.hip", "k_pair_coop": "k_pair.hip", "k_pair_adjoint": "k_pair.hip",
-                  "k_rho_partial": "k_kspace.hip", "k_kspace_forces": "k_kspace.hip", "k_draw_batches": "k_pair.hip"}
+                  "k_rho_partial": "k_kspace.hip", "k_kspace_forces": "k_kspace.hip", "k_draw_batches": "k_pair.hip", "k_bucket_reduce": "k_pair.hip"}
 
 
 def source_hash(kernel: str) -> str | None:

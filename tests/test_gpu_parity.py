@@ -107,12 +107,23 @@ def test_forces_energies_parity(orc, name, precision, p_shell, tol_f, tol_e):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
-@pytest.mark.parametrize("p_shell", [100, 0])
-def test_backward_parity(orc, precision, tol, p_shell):
-    w = inputs.workload("water512")
+@pytest.mark.parametrize("name,p_shell,moved", [("water512", 100, False), ("water512", 0, False),
+                                                ("water4k", 100, False), ("water4k", 300, False),
+                                                ("water4k", 100, True)])
+def test_backward_parity(orc, precision, tol, name, p_shell, moved):
+    """p_shell = 100 takes the bucketed shell scatter, 300 the direct-atomic one
+    (a block's records exceed the staging area); `moved` evaluates at positions
+    displaced by up to 0.04 nm after the lists were built, so that some pairs
+    leave their build-time cell rows and take the fallback atomics."""
+    w = inputs.workload(name)
     step = 5
     h, pos, q, pos_np, q_np = _setup(w, precision, p_shell=p_shell)
     h.build_lists(pos, step)
+    s_build = orc.quantize(pos_np, w.box)
+    if moved:
+        disp = np.random.default_rng(12).uniform(-0.04, 0.04, size=pos_np.shape)
+        pos = pos + torch.tensor(disp, dtype=pos.dtype, device=pos.device)
+        pos_np = pos.double().cpu().numpy()
     G = np.random.default_rng(11).standard_normal((w.n_atoms, 3))
     Gt = torch.tensor(G, dtype=pos.dtype, device=pos.device)
     gp, gq, gl = h.compute_forces_backward(pos, step, Gt)
@@ -121,7 +132,9 @@ def test_backward_parity(orc, precision, tol, p_shell):
     gl = gl.cpu().numpy()
     p = _oracle_params(orc, w, p_shell=p_shell)
     mode = "full" if p_shell <= 0 else "rbl"
-    ref = orc.forward(pos_np, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step, mode=mode)
+    lists = orc.build_lists(s_build, w.molecule, w.box, 0.5, 1.2, full=p_shell <= 0)
+    ref = orc.forward(None, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step, mode=mode,
+                      s=orc.quantize(pos_np, w.box), lists=lists)
     G_used = Gt.double().cpu().numpy()
     r_pos, r_q, r_sig, r_eps = orc.backward(G_used, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, ref,
                                             mode=mode)
