@@ -89,7 +89,7 @@ namespace irbe {
 hipError_t ensure_buckets(irbe_ctx* h, int64_t records)
 {
     hipError_t e = hipSuccess;
-    if (!h->bk_cursor) e = dalloc(h, &h->bk_cursor, (size_t)h->geo.n_c * (size_t)h->geo.n_c);
+    if (!h->bk_cursor) e = dalloc(h, &h->bk_cursor, 2 * (size_t)h->geo.n_c * (size_t)h->geo.n_c);
     if (e != hipSuccess || records <= h->bk_total) return e;
     dfree(h, h->bk_c);
     dfree(h, h->bk_j);

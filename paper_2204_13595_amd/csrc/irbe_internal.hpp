@@ -25,8 +25,8 @@ constexpr int kAtomsPerWave = 8;     // atoms per wavefront in the cooperative p
 // Shell-adjoint transpose: scatter records staged per block in LDS, then
 // bucketed by destination cell row (y, z) and reduced per row.
 constexpr int kBucketRowLds = 2048;  // atoms of a row accumulated in LDS (the rest: device atomics)
-constexpr int kBucketRecF = 2048;    // staged records per block, FP32
-constexpr int kBucketRecD = 1024;    // staged records per block, FP64
+constexpr int kBucketRecF = 1024;    // staged records per block, FP32
+constexpr int kBucketRecD = 512;     // staged records per block, FP64
 constexpr int kBucketMaxKeys = 256;  // (source row, destination row) keys per block
 constexpr int kBucketSlack = 64;     // records of spare capacity per destination row
 
@@ -147,7 +147,7 @@ struct irbe_ctx {
     int64_t adj_nb = 0;               // blocks of the last pair-adjoint launch
     int64_t pair_nb = 0;              // blocks of the last pair-force launch
     int64_t part_blocks = 0;          // capacity (blocks) of pair_part and ljpart
-    unsigned long long* bk_cursor = nullptr;  // [n_c^2] records reserved per destination row
+    unsigned long long* bk_cursor = nullptr;  // [2 n_c^2] records reserved per destination row, then max |record|
     void* bk_c = nullptr;             // real[4 * bk_total] shell-adjoint records: dL/dr_j (3), dL/dq_j
     uint16_t* bk_j = nullptr;         // [bk_total] record's atom, relative to its row's first atom
     int64_t bk_total = 0;             // allocated records

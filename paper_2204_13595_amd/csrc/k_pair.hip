@@ -384,7 +384,12 @@ hipError_t launch_pair_forces(irbe_ctx* h, uint64_t step, bool ev)
 // (source row, destination row) key, reserves one contiguous range per key in
 // the destination row's bucket with a single atomic, and writes the records
 // there. A second kernel reduces each row's bucket in LDS and adds the row's
-// gradients with plain stores. Records that do not fit (a third source row in
+// gradients with plain stores. LDS floating-point atomics are several times
+// slower than integer ones here, so the row sums are accumulated in 64-bit
+// fixed point, scaled by a power of two chosen from the row's largest record
+// (bounded above by the largest component any contributing block staged)
+// and record count so that no sum can overflow (integer sums are also
+// independent of the order). Records that do not fit (a third source row in
 // one block, a full bucket, an atom beyond the LDS row window) fall back to
 // device atomics, so the result never depends on the capacities.
 // ---------------------------------------------------------------------------
@@ -396,34 +401,58 @@ struct PairGrad {
     real dc_dsig;       // d c_lj / d sigma
 };
 
+// LJ constants of one type pair for the adjoint (sigma powers folded in).
 template <typename real>
-__device__ __forceinline__ PairGrad<real> pair_grad(real r2, real qq, real sig, real eps, const PairParams<real>& pp)
+struct LJGrad {
+    real a48, b24;    // 48 s^12, 24 s^6:   c_lj = (a48 r^-6 - b24) r^-8
+    real a672, b192;  // 672 s^12, 192 s^6: d c_lj / dr = (b192 - a672 r^-6) r^-9
+    real as, bs;      // 576 s^11, 144 s^5: d c_lj / d sigma = (as r^-6 - bs) r^-8
+    real eps, pad;
+};
+
+template <typename real>
+__device__ __forceinline__ LJGrad<real> lj_grad_entry(real sig, real eps)
+{
+    const real s2 = sig * sig;
+    const real s6 = s2 * s2 * s2;
+    const real s12 = s6 * s6;
+    LJGrad<real> L;
+    L.a48 = (real)48 * s12;
+    L.b24 = (real)24 * s6;
+    L.a672 = (real)672 * s12;
+    L.b192 = (real)192 * s6;
+    L.as = sig != (real)0 ? (real)576 * s12 / sig : (real)0;
+    L.bs = sig != (real)0 ? (real)144 * s6 / sig : (real)0;
+    L.eps = eps;
+    L.pad = 0;
+    return L;
+}
+
+template <typename real>
+__device__ __forceinline__ PairGrad<real> pair_grad(real r2, real qq, const LJGrad<real>& L, const PairParams<real>& pp)
 {
     using M = Math<real>;
     const real rinv = M::rsqrt_(r2);
     const real r = r2 * rinv;
     const real br = pp.beta * r;
     const real ex = M::exp_(-br * br);
-    const real ec = M::erfc_(br);
+    const real ec = M::erfc_ex(br, ex);
     const real rinv2 = rinv * rinv;
     const real rinv3 = rinv2 * rinv;
     const real A = ec * rinv3;
     const real B = pp.cgauss * ex * rinv2;
-    const real dA = -pp.cgauss * ex * rinv3 - (real)3 * ec * rinv3 * rinv;
-    const real dB = -pp.cgauss * ex * ((real)2 * pp.beta * pp.beta * rinv + (real)2 * rinv3);
-    const real s2 = sig * sig;
-    const real s6 = s2 * s2 * s2;
-    const real s12 = s6 * s6;
+    const real dA = -rinv * (B + (real)3 * A);
+    const real dB = -B * ((real)2 * pp.beta * pp.beta * r + (real)2 * rinv);
     const real r6 = rinv2 * rinv2 * rinv2;
-    const real C = rinv2 * r6 * ((real)48 * s12 * r6 - (real)24 * s6);
-    const real dC = rinv * rinv2 * r6 * ((real)-672 * s12 * r6 + (real)192 * s6);
-    const real dCs = sig != (real)0 ? rinv2 * r6 * ((real)576 * s12 * r6 - (real)144 * s6) / sig : (real)0;
+    const real r8 = r6 * rinv2;
+    const real C = r8 * (L.a48 * r6 - L.b24);
+    const real dC = rinv * r8 * (L.b192 - L.a672 * r6);
     PairGrad<real> g;
     g.a_coul = A + B;
-    g.phi = -qq * (A + B) - eps * C;
-    g.dphi_r = (-qq * (dA + dB) - eps * dC) * rinv;
+    g.phi = -qq * (A + B) - L.eps * C;
+    g.dphi_r = (-qq * (dA + dB) - L.eps * dC) * rinv;
     g.c_lj = C;
-    g.dc_dsig = dCs;
+    g.dc_dsig = r8 * (L.as * r6 - L.bs);
     return g;
 }
 
@@ -465,6 +494,7 @@ struct BucketArgs {
     int64_t p9;                   // 9 * p_eff
     const int32_t* cell_start;
     unsigned long long* cursor;   // [n_c^2] records reserved per destination row
+    unsigned long long* rowmax;   // [n_c^2] bits of the largest |record component| (as a non-negative double)
     void* rec_c;                  // real[4 * total]
     uint16_t* rec_j;              // [total]
 };
@@ -516,9 +546,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
 {
     constexpr int NLJ = 2 * kMaxTypesGrad * kMaxTypesGrad;
     constexpr int NW = kCoopBlock / 64;
-    __shared__ real ljraw[2 * 256];  // sigma[nt2], eps[nt2]
+    __shared__ LJGrad<real> ljg[256];
     __shared__ double ljacc[NW][NLJ];
     __shared__ int nrec;
+    __shared__ double bmaxw[NW];
     extern __shared__ __align__(16) unsigned char bk_lds[];
     real* rc = (real*)bk_lds;                              // [rec_cap][4]
     int32_t* rj = (int32_t*)(rc + 4 * (size_t)rec_cap);    // [rec_cap] sorted index of j
@@ -533,7 +564,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int32_t* kcap = kfirst + nkeys;                         // [nkeys] bucket capacity
     int32_t* kcount = kcap + nkeys;                         // [nkeys] atoms of the row in the LDS window
     const int nt2 = n_types * n_types;
-    for (int t = threadIdx.x; t < 2 * nt2; t += kCoopBlock) ljraw[t] = ljraw_g[t];
+    for (int t = threadIdx.x; t < nt2; t += kCoopBlock) ljg[t] = lj_grad_entry(ljraw_g[t], ljraw_g[nt2 + t]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (WANT_LJ)
         for (int t = lane; t < NLJ; t += 64) ljacc[wave][t] = 0.0;
@@ -552,6 +583,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const int64_t a1 = min(n, a0 + apw);
     // cell row of the block's first atom: the block's atoms lie in rows row0, row0 + 1, ...
     const int row0 = BK ? cell_row(spos[min(blk * NW * apw, n - 1)], bk.n_c) : 0;
+    real lane_max = 0;  // largest |component| of the records this lane staged
     for (int64_t a = a0; a < a1; ++a) {
         const uint4 si = spos[a];
         const int ti = (int)si.w;
@@ -571,10 +603,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
             const real r2 = dx * dx + dy * dy + dz * dz;
-            const int tp = ti * n_types + (int)sj.w;
-            const real sig = ljraw[tp], eps = ljraw[nt2 + tp];
+            const LJGrad<real>& L = ljg[ti * n_types + (int)sj.w];
             const real qj = sqr[j];
-            const PairGrad<real> g = pair_grad(r2, ke * qi * qj, sig, eps, pp);
+            const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp);
             const real ex_ = gs[3 * j] - mx - pgx, ey_ = gs[3 * j + 1] - my - pgy, ez_ = gs[3 * j + 2] - mz - pgz;
             const real gd = dx * ex_ + dy * ey_ + dz * ez_;
             rx += g.phi * ex_ + g.dphi_r * dx * gd;
@@ -587,7 +618,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
 #pragma unroll
                 for (int t = 0; t < kMaxTypesGrad; ++t)
                     if (t == tj) {
-                        acc_sig[t] += -eps * g.dc_dsig * gdi;
+                        acc_sig[t] += -L.eps * g.dc_dsig * gdi;
                         acc_eps[t] += -g.c_lj * gdi;
                     }
             }
@@ -606,10 +637,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                 real dx, dy, dz;
                 separation(si, sj, pp.quantum, dx, dy, dz);
                 const real r2 = dx * dx + dy * dy + dz * dz;
-                const int tp = ti * n_types + (int)sj.w;
-                const real sig = ljraw[tp], eps = ljraw[nt2 + tp];
+                const LJGrad<real>& L = ljg[ti * n_types + (int)sj.w];
                 const real qj = sqr[j];
-                const PairGrad<real> g = pair_grad(r2, ke * qi * qj, sig, eps, pp);
+                const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp);
                 const real gdi = dx * pgx + dy * pgy + dz * pgz;
                 const real jx = w * (g.phi * pgx + g.dphi_r * dx * gdi);
                 const real jy = w * (g.phi * pgy + g.dphi_r * dy * gdi);
@@ -646,6 +676,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                             rj[slot] = j;
                             rk[slot] = (uint16_t)key;
                             atomicAdd(&kcnt[key], 1);
+                            lane_max = fmax(lane_max, fmax(fmax(fabs(jx), fabs(jy)), fmax(fabs(jz), fabs(jq))));
                         } else {
                             scatter_atomic(gscat, gqscat, j, jx, jy, jz, jq);
                         }
@@ -660,7 +691,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
 #pragma unroll
                     for (int t = 0; t < kMaxTypesGrad; ++t)
                         if (t == tj) {
-                            acc_sig[t] += w * (-eps * g.dc_dsig * gdi);
+                            acc_sig[t] += w * (-L.eps * g.dc_dsig * gdi);
                             acc_eps[t] += w * (-g.c_lj * gdi);
                         }
                 }
@@ -717,8 +748,16 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         }
     }
     if (BK) {
-        // reserve one range per key in its destination row's bucket
+        // reserve one range per key in its destination row's bucket, and raise the
+        // row's bound on |record| to this block's largest staged component
+        double wmax = (double)lane_max;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wmax = fmax(wmax, __shfl_xor(wmax, off, 64));
+        if (lane == 0) bmaxw[wave] = wmax;
         __syncthreads();
+        double bmax = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) bmax = fmax(bmax, bmaxw[w]);
         for (int t = threadIdx.x; t < nkeys; t += kCoopBlock) {
             const int c = kcnt[t];
             kcur[t] = 0;
@@ -738,6 +777,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             kcap[t] = (int32_t)min(cap, (int64_t)INT32_MAX);
             const unsigned long long old = atomicAdd(&bk.cursor[dst], (unsigned long long)c);
             kbase[t] = (int32_t)min(old, (unsigned long long)INT32_MAX);
+            atomicMax(&bk.rowmax[dst], (unsigned long long)__double_as_longlong(bmax));
         }
         __syncthreads();
         const int nr = min(nrec, rec_cap);
@@ -765,40 +805,79 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     }
 }
 
-// Reduce one destination row's bucket: LDS sums over its records, then added
-// to the row's scatter gradients (the atomics of the fallback paths already in
-// place). One block per row.
+template <typename real>
+struct Rec4;
+template <>
+struct Rec4<float> {
+    using type = float4;
+};
+template <>
+struct Rec4<double> {
+    using type = double4;
+};
+
+// Reduce one destination row's bucket: 64-bit fixed-point LDS sums over its
+// records, then added to the row's scatter gradients (the atomics of the
+// fallback paths already in place). One block per row. With m a bound on the
+// row's largest |record component| and nr its record count, values are scaled
+// by 2^sh with m nr 2^sh < 2^62, so no partial sum overflows.
 template <typename real>
 __global__ __launch_bounds__(512) void k_bucket_reduce(BucketArgs bk, real* __restrict__ gscat,
                                                        real* __restrict__ gqscat)
 {
-    __shared__ real acc[4 * kBucketRowLds];
+    __shared__ long long acc[4 * kBucketRowLds];  // component-major: acc[d * kBucketRowLds + j]
     const int row = (int)xcd_block(blockIdx.x, gridDim.x);
     const int first = bk.cell_start[(int64_t)row * bk.n_c];
     const int count = bk.cell_start[(int64_t)(row + 1) * bk.n_c] - first;
     const int nl = min(count, kBucketRowLds);
-    for (int t = threadIdx.x; t < 4 * nl; t += 512) acc[t] = (real)0;
     const int64_t b0 = bucket_start(bk, row);
     const int64_t cap = bucket_start(bk, row + 1) - b0;
     const int64_t nr = (int64_t)min(bk.cursor[row], (unsigned long long)cap);
+    const double mx = __longlong_as_double((long long)bk.rowmax[row]);
+    if (nr == 0 || !(mx > 0.0)) return;  // block-uniform: no records or all zero
+    int e;
+    frexp(mx * (double)nr, &e);  // mx nr < 2^e
+    const int sh = 62 - e;
+    for (int t = threadIdx.x; t < nl; t += 512)
+        for (int d = 0; d < 4; ++d) acc[d * kBucketRowLds + t] = 0;
     __syncthreads();
-    const real* rcg = (const real*)bk.rec_c + 4 * b0;
+    using V4 = typename Rec4<real>::type;
+    const V4* rcg = (const V4*)bk.rec_c + b0;
     const uint16_t* rjg = bk.rec_j + b0;
-    for (int64_t s = threadIdx.x; s < nr; s += 512) {
-        const int jr = rjg[s];
-        if (jr >= nl) continue;
-        atomicAdd(&acc[4 * jr + 0], rcg[4 * s + 0]);
-        atomicAdd(&acc[4 * jr + 1], rcg[4 * s + 1]);
-        atomicAdd(&acc[4 * jr + 2], rcg[4 * s + 2]);
-        atomicAdd(&acc[4 * jr + 3], rcg[4 * s + 3]);
+    // kU records per thread per pass, all loads issued before the LDS updates
+    // (indices past the end are clamped to the last record and then ignored)
+    constexpr int kU = 4;
+    for (int64_t s0 = 0; s0 < nr; s0 += 512 * kU) {
+        int jr[kU];
+        V4 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t s = s0 + u * 512 + threadIdx.x;
+            const int64_t sc = min(s, nr - 1);
+            jr[u] = rjg[sc];
+            v[u] = rcg[sc];
+            if (s >= nr) jr[u] = nl;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (jr[u] >= nl) continue;
+            atomicAdd((unsigned long long*)&acc[0 * kBucketRowLds + jr[u]],
+                      (unsigned long long)__double2ll_rn(ldexp((double)v[u].x, sh)));
+            atomicAdd((unsigned long long*)&acc[1 * kBucketRowLds + jr[u]],
+                      (unsigned long long)__double2ll_rn(ldexp((double)v[u].y, sh)));
+            atomicAdd((unsigned long long*)&acc[2 * kBucketRowLds + jr[u]],
+                      (unsigned long long)__double2ll_rn(ldexp((double)v[u].z, sh)));
+            atomicAdd((unsigned long long*)&acc[3 * kBucketRowLds + jr[u]],
+                      (unsigned long long)__double2ll_rn(ldexp((double)v[u].w, sh)));
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nl; k += 512) {
         const int64_t j = first + k;
-        gscat[3 * j + 0] += acc[4 * k + 0];
-        gscat[3 * j + 1] += acc[4 * k + 1];
-        gscat[3 * j + 2] += acc[4 * k + 2];
-        gqscat[j] += acc[4 * k + 3];
+        gscat[3 * j + 0] += (real)ldexp((double)acc[0 * kBucketRowLds + k], -sh);
+        gscat[3 * j + 1] += (real)ldexp((double)acc[1 * kBucketRowLds + k], -sh);
+        gscat[3 * j + 2] += (real)ldexp((double)acc[2 * kBucketRowLds + k], -sh);
+        gqscat[j] += (real)ldexp((double)acc[3 * kBucketRowLds + k], -sh);
     }
 }
 
@@ -866,10 +945,11 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
         const int64_t total = ((int64_t)n * bk.p9 >> 3) + (int64_t)kBucketSlack * (rows + 1);
         e = ensure_buckets(h, total);
         if (e != hipSuccess) return e;
-        e = launch_fill_i32(h->stream, (int32_t*)h->bk_cursor, 0, 2 * rows);
+        e = launch_fill_i32(h->stream, (int32_t*)h->bk_cursor, 0, 4 * rows);
         if (e != hipSuccess) return e;
         bk.cell_start = h->cell_start;
         bk.cursor = h->bk_cursor;
+        bk.rowmax = h->bk_cursor + rows;
         bk.rec_c = h->bk_c;
         bk.rec_j = h->bk_j;
         lds = (size_t)rec_cap * (4 * h->real_size + 4) + (size_t)((rec_cap + 1) & ~1) * 2 + (size_t)nkeys * 7 * 4;
