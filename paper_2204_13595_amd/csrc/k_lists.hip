@@ -39,33 +39,6 @@ __device__ __forceinline__ uint64_t dist2_exact(uint4 a, uint4 b)
 
 __device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-// Append v to a row through a 4-entry register buffer (16-byte stores).
-struct RowWriter {
-    int32_t* row;
-    int cap;
-    int count;
-    int b0, b1, b2;
-
-    __device__ __forceinline__ void push(int v)
-    {
-        const int slot = count & 3;
-        if (slot == 0) b0 = v;
-        else if (slot == 1) b1 = v;
-        else if (slot == 2) b2 = v;
-        else if (count < cap) *(int4*)(row + (count - 3)) = make_int4(b0, b1, b2, v);
-        ++count;
-    }
-
-    __device__ __forceinline__ void flush()
-    {
-        const int slot = count & 3;
-        const int base = count - slot;
-        if (slot > 0 && base < cap) row[base] = b0;
-        if (slot > 1 && base + 1 < cap) row[base + 1] = b1;
-        if (slot > 2 && base + 2 < cap) row[base + 2] = b2;
-    }
-};
-
 // Distance (quanta) from coordinate s to the slab of cell c on one axis when
 // the slab lies at offset d (d > 0 above, d < 0 below); bound[c] is the first
 // coordinate of cell c (bound[n_c] wraps to 0).
@@ -74,6 +47,12 @@ __device__ __forceinline__ uint32_t slab_gap(uint32_t s, int d, int c, const uin
     if (d > 0) return bound[c] - s;
     if (d < 0) return s - (bound[c + 1] - 1u);
     return 0u;
+}
+
+// Number of set bits of mask below this lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 template <bool FULL>
@@ -85,10 +64,14 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     int32_t* __restrict__ ncore, int32_t* __restrict__ shell, int32_t* __restrict__ nshell,
     int32_t* __restrict__ maxcnt)
 {
-    __shared__ uint4 tile[kTileCap];
-    __shared__ int32_t tmol[kTileCap];
+    __shared__ uint4 tile[kTileCap];      // staged candidates: fixed-point x, y, z and sorted index
+    __shared__ int32_t tmol[kTileCap];    // candidate's exclusion id (molecule, or -2 - index)
+    __shared__ uint4 apos[kListWave];     // atom's x, y, z and exclusion id
+    __shared__ int2 arng[kListWave];      // atom's candidate range in the tile
+    __shared__ int2 acnt[kListWave];      // atom's core / shell list lengths so far
     const uint32_t* bound = bound_g;  // indexed by wave-uniform cell coordinates
     const int lane = threadIdx.x;
+    const int half = lane >> 5, hl = lane & 31;
     const int groups_per_row = (n_c + G - 1) / G;
     const int g = (int)xcd_block(blockIdx.x, gridDim.x);
     const int rowid = g / groups_per_row;
@@ -105,19 +88,20 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     for (int chunk = a0; chunk < a1; chunk += kListWave) {
         const int k = chunk + lane;
         const bool act = k < a1;
+        const int na = min(kListWave, a1 - chunk);
         const uint4 si = act ? spos[k] : make_uint4(0, 0, 0, 0);
         const int32_t mi = act ? smol[k] : -1;
         const int cx = (int)(((uint64_t)si.x * (uint32_t)n_c) >> 32);
         const int ti = act ? wrap(cx - x0, n_c) : 0;  // lane's home cell in [0, gr)
-        int32_t* crow = core + (int64_t)(act ? k : 0) * cap_core;  // core entries are few: stored directly
-        int nc = 0;
-        RowWriter ws{shell + (int64_t)(act ? k : 0) * cap_shell, cap_shell, 0, 0, 0, 0};
+        apos[lane] = make_uint4(si.x, si.y, si.z, (uint32_t)(mi >= 0 ? mi : -2 - k));
+        acnt[lane] = make_int2(0, 0);
         for (int dz = lo; dz <= hi; ++dz) {
             const int z = wrap(cz + dz, n_c);
             const float gz = prune ? (float)slab_gap(si.z, dz, z, bound) : 0.0f;
             for (int dy = lo; dy <= hi; ++dy) {
                 const int y = wrap(cy + dy, n_c);
                 const int row = (z * n_c + y) * n_c;
+                const bool core_row = !FULL && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
                 // lane's candidate cells in this row: tile cells [u_lo, u_hi]
                 int u_lo = ti, u_hi = ti + span_c - 1;
                 bool need = act;
@@ -167,8 +151,10 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                     for (int t = lane; t < cnt; t += kListWave) {
                         const int p = base + t;
                         const int j = p < nA ? jA + p : jB + (p - nA);
-                        tile[t] = spos[j];
-                        tmol[t] = smol[j];
+                        const uint4 sj = spos[j];
+                        const int32_t mj = smol[j];
+                        tile[t] = make_uint4(sj.x, sj.y, sj.z, (uint32_t)j);
+                        tmol[t] = mj >= 0 ? mj : -2 - j;
                     }
                     __syncthreads();
                     if (prune && need && total <= kTileCap) {
@@ -189,54 +175,83 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         }
                         p_hi = a;
                     }
-                    const int s0 = max(p_lo, base), s1 = min(p_hi, base + cnt);
-                    // classify one staged candidate (FP32 estimate, exact test near a threshold)
-                    auto visit = [&](int p, uint4 sj) {
-                        const float fx = (float)(int32_t)(sj.x - si.x);
-                        const float fy = (float)(int32_t)(sj.y - si.y);
-                        const float fz = (float)(int32_t)(sj.z - si.z);
-                        const float d2f = fx * fx + fy * fy + fz * fz;
-                        if (d2f > tfs_hi) return;
-                        const int j = p < nA ? jA + p : jB + (p - nA);
-                        if (j == k || (mi >= 0 && tmol[p - base] == mi)) return;
-                        int cls;
-                        if (FULL) {
-                            cls = d2f < tfs_lo ? 2 : (dist2_exact(si, sj) <= t_shell ? 2 : 0);
-                        } else if (d2f < tfc_lo) {
-                            cls = 1;
-                        } else if (d2f > tfc_hi && d2f < tfs_lo) {
-                            cls = 2;
-                        } else {
-                            const uint64_t d2 = dist2_exact(si, sj);
-                            cls = d2 <= t_core ? 1 : (d2 <= t_shell ? 2 : 0);
+                    // this tile's part of the lane's range, in tile coordinates
+                    const int s0 = need ? max(p_lo, base) - base : 0;
+                    const int s1 = need ? min(p_hi, base + cnt) - base : 0;
+                    arng[lane] = make_int2(s0, max(s1, s0));
+                    __syncthreads();
+                    // two atoms at a time, one per half-wave; the lanes of a half run over
+                    // the atom's candidates and the members are compacted in candidate order
+                    for (int pa = 0; pa < na; pa += 2) {
+                        const int ka = min(pa + half, na - 1);
+                        const bool hv = pa + half < na;
+                        const int2 rg = arng[ka];
+                        const int len = hv ? rg.y - rg.x : 0;
+                        const int maxlen = max(len, __shfl_xor(len, 32, 64));
+                        if (maxlen == 0) continue;
+                        const uint4 sa = apos[ka];
+                        const int32_t ma = (int32_t)sa.w;
+                        const int kk = chunk + ka;
+                        int2 c = acnt[ka];
+                        int32_t* srow = shell + (int64_t)kk * cap_shell;
+                        int32_t* crow = core + (int64_t)kk * cap_core;
+                        for (int c0 = 0; c0 < maxlen; c0 += 32) {
+                            const int q = (rg.x + c0 + hl) & (kTileCap - 1);
+                            const uint4 sj = tile[q];
+                            const int32_t mj = tmol[q];
+                            const int32_t ddx = (int32_t)(sj.x - sa.x);
+                            const int32_t ddy = (int32_t)(sj.y - sa.y);
+                            const int32_t ddz = (int32_t)(sj.z - sa.z);
+                            const float fx = (float)ddx, fy = (float)ddy, fz = (float)ddz;
+                            const float d2f = fx * fx + fy * fy + fz * fz;
+                            const bool keep = c0 + hl < len && mj != ma;
+                            bool in_core = !FULL && keep && d2f < tfc_lo;
+                            bool in_shell = keep && (FULL || d2f > tfc_hi) && d2f < tfs_lo;
+                            const bool amb = keep && d2f <= tfs_hi && !in_core && !in_shell;
+                            if (__ballot(amb)) {
+                                // within 2e-6 of a threshold: the exact integer test decides
+                                if (amb) {
+                                    const uint64_t d2 = (uint64_t)((int64_t)ddx * ddx) +
+                                                        (uint64_t)((int64_t)ddy * ddy) + (uint64_t)((int64_t)ddz * ddz);
+                                    in_core = !FULL && d2 <= t_core;
+                                    in_shell = !in_core && d2 <= t_shell;
+                                }
+                            }
+                            const uint64_t m_shell = __ballot(in_shell);
+                            // positions within the half: members below this lane, minus the
+                            // other half's members when this is the upper half
+                            const int s_lo = __popc((uint32_t)m_shell);
+                            const int s_hi = __popc((uint32_t)(m_shell >> 32));
+                            if (in_shell) {
+                                const int pos = c.y + lanes_below(m_shell) - (half ? s_lo : 0);
+                                if (pos < cap_shell) srow[pos] = (int32_t)sj.w;
+                            }
+                            c.y += half ? s_hi : s_lo;
+                            if (core_row) {
+                                const uint64_t m_core = __ballot(in_core);
+                                const int c_lo = __popc((uint32_t)m_core);
+                                const int c_hi = __popc((uint32_t)(m_core >> 32));
+                                if (in_core) {
+                                    const int pos = c.x + lanes_below(m_core) - (half ? c_lo : 0);
+                                    if (pos < cap_core) crow[pos] = (int32_t)sj.w;
+                                }
+                                c.x += half ? c_hi : c_lo;
+                            }
                         }
-                        if (cls == 1) {
-                            if (nc < cap_core) crow[nc] = j;
-                            ++nc;
-                        } else if (cls == 2) {
-                            ws.push(j);
-                        }
-                    };
-                    int p = s0;
-                    for (; p + 4 <= s1; p += 4) {
-                        const uint4 q0 = tile[p - base], q1 = tile[p + 1 - base];
-                        const uint4 q2 = tile[p + 2 - base], q3 = tile[p + 3 - base];
-                        visit(p, q0);
-                        visit(p + 1, q1);
-                        visit(p + 2, q2);
-                        visit(p + 3, q3);
+                        if (hv && hl == 0) acnt[ka] = c;
                     }
-                    for (; p < s1; ++p) visit(p, tile[p - base]);
                 }
             }
         }
+        __syncthreads();
         if (act) {
-            ws.flush();
-            ncore[k] = nc;
-            nshell[k] = ws.count;
-            maxc = max(maxc, nc);
-            maxs = max(maxs, ws.count);
+            const int2 c = acnt[lane];
+            ncore[k] = c.x;
+            nshell[k] = c.y;
+            maxc = max(maxc, c.x);
+            maxs = max(maxs, c.y);
         }
+        __syncthreads();
     }
     // one atomic per wave
 #pragma unroll

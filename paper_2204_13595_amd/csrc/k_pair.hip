@@ -534,7 +534,7 @@ __device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_
 // shell scatter goes through the LDS-staged buckets (dynamic LDS: rec_cap
 // records of 4 reals + j + key, then 7 ints per key).
 template <typename real, bool FULL, bool WANT_LJ, bool BK>
-__global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
+__global__ __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
