@@ -371,6 +371,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc(h, &h->spos, n));
     ALLOC(dalloc_bytes(h, &h->sq_r, n * rs));
     ALLOC(dalloc(h, &h->smol, n));
+    ALLOC(dalloc(h, &h->sxr, n));
     ALLOC(dalloc(h, &h->ncore, n));
     h->p_stride = c.p_shell > 0 ? (c.p_shell + 3) / 4 * 4 : 0;
     if (h->p_stride > 0) ALLOC(dalloc(h, &h->ranks, n * (size_t)h->p_stride));
@@ -482,9 +483,11 @@ irbe_status irbe_set_system(irbe_handle h, const int32_t* type, const void* char
     }
     dfree(h, h->xoff);
     dfree(h, h->xidx);
-    h->xoff = h->xidx = nullptr;
+    dfree(h, h->sxidx);
+    h->xoff = h->xidx = h->sxidx = nullptr;
     IRBE_TRY(h, dalloc(h, &h->xoff, n + 1), "alloc exclusions");
     IRBE_TRY(h, dalloc(h, &h->xidx, idx.size()), "alloc exclusions");
+    IRBE_TRY(h, dalloc(h, &h->sxidx, idx.size()), "alloc exclusions");
     h->n_excl = total;
     IRBE_TRY(h, hipMemcpyAsync(h->xoff, off.data(), (n + 1) * 4, hipMemcpyHostToDevice, h->stream), "upload");
     IRBE_TRY(h, hipMemcpyAsync(h->xidx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, h->stream), "upload");

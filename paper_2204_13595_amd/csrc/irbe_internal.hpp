@@ -99,6 +99,8 @@ struct irbe_ctx {
     void* lj_raw = nullptr;           // real[2 n_t^2]: sigma, eps
     int32_t* xoff = nullptr;          // [N+1] exclusion partners per atom (caller ids)
     int32_t* xidx = nullptr;
+    int32_t* sxidx = nullptr;         // [n_excl] xidx entries as sorted indices (rebuilt with the cells)
+    int2* sxr = nullptr;              // [N] sorted atom's range (first, count) in sxidx
     int64_t n_excl = 0;
     double* sumq2 = nullptr;          // [1]
     double* q2part = nullptr;

@@ -198,8 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n, const int32
                                                           const uint4* __restrict__ sq,
                                                           const int32_t* __restrict__ type,
                                                           const real* __restrict__ q, const int32_t* __restrict__ mol,
+                                                          const int32_t* __restrict__ xoff,
                                                           uint4* __restrict__ spos, real* __restrict__ sqr,
-                                                          int32_t* __restrict__ smol, int32_t* __restrict__ rank)
+                                                          int32_t* __restrict__ smol, int2* __restrict__ sxr,
+                                                          int32_t* __restrict__ rank)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -208,7 +210,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n, const int32
     spos[k] = make_uint4(s.x, s.y, s.z, (uint32_t)type[i]);
     sqr[k] = q[i];
     smol[k] = mol[i];
+    sxr[k] = make_int2(xoff[i], xoff[i + 1] - xoff[i]);
     rank[i] = (int32_t)k;
+}
+
+// Excluded partners as sorted indices (same layout as the caller-order table).
+__global__ __launch_bounds__(kBlock) void k_excl_sorted(int64_t n_excl, const int32_t* __restrict__ xidx,
+                                                        const int32_t* __restrict__ rank, int32_t* __restrict__ sxidx)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n_excl) sxidx[e] = rank[xidx[e]];
 }
 
 hipError_t launch_bin(irbe_ctx* h, const void* pos)
@@ -233,11 +244,15 @@ hipError_t launch_bin(irbe_ctx* h, const void* pos)
                                                                                          h->cell_start, h->sq, h->perm);
     if (h->fp64)
         k_gather_sorted<double><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const double*)h->q_orig,
-                                                              h->mol_orig, h->spos, (double*)h->sq_r, h->smol,
-                                                              h->rank);
+                                                              h->mol_orig, h->xoff, h->spos, (double*)h->sq_r,
+                                                              h->smol, h->sxr, h->rank);
     else
         k_gather_sorted<float><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const float*)h->q_orig,
-                                                             h->mol_orig, h->spos, (float*)h->sq_r, h->smol, h->rank);
+                                                             h->mol_orig, h->xoff, h->spos, (float*)h->sq_r, h->smol,
+                                                             h->sxr, h->rank);
+    if (h->n_excl > 0)
+        k_excl_sorted<<<(unsigned)blocks_for(h->n_excl, kBlock), kBlock, 0, h->stream>>>(h->n_excl, h->xidx, h->rank,
+                                                                                        h->sxidx);
     return hipGetLastError();
 }
 

@@ -151,14 +151,33 @@ __device__ __forceinline__ real wave_sum_r(real v)
 
 constexpr int kCoopBlock = 256;
 
+// Excluded-pair correction of one pair, accumulated into px.
+template <typename real, bool EV>
+__device__ __forceinline__ void add_excl(PairSum<real>& px, uint4 si, real qi, uint4 sj, real qj,
+                                         const PairParams<real>& pp)
+{
+    real dx, dy, dz;
+    separation(si, sj, pp.quantum, dx, dy, dz);
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    real u;
+    const real psi = excl_psi<real, EV>(r2, qi * qj, pp, u);
+    px.fx += psi * dx;
+    px.fy += psi * dy;
+    px.fz += psi * dz;
+    if (EV) {
+        px.uc += u;
+        px.v[0] += psi * dx * dx; px.v[1] += psi * dy * dy; px.v[2] += psi * dz * dz;
+        px.v[3] += psi * dx * dy; px.v[4] += psi * dx * dz; px.v[5] += psi * dy * dz;
+    }
+}
+
 template <typename real, bool FULL, bool EV>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
-    const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, const int32_t* __restrict__ core,
+    const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
-    const int32_t* __restrict__ nshell, int cap_shell, const int32_t* __restrict__ xoff,
-    const int32_t* __restrict__ xidx, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, int p_stride,
-    const uint16_t* __restrict__ ranks, real* __restrict__ fsr, double* __restrict__ part)
+    const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
+    int p_stride, const uint16_t* __restrict__ ranks, real* __restrict__ fsr, double* __restrict__ part)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -172,52 +191,75 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int64_t a1 = min(n, a0 + apw);
     double fc_sum[3] = {0.0, 0.0, 0.0};
     PairSum<real> ev;  // per-lane energy/virial totals (forces unused)
+    // per-atom headers of the wavefront's atoms, one atom per lane, read once
+    const int64_t ah = min(a0 + min(lane, apw - 1), n - 1);
+    const uint4 h_s = spos[ah];
+    const real h_q = sqr[ah];
+    const int h_nc = FULL ? 0 : ncore[ah];
+    const int h_ns = nshell[ah];
+    const int2 h_x = sxr[ah];
+    // first-level indices of one atom's first pass: the lane's first core entry,
+    // its two batch ranks (or shell positions) and its first excluded partner
+    auto first_level = [&](int64_t a, int t, int& jc, int& r0, int& r1, int& jx) {
+        const int nc = __shfl(h_nc, t, 64);
+        const int ns = __shfl(h_ns, t, 64);
+        const int2 xr = make_int2(__shfl(h_x.x, t, 64), __shfl(h_x.y, t, 64));
+        const bool sample = !FULL && ns > p_shell;
+        const int cnt = sample ? p_shell : ns;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        jc = lane < nc ? core[a * (int64_t)cap_core + lane] : -1;
+        r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
+        r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+        jx = lane < xr.y ? sxidx[xr.x + lane] : -1;
+    };
+    int n_jc = -1, n_r0 = -1, n_r1 = -1, n_jx = -1;
+    if (a0 < a1) first_level(a0, 0, n_jc, n_r0, n_r1, n_jx);
     for (int64_t a = a0; a < a1; ++a) {
-        const uint4 si = spos[a];
-        const real qi = sqr[a] * pp.ke;
+        const int t = (int)(a - a0);
+        const int jc = n_jc, r0 = n_r0, r1 = n_r1, jx = n_jx;
+        // the next atom's first-level loads go out before this atom's dependent ones
+        if (a + 1 < a1) first_level(a + 1, t + 1, n_jc, n_r0, n_r1, n_jx);
+        const uint4 si = make_uint4(__shfl(h_s.x, t, 64), __shfl(h_s.y, t, 64), __shfl(h_s.z, t, 64),
+                                    __shfl(h_s.w, t, 64));
+        const real qi = __shfl(h_q, t, 64) * pp.ke;
         const LJ<real>* lrow = lj + (int)si.w * n_types;
-        PairSum<real> pc, ps, px;
-        const int nc = ncore[a];
+        const int nc = __shfl(h_nc, t, 64);
+        const int ns = __shfl(h_ns, t, 64);
+        const int2 xr = make_int2(__shfl(h_x.x, t, 64), __shfl(h_x.y, t, 64));
         const int32_t* crow = core + a * (int64_t)cap_core;
-        for (int c = lane; c < nc; c += 64) {
+        const int32_t* srow = shell + a * (int64_t)cap_shell;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        const bool sample = !FULL && ns > p_shell;
+        const int cnt = sample ? p_shell : ns;
+        const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
+        PairSum<real> pc, ps, px;
+        const int js0 = r0 >= 0 ? srow[r0] : -1;
+        const int js1 = r1 >= 0 ? srow[r1] : -1;
+        // (unused slots load atom 0, so that every position is one 16-byte load)
+        const uint4 pjc = spos[max(jc, 0)];
+        const real qjc = sqr[max(jc, 0)];
+        const uint4 pj0 = spos[max(js0, 0)];
+        const real qj0 = sqr[max(js0, 0)];
+        const uint4 pj1 = spos[max(js1, 0)];
+        const real qj1 = sqr[max(js1, 0)];
+        const uint4 pjx = spos[max(jx, 0)];
+        const real qjx = sqr[max(jx, 0)];
+        if (jc >= 0) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
+        if (js0 >= 0) add_pair<real, EV>(ps, si, qi, pj0, qj0, lrow, pp);
+        if (js1 >= 0) add_pair<real, EV>(ps, si, qi, pj1, qj1, lrow, pp);
+        if (jx >= 0) add_excl<real, EV>(px, si, qi, pjx, qjx, pp);
+        // the rest (long lists and large batches)
+        for (int c = lane + 64; c < nc; c += 64) {
             const int j = crow[c];
             add_pair<real, EV>(pc, si, qi, spos[j], sqr[j], lrow, pp);
         }
-        const int ns = nshell[a];
-        const int32_t* srow = shell + a * (int64_t)cap_shell;
-        const bool sample = !FULL && ns > p_shell;
-        real w = 1;
-        if (sample) {
-            w = (real)((double)ns / (double)p_shell);
-            const uint16_t* rrow = ranks + a * (int64_t)p_stride;
-            for (int c = lane; c < p_shell; c += 64) {
-                const int j = srow[rrow[c]];
-                add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
-            }
-        } else {
-            for (int c = lane; c < ns; c += 64) {
-                const int j = srow[c];
-                add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
-            }
+        for (int c = lane + 128; c < cnt; c += 64) {
+            const int j = srow[sample ? (int)rrow[c] : c];
+            add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
         }
-        const int ia = perm[a];
-        const int xb = xoff[ia], nx = xoff[ia + 1] - xb;
-        for (int c = lane; c < nx; c += 64) {
-            const int j = rank[xidx[xb + c]];
-            const uint4 sj = spos[j];
-            real dx, dy, dz;
-            separation(si, sj, pp.quantum, dx, dy, dz);
-            const real r2 = dx * dx + dy * dy + dz * dz;
-            real u;
-            const real psi = excl_psi<real, EV>(r2, qi * sqr[j], pp, u);
-            px.fx += psi * dx;
-            px.fy += psi * dy;
-            px.fz += psi * dz;
-            if (EV) {
-                px.uc += u;
-                px.v[0] += psi * dx * dx; px.v[1] += psi * dy * dy; px.v[2] += psi * dz * dz;
-                px.v[3] += psi * dx * dy; px.v[4] += psi * dx * dz; px.v[5] += psi * dy * dz;
-            }
+        for (int c = lane + 64; c < xr.y; c += 64) {
+            const int j = sxidx[xr.x + c];
+            add_excl<real, EV>(px, si, qi, spos[j], sqr[j], pp);
         }
         const real fx = wave_sum_r(pc.fx + w * ps.fx);
         const real fy = wave_sum_r(pc.fy + w * ps.fy);
@@ -302,9 +344,9 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     k_pair_coop<real, FULL, EV><<<nb, kCoopBlock, 0, h->stream>>>(
-        n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core,
-        h->shell, h->nshell, h->cap_shell, h->xoff, h->xidx, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell,
-        h->p_stride, h->ranks, (real*)h->fsr, h->pair_part);
+        n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
+        h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
+        h->ranks, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
     return hipGetLastError();
 }
@@ -536,10 +578,10 @@ __device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_
 template <typename real, bool FULL, bool WANT_LJ, bool BK>
 __global__ __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
-    const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, const int32_t* __restrict__ core,
+    const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
-    const int32_t* __restrict__ nshell, int cap_shell, const int32_t* __restrict__ xoff,
-    const int32_t* __restrict__ xidx, const real* __restrict__ ljraw_g, int n_types, int p_shell, int p_stride,
+    const int32_t* __restrict__ nshell, int cap_shell, const real* __restrict__ ljraw_g, int n_types, int p_shell,
+    int p_stride,
     const uint16_t* __restrict__ ranks, const real* __restrict__ gs, const double* __restrict__ gmean_d,
     real* __restrict__ gself, real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat,
     double* __restrict__ ljpart, BucketArgs bk, int rec_cap)
@@ -698,10 +740,9 @@ __global__ __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(5)))
             }
         }
         // excluded pairs (symmetric; G itself)
-        const int ia = perm[a];
-        const int xb = xoff[ia], nx = xoff[ia + 1] - xb;
-        for (int c = lane; c < nx; c += 64) {
-            const int j = rank[xidx[xb + c]];
+        const int2 xr = sxr[a];
+        for (int c = lane; c < xr.y; c += 64) {
+            const int j = sxidx[xr.x + c];
             const uint4 sj = spos[j];
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
@@ -897,8 +938,8 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     h->adj_nb = nb;
     k_pair_adjoint<real, FULL, WANT_LJ, BK><<<nb, kCoopBlock, lds, h->stream>>>(
-        n, apw, pp, h->spos, (const real*)h->sq_r, h->perm, h->rank, h->core, h->ncore, h->cap_core,
-        h->shell, h->nshell, h->cap_shell, h->xoff, h->xidx, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
+        n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
+        h->shell, h->nshell, h->cap_shell, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
         h->p_stride, h->ranks, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
         (real*)h->gqscat, h->ljpart, bk, rec_cap);
     e = hipGetLastError();
