@@ -151,6 +151,38 @@ __device__ __forceinline__ real wave_sum_r(real v)
 
 constexpr int kCoopBlock = 256;
 
+// A core pair (ex = false, accumulated into pc) or an excluded pair (ex = true,
+// into px) with one code path: the excluded-pair correction -erf(br)/r equals
+// the real-space term erfc(br)/r minus the bare 1/r, so its force factor is the
+// Coulomb part of phi plus qq / r^3, without LJ. Forces only.
+template <typename real>
+__device__ __forceinline__ void add_pair_or_excl(PairSum<real>& pc, PairSum<real>& px, uint4 si, real qi, uint4 sj,
+                                                 real qj, const LJ<real>* lrow, const PairParams<real>& pp, bool ex)
+{
+    using M = Math<real>;
+    real dx, dy, dz;
+    separation(si, sj, pp.quantum, dx, dy, dz);
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    const real qq = qi * qj;
+    const LJ<real> lj = lrow[sj.w];
+    const real rinv = M::rsqrt_(r2);
+    const real r = r2 * rinv;
+    const real br = pp.beta * r;
+    const real e = M::exp_(-br * br);
+    const real ec = M::erfc_ex(br, e);
+    const real rinv2 = rinv * rinv;
+    const real r6 = rinv2 * rinv2 * rinv2;
+    const real coul = -qq * rinv2 * (ec * rinv + pp.cgauss * e);
+    const real phi = ex ? coul + qq * rinv2 * rinv : coul - r6 * rinv2 * (lj.a12 * r6 - lj.b6);
+    const real fx = phi * dx, fy = phi * dy, fz = phi * dz;
+    pc.fx += ex ? (real)0 : fx;
+    pc.fy += ex ? (real)0 : fy;
+    pc.fz += ex ? (real)0 : fz;
+    px.fx += ex ? fx : (real)0;
+    px.fy += ex ? fy : (real)0;
+    px.fz += ex ? fz : (real)0;
+}
+
 // Excluded-pair correction of one pair, accumulated into px.
 template <typename real, bool EV>
 __device__ __forceinline__ void add_excl(PairSum<real>& px, uint4 si, real qi, uint4 sj, real qj,
@@ -200,6 +232,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int2 h_x = sxr[ah];
     // first-level indices of one atom's first pass: the lane's first core entry,
     // its two batch ranks (or shell positions) and its first excluded partner
+    // Without energies the excluded partners follow the core entries in one slot
+    // (entries nc .. nc + nx - 1 of the combined list); with energies they keep
+    // their own slot.
+    constexpr bool kFold = !EV;
     auto first_level = [&](int64_t a, int t, int& jc, int& r0, int& r1, int& jx) {
         const int nc = __shfl(h_nc, t, 64);
         const int ns = __shfl(h_ns, t, 64);
@@ -207,10 +243,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const bool sample = !FULL && ns > p_shell;
         const int cnt = sample ? p_shell : ns;
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
-        jc = lane < nc ? core[a * (int64_t)cap_core + lane] : -1;
+        if (kFold)
+            jc = lane < nc ? core[a * (int64_t)cap_core + lane]
+                           : (lane < nc + xr.y ? sxidx[xr.x + lane - nc] : -1);
+        else
+            jc = lane < nc ? core[a * (int64_t)cap_core + lane] : -1;
         r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
         r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
-        jx = lane < xr.y ? sxidx[xr.x + lane] : -1;
+        jx = (!kFold && lane < xr.y) ? sxidx[xr.x + lane] : -1;
     };
     int n_jc = -1, n_r0 = -1, n_r1 = -1, n_jx = -1;
     if (a0 < a1) first_level(a0, 0, n_jc, n_r0, n_r1, n_jx);
@@ -242,24 +282,35 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const real qj0 = sqr[max(js0, 0)];
         const uint4 pj1 = spos[max(js1, 0)];
         const real qj1 = sqr[max(js1, 0)];
-        const uint4 pjx = spos[max(jx, 0)];
-        const real qjx = sqr[max(jx, 0)];
-        if (jc >= 0) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
+        const uint4 pjx = kFold ? pjc : spos[max(jx, 0)];
+        const real qjx = kFold ? qjc : sqr[max(jx, 0)];
+        if (kFold) {
+            if (jc >= 0) add_pair_or_excl(pc, px, si, qi, pjc, qjc, lrow, pp, lane >= nc);
+        } else {
+            if (jc >= 0) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
+            if (jx >= 0) add_excl<real, EV>(px, si, qi, pjx, qjx, pp);
+        }
         if (js0 >= 0) add_pair<real, EV>(ps, si, qi, pj0, qj0, lrow, pp);
         if (js1 >= 0) add_pair<real, EV>(ps, si, qi, pj1, qj1, lrow, pp);
-        if (jx >= 0) add_excl<real, EV>(px, si, qi, pjx, qjx, pp);
         // the rest (long lists and large batches)
-        for (int c = lane + 64; c < nc; c += 64) {
-            const int j = crow[c];
-            add_pair<real, EV>(pc, si, qi, spos[j], sqr[j], lrow, pp);
+        if (kFold) {
+            for (int c = lane + 64; c < nc + xr.y; c += 64) {
+                const int j = c < nc ? crow[c] : sxidx[xr.x + c - nc];
+                add_pair_or_excl(pc, px, si, qi, spos[j], sqr[j], lrow, pp, c >= nc);
+            }
+        } else {
+            for (int c = lane + 64; c < nc; c += 64) {
+                const int j = crow[c];
+                add_pair<real, EV>(pc, si, qi, spos[j], sqr[j], lrow, pp);
+            }
+            for (int c = lane + 64; c < xr.y; c += 64) {
+                const int j = sxidx[xr.x + c];
+                add_excl<real, EV>(px, si, qi, spos[j], sqr[j], pp);
+            }
         }
         for (int c = lane + 128; c < cnt; c += 64) {
             const int j = srow[sample ? (int)rrow[c] : c];
             add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
-        }
-        for (int c = lane + 64; c < xr.y; c += 64) {
-            const int j = sxidx[xr.x + c];
-            add_excl<real, EV>(px, si, qi, spos[j], sqr[j], pp);
         }
         const real fx = wave_sum_r(pc.fx + w * ps.fx);
         const real fy = wave_sum_r(pc.fy + w * ps.fy);
@@ -470,8 +521,12 @@ __device__ __forceinline__ LJGrad<real> lj_grad_entry(real sig, real eps)
     return L;
 }
 
+// xp: an excluded pair, whose correction -erf(br)/r is the real-space term
+// erfc(br)/r minus the bare 1/r: the Coulomb factor gains -1/r^3, phi gains
+// qq/r^3, phi'/r gains -3 qq/r^5, and there is no LJ term.
 template <typename real>
-__device__ __forceinline__ PairGrad<real> pair_grad(real r2, real qq, const LJGrad<real>& L, const PairParams<real>& pp)
+__device__ __forceinline__ PairGrad<real> pair_grad(real r2, real qq, const LJGrad<real>& L, const PairParams<real>& pp,
+                                                    bool xp = false)
 {
     using M = Math<real>;
     const real rinv = M::rsqrt_(r2);
@@ -487,36 +542,17 @@ __device__ __forceinline__ PairGrad<real> pair_grad(real r2, real qq, const LJGr
     const real dB = -B * ((real)2 * pp.beta * pp.beta * r + (real)2 * rinv);
     const real r6 = rinv2 * rinv2 * rinv2;
     const real r8 = r6 * rinv2;
-    const real C = r8 * (L.a48 * r6 - L.b24);
-    const real dC = rinv * r8 * (L.b192 - L.a672 * r6);
+    const real on = xp ? (real)0 : (real)1;
+    const real C = on * r8 * (L.a48 * r6 - L.b24);
+    const real dC = on * rinv * r8 * (L.b192 - L.a672 * r6);
+    const real eps = on * L.eps;
     PairGrad<real> g;
-    g.a_coul = A + B;
-    g.phi = -qq * (A + B) - L.eps * C;
-    g.dphi_r = (-qq * (dA + dB) - L.eps * dC) * rinv;
+    g.a_coul = xp ? A + B - rinv3 : A + B;
+    g.phi = -qq * g.a_coul - eps * C;
+    g.dphi_r = (-qq * (dA + dB) - eps * dC) * rinv - (xp ? (real)3 * qq * rinv2 * rinv3 : (real)0);
     g.c_lj = C;
-    g.dc_dsig = r8 * (L.as * r6 - L.bs);
+    g.dc_dsig = on * r8 * (L.as * r6 - L.bs);
     return g;
-}
-
-template <typename real>
-__device__ __forceinline__ void excl_grad(real r2, real qq, const PairParams<real>& pp, real& psi, real& dpsi_r,
-                                          real& a_x)
-{
-    using M = Math<real>;
-    const real rinv = M::rsqrt_(r2);
-    const real r = r2 * rinv;
-    const real br = pp.beta * r;
-    const real ex = M::exp_(-br * br);
-    const real ef = M::erf_(br);
-    const real rinv2 = rinv * rinv;
-    const real rinv3 = rinv2 * rinv;
-    const real Bx = pp.cgauss * ex * rinv2;
-    const real E = ef * rinv3;
-    const real dBx = -pp.cgauss * ex * ((real)2 * pp.beta * pp.beta * rinv + (real)2 * rinv3);
-    const real dE = pp.cgauss * ex * rinv3 - (real)3 * ef * rinv3 * rinv;
-    a_x = Bx - E;
-    psi = -qq * a_x;
-    dpsi_r = -qq * (dBx - dE) * rinv;
 }
 
 template <typename real>
@@ -576,7 +612,7 @@ __device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_
 // shell scatter goes through the LDS-staged buckets (dynamic LDS: rec_cap
 // records of 4 reals + j + key, then 7 ints per key).
 template <typename real, bool FULL, bool WANT_LJ, bool BK>
-__global__ __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_pair_adjoint(
+__global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
@@ -626,29 +662,67 @@ __global__ __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(5)))
     // cell row of the block's first atom: the block's atoms lie in rows row0, row0 + 1, ...
     const int row0 = BK ? cell_row(spos[min(blk * NW * apw, n - 1)], bk.n_c) : 0;
     real lane_max = 0;  // largest |component| of the records this lane staged
+    // per-atom headers of the wavefront's atoms, one atom per lane, read once
+    const int64_t ah = min(a0 + min(lane, apw - 1), n - 1);
+    const uint4 h_s = spos[ah];
+    const real h_q = sqr[ah];
+    const real h_gx = gs[3 * ah], h_gy = gs[3 * ah + 1], h_gz = gs[3 * ah + 2];
+    const int h_nsym = FULL ? nshell[ah] : ncore[ah];
+    const int h_ns = FULL ? 0 : nshell[ah];
+    const int2 h_x = sxr[ah];
+    // first-level indices of one atom's first pass: the lane's first symmetric-list
+    // entry, its two batch ranks (or shell positions) and its first excluded partner
+    auto first_level = [&](int64_t a, int t, int& jc, int& r0, int& r1, int& jx) {
+        const int nsym = __shfl(h_nsym, t, 64);
+        const int ns = __shfl(h_ns, t, 64);
+        const int2 xr = make_int2(__shfl(h_x.x, t, 64), __shfl(h_x.y, t, 64));
+        const bool sample = ns > p_shell;
+        const int cnt = sample ? p_shell : ns;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        const int32_t* srow_sym = FULL ? shell + a * (int64_t)cap_shell : core + a * (int64_t)cap_core;
+        // the excluded partners follow the symmetric list (entries nsym .. nsym + nx - 1)
+        jc = lane < nsym ? srow_sym[lane] : (lane < nsym + xr.y ? sxidx[xr.x + lane - nsym] : -1);
+        r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
+        r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+        jx = -1;
+    };
+    int n_jc = -1, n_r0 = -1, n_r1 = -1, n_jx = -1;
+    if (a0 < a1) first_level(a0, 0, n_jc, n_r0, n_r1, n_jx);
     for (int64_t a = a0; a < a1; ++a) {
-        const uint4 si = spos[a];
+        const int t_a = (int)(a - a0);
+        const int jc = n_jc, r0 = n_r0, r1 = n_r1, jx = n_jx;
+        // the next atom's first-level loads go out before this atom's dependent ones
+        if (a + 1 < a1) first_level(a + 1, t_a + 1, n_jc, n_r0, n_r1, n_jx);
+        const uint4 si = make_uint4(__shfl(h_s.x, t_a, 64), __shfl(h_s.y, t_a, 64), __shfl(h_s.z, t_a, 64),
+                                    __shfl(h_s.w, t_a, 64));
         const int ti = (int)si.w;
-        const real qi = sqr[a];
-        const real gx = gs[3 * a], gy = gs[3 * a + 1], gz = gs[3 * a + 2];
+        const real qi = __shfl(h_q, t_a, 64);
+        const real gx = __shfl(h_gx, t_a, 64), gy = __shfl(h_gy, t_a, 64), gz = __shfl(h_gz, t_a, 64);
         const real pgx = gx - mx, pgy = gy - my, pgz = gz - mz;  // G'_i
+        const int nsym = __shfl(h_nsym, t_a, 64);
+        const int ns = __shfl(h_ns, t_a, 64);
+        const int2 xr = make_int2(__shfl(h_x.x, t_a, 64), __shfl(h_x.y, t_a, 64));
         real rx = 0, ry = 0, rz = 0, rq = 0;
         real acc_sig[kMaxTypesGrad], acc_eps[kMaxTypesGrad];
 #pragma unroll
         for (int t = 0; t < kMaxTypesGrad; ++t) acc_sig[t] = acc_eps[t] = 0;
-        // symmetric lists: core pairs (RBL) or the whole list (full-list mode)
-        const int nsym = FULL ? nshell[a] : ncore[a];
         const int32_t* srow_sym = FULL ? shell + a * (int64_t)cap_shell : core + a * (int64_t)cap_core;
-        for (int c = lane; c < nsym; c += 64) {
-            const int j = srow_sym[c];
-            const uint4 sj = spos[j];
+        const int32_t* srow = shell + a * (int64_t)cap_shell;
+        const bool sample = ns > p_shell;
+        const int cnt = sample ? p_shell : ns;
+        const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+
+        // symmetric sets (core pairs, or the whole list in full-list mode, and the
+        // excluded pairs, xp): gathered. G'_j - G'_i = G_j - G_i, so the same
+        // difference serves both.
+        auto sym_pair = [&](uint4 sj, real qj, real gjx, real gjy, real gjz, bool xp) {
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
             const real r2 = dx * dx + dy * dy + dz * dz;
             const LJGrad<real>& L = ljg[ti * n_types + (int)sj.w];
-            const real qj = sqr[j];
-            const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp);
-            const real ex_ = gs[3 * j] - mx - pgx, ey_ = gs[3 * j + 1] - my - pgy, ez_ = gs[3 * j + 2] - mz - pgz;
+            const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp, xp);
+            const real ex_ = gjx - gx, ey_ = gjy - gy, ez_ = gjz - gz;
             const real gd = dx * ex_ + dy * ey_ + dz * ez_;
             rx += g.phi * ex_ + g.dphi_r * dx * gd;
             ry += g.phi * ey_ + g.dphi_r * dy * gd;
@@ -664,99 +738,94 @@ __global__ __launch_bounds__(kCoopBlock) __attribute__((amdgpu_waves_per_eu(5)))
                         acc_eps[t] += -g.c_lj * gdi;
                     }
             }
-        }
-        if (!FULL) {
-            // sampled shell pairs, one-sided: gather for i, scatter (atomics) for j
-            const int ns = nshell[a];
-            const int32_t* srow = shell + a * (int64_t)cap_shell;
-            const bool sample = ns > p_shell;
-            const int cnt = sample ? p_shell : ns;
-            const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
-            const uint16_t* rrow = ranks + a * (int64_t)p_stride;
-            for (int c = lane; c < cnt; c += 64) {
-                const int j = srow[sample ? (int)rrow[c] : c];
-                const uint4 sj = spos[j];
-                real dx, dy, dz;
-                separation(si, sj, pp.quantum, dx, dy, dz);
-                const real r2 = dx * dx + dy * dy + dz * dz;
-                const LJGrad<real>& L = ljg[ti * n_types + (int)sj.w];
-                const real qj = sqr[j];
-                const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp);
-                const real gdi = dx * pgx + dy * pgy + dz * pgz;
-                const real jx = w * (g.phi * pgx + g.dphi_r * dx * gdi);
-                const real jy = w * (g.phi * pgy + g.dphi_r * dy * gdi);
-                const real jz = w * (g.phi * pgz + g.dphi_r * dz * gdi);
-                rx -= jx;
-                ry -= jy;
-                rz -= jz;
-                rq += w * (-ke * qj * g.a_coul) * gdi;
-                const real jq = w * (-ke * qi * g.a_coul) * gdi;
-                if (BK) {
-                    // key: (source row - row0, row offset of j); positions moved since the
-                    // lists were built can leave the window, and then take the atomics
-                    const int nc_ = bk.n_c;
-                    const int src = cell_row(si, nc_) - row0;  // wave-uniform
-                    const int dz = stencil_offset((int)(((uint64_t)sj.z * (uint32_t)nc_) >> 32),
-                                                  (int)(((uint64_t)si.z * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
-                                   bk.lo;
-                    const int dy = stencil_offset((int)(((uint64_t)sj.y * (uint32_t)nc_) >> 32),
-                                                  (int)(((uint64_t)si.y * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
-                                   bk.lo;
-                    if (src >= 0 && src < 2 && dz >= 0 && dz < bk.span && dy >= 0 && dy < bk.span) {
-                        const int key = src * span2 + dz * bk.span + dy;
-                        const uint64_t m = __ballot(1);
-                        const int leader = __ffsll((unsigned long long)m) - 1;
-                        int base = 0;
-                        if (lane == leader) base = atomicAdd(&nrec, __popcll(m));
-                        base = __shfl(base, leader, 64);
-                        const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-                        if (slot < rec_cap) {
-                            rc[4 * slot + 0] = jx;
-                            rc[4 * slot + 1] = jy;
-                            rc[4 * slot + 2] = jz;
-                            rc[4 * slot + 3] = jq;
-                            rj[slot] = j;
-                            rk[slot] = (uint16_t)key;
-                            atomicAdd(&kcnt[key], 1);
-                            lane_max = fmax(lane_max, fmax(fmax(fabs(jx), fabs(jy)), fmax(fabs(jz), fabs(jq))));
-                        } else {
-                            scatter_atomic(gscat, gqscat, j, jx, jy, jz, jq);
-                        }
-                    } else {
-                        scatter_atomic(gscat, gqscat, j, jx, jy, jz, jq);
-                    }
-                } else {
-                    scatter_atomic(gscat, gqscat, j, jx, jy, jz, jq);
-                }
-                if (WANT_LJ) {
-                    const int tj = (int)sj.w;
-#pragma unroll
-                    for (int t = 0; t < kMaxTypesGrad; ++t)
-                        if (t == tj) {
-                            acc_sig[t] += w * (-L.eps * g.dc_dsig * gdi);
-                            acc_eps[t] += w * (-g.c_lj * gdi);
-                        }
-                }
-            }
-        }
-        // excluded pairs (symmetric; G itself)
-        const int2 xr = sxr[a];
-        for (int c = lane; c < xr.y; c += 64) {
-            const int j = sxidx[xr.x + c];
-            const uint4 sj = spos[j];
+        };
+        // sampled shell pairs, one-sided: gathered for i, scattered for j
+        auto shell_pair = [&](int j, uint4 sj, real qj) {
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
             const real r2 = dx * dx + dy * dy + dz * dz;
-            const real qj = sqr[j];
-            real psi, dpsi_r, a_x;
-            excl_grad(r2, ke * qi * qj, pp, psi, dpsi_r, a_x);
-            const real ex_ = gs[3 * j] - gx, ey_ = gs[3 * j + 1] - gy, ez_ = gs[3 * j + 2] - gz;
-            const real gd = dx * ex_ + dy * ey_ + dz * ez_;
-            rx += psi * ex_ + dpsi_r * dx * gd;
-            ry += psi * ey_ + dpsi_r * dy * gd;
-            rz += psi * ez_ + dpsi_r * dz * gd;
-            rq += ke * qj * a_x * gd;
+            const LJGrad<real>& L = ljg[ti * n_types + (int)sj.w];
+            const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp);
+            const real gdi = dx * pgx + dy * pgy + dz * pgz;
+            const real jx_ = w * (g.phi * pgx + g.dphi_r * dx * gdi);
+            const real jy_ = w * (g.phi * pgy + g.dphi_r * dy * gdi);
+            const real jz_ = w * (g.phi * pgz + g.dphi_r * dz * gdi);
+            rx -= jx_;
+            ry -= jy_;
+            rz -= jz_;
+            rq += w * (-ke * qj * g.a_coul) * gdi;
+            const real jq_ = w * (-ke * qi * g.a_coul) * gdi;
+            bool staged = false;
+            if (BK) {
+                // key: (source row - row0, row offset of j); positions moved since the
+                // lists were built can leave the window, and then take the atomics
+                const int nc_ = bk.n_c;
+                const int src = cell_row(si, nc_) - row0;  // wave-uniform
+                const int kz = stencil_offset((int)(((uint64_t)sj.z * (uint32_t)nc_) >> 32),
+                                              (int)(((uint64_t)si.z * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
+                               bk.lo;
+                const int ky = stencil_offset((int)(((uint64_t)sj.y * (uint32_t)nc_) >> 32),
+                                              (int)(((uint64_t)si.y * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
+                               bk.lo;
+                if (src >= 0 && src < 2 && kz >= 0 && kz < bk.span && ky >= 0 && ky < bk.span) {
+                    const int key = src * span2 + kz * bk.span + ky;
+                    const uint64_t m = __ballot(1);
+                    const int leader = __ffsll((unsigned long long)m) - 1;
+                    int base = 0;
+                    if (lane == leader) base = atomicAdd(&nrec, __popcll(m));
+                    base = __shfl(base, leader, 64);
+                    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                    if (slot < rec_cap) {
+                        rc[4 * slot + 0] = jx_;
+                        rc[4 * slot + 1] = jy_;
+                        rc[4 * slot + 2] = jz_;
+                        rc[4 * slot + 3] = jq_;
+                        rj[slot] = j;
+                        rk[slot] = (uint16_t)key;
+                        atomicAdd(&kcnt[key], 1);
+                        lane_max = fmax(lane_max, fmax(fmax(fabs(jx_), fabs(jy_)), fmax(fabs(jz_), fabs(jq_))));
+                        staged = true;
+                    }
+                }
+            }
+            if (!staged) scatter_atomic(gscat, gqscat, (int64_t)j, jx_, jy_, jz_, jq_);
+            if (WANT_LJ) {
+                const int tj = (int)sj.w;
+#pragma unroll
+                for (int t = 0; t < kMaxTypesGrad; ++t)
+                    if (t == tj) {
+                        acc_sig[t] += w * (-L.eps * g.dc_dsig * gdi);
+                        acc_eps[t] += w * (-g.c_lj * gdi);
+                    }
+            }
+        };
+        // first pass, every load of the dependent levels issued together (unused
+        // slots load atom 0)
+        const int js0 = (!FULL && r0 >= 0) ? srow[r0] : -1;
+        const int js1 = (!FULL && r1 >= 0) ? srow[r1] : -1;
+        const int ic = max(jc, 0), i0 = max(js0, 0), i1 = max(js1, 0), ix = max(jx, 0);
+        const uint4 pjc = spos[ic];
+        const real qjc = sqr[ic];
+        const real gcx = gs[3 * (int64_t)ic], gcy = gs[3 * (int64_t)ic + 1], gcz = gs[3 * (int64_t)ic + 2];
+        const uint4 pj0 = spos[i0];
+        const real qj0 = sqr[i0];
+        const uint4 pj1 = spos[i1];
+        const real qj1 = sqr[i1];
+        (void)jx;
+        (void)ix;
+        if (jc >= 0) sym_pair(pjc, qjc, gcx, gcy, gcz, lane >= nsym);
+        if (js0 >= 0) shell_pair(js0, pj0, qj0);
+        if (js1 >= 0) shell_pair(js1, pj1, qj1);
+        // the rest (long lists and large batches)
+        for (int c = lane + 64; c < nsym + xr.y; c += 64) {
+            const int j = c < nsym ? srow_sym[c] : sxidx[xr.x + c - nsym];
+            sym_pair(spos[j], sqr[j], gs[3 * (int64_t)j], gs[3 * (int64_t)j + 1], gs[3 * (int64_t)j + 2], c >= nsym);
         }
+        if (!FULL)
+            for (int c = lane + 128; c < cnt; c += 64) {
+                const int j = srow[sample ? (int)rrow[c] : c];
+                shell_pair(j, spos[j], sqr[j]);
+            }
         rx = wave_sum_r(rx);
         ry = wave_sum_r(ry);
         rz = wave_sum_r(rz);
