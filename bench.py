@@ -91,31 +91,21 @@ def measured_traffic(kernel: str, workload: str):
 
 
 def cpu_baseline(w, args):
-    """The FP64 oracle (lists rebuilt, RBL+RBE forward) on row samples of the
-    same workload; the full-step time is extrapolated as setup + per-atom cost."""
-    import numpy as np
-
+    """The FP64 oracle (lists rebuilt, RBL+RBE forward) on the host cores: one
+    full step of the same workload, timed once (about 10 s of CPU work)."""
     from oracle import oracle as orc
     orc.lib()
     p = orc.Params(box=w.box, p_shell=args.p_shell, p_kspace=args.p_kspace)
-    rng = np.random.default_rng(7)
-    sizes = (1 << 16, 1 << 19)
-    times = []
-    for r in sizes:
-        rows = np.sort(rng.choice(w.n_atoms, size=r, replace=False))
-        t0 = time.perf_counter()
-        orc.forward(w.pos, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=0, mode="rbl", rows=rows)
-        times.append(time.perf_counter() - t0)
-        log(f"cpu oracle: {r} rows in {times[-1]:.2f} s")
-    per_atom = max((times[1] - times[0]) / (sizes[1] - sizes[0]), 1e-12)
-    setup = max(times[0] - per_atom * sizes[0], 0.0)
-    full = setup + per_atom * w.n_atoms
+    t0 = time.perf_counter()
+    orc.forward(w.pos, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=0, mode="rbl")
+    t = time.perf_counter() - t0
+    log(f"cpu oracle: one {w.n_atoms}-atom step in {t:.2f} s")
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
-        "value": w.n_atoms / full, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
-        "sample": (f"FP64 oracle RBL+RBE forward with lists rebuilt, on {sizes[0]} and {sizes[1]} random rows of the "
-                   f"{w.n_atoms}-atom workload ({sum(times):.1f} s); full step extrapolated as setup "
-                   f"{setup:.2f} s + {per_atom * 1e6:.2f} us/atom"),
+        "value": w.n_atoms / t, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+        "sample": (f"one full step (cell lists, core/shell lists, batches, pair forces, momentum correction, "
+                   f"k samples, FP64 structure factor, k-space force) of the {w.n_atoms}-atom workload by the FP64 "
+                   f"oracle with OpenMP over atoms: {t:.2f} s"),
     }
 
 
