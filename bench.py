@@ -109,6 +109,113 @@ def cpu_baseline(w, args):
     }
 
 
+def rms(a):
+    return float(a.double().pow(2).sum(dim=1).mean().sqrt())
+
+
+def forces(make, pos, p_shell, p_kspace, seed, step=7):
+    h = make(p_shell, p_kspace, seed)
+    h.build_lists(pos, step)
+    f = h.compute_forces(pos, step).clone()
+    h.close()
+    return f
+
+
+def accuracy(make, pos, G, w, args, ms_rbl, timed_steps):
+    """Force errors of the estimators and the full-list variant at matched error.
+
+    Errors are RMS over atoms of |F - E[F]|, in kJ/mol/nm:
+    * total error of a stochastic force from two independent seeds:
+      E|F1 - F2|^2 = 2 Var, so e = RMS(F1 - F2) / sqrt(2) (the real-space
+      truncation, erfc(3.6) = 3.6e-7, is negligible);
+    * the RMS of the exact force follows as sqrt(E RMS(F)^2 - e^2);
+    * the shell-sampling error alone: with one seed both variants draw the same
+      k-vectors, so F_RBL - F_full is exactly the random batch list estimate
+      minus the exact short-range force;
+    * matched error: the full-list variant's error at k-space batch size p is
+      e_full(p); RBL+RBE at p0 has e_full(p0)^2 + e_shell^2 (independent
+      samples); the full list matches it at the smallest p with
+      e_full(p)^2 <= e_full(p0)^2 + e_shell^2.
+    Plus a sweep of (p_shell, p) and the FP32-vs-FP64 error of forces and gradients."""
+    import math
+
+    import torch
+
+    from paper_2204_13595_amd import irbe
+    n = w.n_atoms
+    P0 = args.p_kspace
+    seeds = (13595, 24681)
+    f_rbl = [forces(make, pos, args.p_shell, P0, sd) for sd in seeds]
+    e_rbl = rms(f_rbl[0] - f_rbl[1]) / math.sqrt(2.0)
+    ms2 = 0.5 * (rms(f_rbl[0]) ** 2 + rms(f_rbl[1]) ** 2)
+    f_full0 = forces(make, pos, 0, P0, seeds[0])
+    e_shell = rms(f_rbl[0] - f_full0)
+    del f_rbl
+    e_full = {}
+    for P in sorted({25, 50, 100, 200, 500, P0}):
+        ff = [f_full0 if (P == P0 and sd == seeds[0]) else forces(make, pos, 0, P, sd) for sd in seeds]
+        e_full[P] = rms(ff[0] - ff[1]) / math.sqrt(2.0)
+    f_exact = math.sqrt(max(ms2 - e_rbl ** 2, 0.0))
+    target = math.sqrt(e_full[P0] ** 2 + e_shell ** 2)
+    matched = min((P for P in e_full if e_full[P] <= target), default=max(e_full))
+    hf = make(0, matched)
+
+    def fwd_full(step):
+        hf.build_lists(pos, step)
+        hf.compute_forces(pos, step)
+
+    ms_full = timed_steps(fwd_full, 1, 5, 6000) * 1e3
+    hf.close()
+    sweep = []
+    for ps in (50, 100, 200):
+        for P in (100, 500):
+            h = make(ps, P)
+
+            def fwd(step):
+                h.build_lists(pos, step)
+                h.compute_forces(pos, step)
+
+            ms_c = timed_steps(fwd, 1, 5, 7000) * 1e3
+            h.close()
+            fr, ff = forces(make, pos, ps, P, seeds[0]), forces(make, pos, 0, P, seeds[0])
+            sweep.append({"p_shell": ps, "p_kspace": P, "ms_per_step": round(ms_c, 3),
+                          "atom_steps_per_s": n / (ms_c * 1e-3), "shell_sampling_err": rms(fr - ff)})
+    out = {
+        "unit": "kJ/mol/nm, RMS over atoms",
+        "exact_force_rms_estimate": f_exact,
+        "rbl_rbe_err": e_rbl,
+        "rbl_shell_sampling_err": e_shell,
+        "full_list_err_by_p": {str(P): e for P, e in e_full.items()},
+        "matched_error_full_list": {"p_kspace": matched, "err": e_full[matched], "target_err": target,
+                                    "ms_per_step": ms_full, "atom_steps_per_s": n / (ms_full * 1e-3),
+                                    "speedup_rbl_rbe": ms_full / ms_rbl},
+        "sweep_rbl_rbe": sweep,
+    }
+    if args.precision == "mixed":
+        # FP32 arithmetic against the FP64 path (itself within 1e-11 of the FP64 oracle)
+        dev = pos.device
+        q64 = torch.tensor(w.charge, device=dev).to(torch.float32).double()
+        res = {}
+        for prec, p_in, q_in in (("mixed", pos, q64.float()), ("fp64", pos.double(), q64)):
+            h = irbe.Handle(n, w.box, p_shell=args.p_shell, p_kspace=P0, precision=prec, device=dev)
+            h.set_system(torch.tensor(w.atom_type, device=dev), q_in, torch.tensor(w.molecule, device=dev),
+                         w.lj_sigma, w.lj_eps)
+            h.build_lists(p_in, 3)
+            f = h.compute_forces(p_in, 3).double()
+            gp, gq, gl = h.compute_forces_backward(p_in, 3, G.to(p_in.dtype))
+            res[prec] = (f, gp.double(), gq.double(), gl.double())
+            h.close()
+        (f32, g32, q32, l32), (f64, g64, q64g, l64) = res["mixed"], res["fp64"]
+        out["fp32_vs_fp64"] = {
+            "force_rms_rel": rms(f32 - f64) / rms(f64),
+            "grad_pos_rms_rel": rms(g32 - g64) / rms(g64),
+            "grad_charge_rms_rel": float((q32 - q64g).pow(2).mean().sqrt() / q64g.pow(2).mean().sqrt()),
+            "grad_lj_sigma_oo_rel": float(abs(l32[0] - l64[0]) / abs(l64[0])),
+            "grad_lj_eps_oo_rel": float(abs(l32[4] - l64[4]) / abs(l64[4])),
+        }
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -131,8 +238,9 @@ def main():
     at = torch.tensor(w.atom_type, device=dev)
     mol = torch.tensor(w.molecule, device=dev)
 
-    def make(p_shell, p_kspace):
-        h = irbe.Handle(n, w.box, p_shell=p_shell, p_kspace=p_kspace, precision=args.precision, device=dev)
+    def make(p_shell, p_kspace, seed=13595):
+        h = irbe.Handle(n, w.box, p_shell=p_shell, p_kspace=p_kspace, seed=seed, precision=args.precision,
+                        device=dev)
         h.set_system(at, q, mol, w.lj_sigma, w.lj_eps)
         return h
 
@@ -193,6 +301,8 @@ def main():
             "algorithmic_bytes": list_bytes, "avg_launch_ms": lists_ms,
         }
         roof["frac"] = roof["achieved"] / roof["peak"]
+        log("accuracy: two-seed error estimates, matched-error full list, precision")
+        acc = accuracy(make, pos, G, w, args, ms, timed_steps)
         extras = {
             "fwd_bwd_atom_steps_per_s": n / (ms_fb * 1e-3), "ms_per_step_fwd_bwd": ms_fb,
             "forces_only_reused_lists_atom_steps_per_s": n / (ms_f * 1e-3), "ms_per_forces_only": ms_f,
@@ -203,6 +313,7 @@ def main():
             "dominant_stage": dom,
             "list_entries_per_atom": {"core": n_core / n, "shell": n_shell / n, "full_list": counts_full[1] / n},
             "roofline": roof,
+            "accuracy": acc,
         }
     else:
         if args.with_backward:

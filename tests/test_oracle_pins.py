@@ -332,21 +332,26 @@ def test_momentum_conservation(orc):
 
 @pytest.mark.slow
 def test_unbiased_over_seeds(orc):
-    """E[F_RBL+RBE] = F_Ewald (Sec. 2.4) and E[U*] = U, as per-component z-scores."""
+    """E[F_RBL+RBE] = F_Ewald (Sec. 2.4), E[U*] = U and E[W*] = W, as per-component z-scores."""
     w = _water()
     ref = orc.forward(*_args(w), orc.Params(box=w.box), mode="ewald")
     n_seed = 160
     f = np.empty((n_seed,) + ref.force.shape)
     u = np.empty(n_seed)
+    vir = np.empty((n_seed, 6))
     for k in range(n_seed):
         r = orc.forward(*_args(w), orc.Params(box=w.box, seed=1000 + k), mode="rbl")
         f[k] = r.force
         u[k] = r.energy[:5].sum()
+        vir[k] = r.energy[5:11]
     z = (f.mean(axis=0) - ref.force) / (f.std(axis=0, ddof=1) / math.sqrt(n_seed))
     assert abs((z ** 2).mean() - 1.0) < 0.15
     assert np.abs(z).max() < 5.5
     zu = (u.mean() - ref.energy[:5].sum()) / (u.std(ddof=1) / math.sqrt(n_seed))
     assert abs(zu) < 4.0
+    # the importance-sampled virial estimator is unbiased too, component by component
+    zv = (vir.mean(axis=0) - ref.energy[5:11]) / (vir.std(axis=0, ddof=1) / math.sqrt(n_seed))
+    assert np.abs(zv).max() < 4.5, zv
 
 
 def test_rbe_variance_scales_as_one_over_p(orc):
@@ -449,3 +454,75 @@ def test_adjoint_matches_central_differences(orc, mode):
         kw_m = {tbl: tm}
         fd = (_loss(orc, w, p, res, G, mode=mode, **kw_p) - _loss(orc, w, p, res, G, mode=mode, **kw_m)) / (2 * hh)
         assert abs(fd - grad[0]) < 1e-5 * max(abs(grad[0]), 1.0)
+
+
+# --------------------------------------------------------------------------- virial tensor
+
+def _ewald_energy_sheared(w, frac, hmat, pairs, beta, ke, r_shell, m):
+    """Plain Ewald energy of the water box in the periodic cell with edge
+    vectors the columns of hmat (positions hmat @ frac), written here
+    independently of the oracle: real space over the given pair set (erfc and LJ,
+    minimum image in the cell), reciprocal space over the integer vectors m
+    (k = 2 pi hmat^-T m; the structure factor's phases 2 pi m.frac do not depend
+    on the cell), the self term and the intramolecular erf corrections."""
+    V = abs(np.linalg.det(hmat))
+    i, j = pairs
+    df = frac[j] - frac[i]
+    df -= np.round(df)
+    d = df @ hmat.T
+    r = np.sqrt((d * d).sum(axis=1))
+    q = w.charge
+    excl = w.molecule[i] == w.molecule[j]
+    inr = (~excl) & (r <= r_shell)
+    u_real = ke * (q[i] * q[j] * special.erfc(beta * r) / r)[inr].sum()
+    nt = 2
+    tp = w.atom_type[i] * nt + w.atom_type[j]
+    sig, eps = w.lj_sigma[tp], w.lj_eps[tp]
+    sr6 = (sig / r) ** 6
+    u_lj = (4.0 * eps * (sr6 * sr6 - sr6))[inr].sum()
+    u_excl = -ke * (q[i] * q[j] * special.erf(beta * r) / r)[excl].sum()
+    kv = 2.0 * math.pi * m @ np.linalg.inv(hmat)  # rows: k = 2 pi h^-T m
+    k2 = (kv * kv).sum(axis=1)
+    rho = np.zeros(len(m), dtype=np.complex128)
+    for c0 in range(0, len(m), 4096):
+        ph = 2.0 * math.pi * (frac @ m[c0:c0 + 4096].T)
+        rho[c0:c0 + 4096] = (q[:, None] * np.exp(1j * ph)).sum(axis=0)
+    u_recip = ke * (2.0 * math.pi / V) * (np.exp(-k2 / (4.0 * beta * beta)) / k2 * np.abs(rho) ** 2).sum()
+    u_self = -ke * beta / math.sqrt(math.pi) * (q * q).sum()
+    return u_real + u_lj + u_recip + u_self + u_excl
+
+
+@pytest.mark.slow
+def test_ewald_virial_tensor_is_shear_derivative(orc):
+    """Every virial component: W_ab = -dU/d(eps_ab) under the deformation
+    (I + eps) of cell and positions (fractional coordinates fixed), with U from
+    an independent plain Ewald sum for a general cell; also U itself at eps = 0."""
+    w = _water()
+    p = orc.Params(box=w.box)
+    res = orc.forward(*_args(w), p, mode="ewald")
+    frac = res.s.astype(np.float64) / 2.0 ** 32
+    n = len(frac)
+    ii, jj = np.triu_indices(n, 1)
+    # the pair set is frozen at the undeformed cell (as the oracle's lists are)
+    df = frac[jj] - frac[ii]
+    df -= np.round(df)
+    r0 = np.sqrt(((df * w.box) ** 2).sum(axis=1))
+    keep = (r0 <= p.r_shell) | (w.molecule[ii] == w.molecule[jj])
+    pairs = (ii[keep], jj[keep])
+    M = orc.ktable(p.beta, w.box)[0]
+    rr = np.arange(-M, M + 1)
+    m = np.stack(np.meshgrid(rr, rr, rr, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    m = m[(m != 0).any(axis=1)]
+    h0 = np.eye(3) * w.box
+    u0 = _ewald_energy_sheared(w, frac, h0, pairs, p.beta, p.ke, p.r_shell, m)
+    assert abs(u0 - res.energy[:5].sum()) < 1e-9 * abs(u0)
+    comp = {(0, 0): 5, (1, 1): 6, (2, 2): 7, (0, 1): 8, (0, 2): 9, (1, 2): 10}
+    delta = 1e-6
+    for (a, b), c in comp.items():
+        us = []
+        for sgn in (1.0, -1.0):
+            e = np.eye(3)
+            e[a, b] += sgn * delta
+            us.append(_ewald_energy_sheared(w, frac, e @ h0, pairs, p.beta, p.ke, p.r_shell, m))
+        dudeps = (us[0] - us[1]) / (2.0 * delta)
+        assert abs(res.energy[c] + dudeps) < 1e-6 * np.abs(res.energy[5:8]).max(), ((a, b), res.energy[c], dudeps)
