@@ -70,3 +70,59 @@ def test_fullsize_sampled_parity(orc, name, precision, p_kspace, tol):
     assert err < tol, err
     # momentum: sum_i F_i = 0 (Eq. 2.12 for the short range, Im|rho|^2 = 0 for RBE)
     assert np.abs(Fsum).max() < (1e-6 if precision == "mixed" else 1e-12) * Fabs
+
+
+def test_fullsize_backward_properties():
+    """The adjoint at the benchmark's size and launch configuration (mixed,
+    p_shell = 100, p = 100, 3,145,728 atoms), checked through identities that
+    hold at any size for fixed lists and samples, with L = sum_i G_i . F_i:
+      * translation invariance of every force term: sum_i dL/dr_i = 0;
+      * without LJ the force is homogeneous of degree 2 in the charges:
+        sum_i q_i dL/dq_i = 2 L;
+      * without charges it is homogeneous of degree 1 in the LJ epsilons:
+        sum_ab eps_ab dL/deps_ab = L;
+    and against the FP64 path (a different scatter: device atomics rather than
+    row buckets) on the same inputs."""
+    from paper_2204_13595_amd import irbe
+    w = inputs.workload("water1M")
+    dev = torch.device("cuda", 0)
+    step = 13
+    at = torch.tensor(w.atom_type, device=dev)
+    mol = torch.tensor(w.molecule, device=dev)
+    # both precisions see the same (FP32-representable) positions, charges and dL/dF
+    G = torch.randn((w.n_atoms, 3), dtype=torch.float32, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(9)).double()
+    pos32 = torch.tensor(w.pos, dtype=torch.float32, device=dev)
+
+    def run(precision, q_scale=1.0, eps_scale=1.0):
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        h = irbe.Handle(w.n_atoms, w.box, p_shell=100, p_kspace=100, precision=precision, device=dev)
+        q = torch.tensor(w.charge * q_scale, dtype=torch.float32, device=dev).to(dt)
+        h.set_system(at, q, mol, w.lj_sigma, w.lj_eps * eps_scale)
+        pos = pos32.to(dt)
+        h.build_lists(pos, step)
+        F = h.compute_forces(pos, step)
+        gp, gq, gl = h.compute_forces_backward(pos, step, G.to(dt))
+        L = float((G * F.double()).sum())
+        out = (L, gp.double(), gq.double(), gl.double().cpu().numpy(), q.double())
+        h.close()
+        return out
+
+    L, gp, gq, gl, q = run("mixed")
+    scale = float(gp.abs().sum())
+    assert float(gp.sum(dim=0).abs().max()) < 1e-6 * scale
+    L64, gp64, gq64, gl64, _ = run("fp64")
+    assert float(((gp - gp64) ** 2).sum().sqrt() / (gp64 ** 2).sum().sqrt()) < 1e-5
+    assert float(((gq - gq64) ** 2).sum().sqrt() / (gq64 ** 2).sum().sqrt()) < 1e-5
+    # the LJ parameter gradients are single sums over ~10^8 FP32 pair terms of both
+    # signs (dL/dF is random here), which cancel to about 1/100 of the sum of
+    # their magnitudes: ~1e-7 per term becomes ~1e-5 of the result, bounded at 1e-4
+    assert abs(gl[0] - gl64[0]) < 1e-4 * abs(gl64[0]) and abs(gl[4] - gl64[4]) < 1e-4 * abs(gl64[4])
+    # Coulomb only (eps = 0): degree 2 in the charges
+    Lc, _, gqc, _, qc = run("mixed", eps_scale=0.0)
+    assert abs(float((qc * gqc).sum()) - 2.0 * Lc) < 1e-5 * float((qc * gqc).abs().sum())
+    # LJ only (q = 0): degree 1 in the epsilons (only the O-O entry is non-zero)
+    Ll, _, _, gll, _ = run("mixed", q_scale=0.0)
+    eps = w.lj_eps
+    nt2 = len(eps)
+    assert abs(float((eps * gll[nt2:2 * nt2]).sum()) - Ll) < 1e-5 * abs(Ll)
