@@ -216,6 +216,48 @@ def accuracy(make, pos, G, w, args, ms_rbl, timed_steps):
     return out
 
 
+def precision_sweep(timed_steps):
+    """FP64 against mixed precision, forward + backward, on the 6,291,456-atom box
+    (2,097,152 waters, L = 39.7 nm, p_shell = 100, p = 500): atom-steps/s of
+    each and the FP32-vs-FP64 error of forces and gradients (the FP64 path is
+    parity-tested against the FP64 oracle)."""
+    import torch
+
+    from paper_2204_13595_amd import inputs, irbe
+    w = inputs.workload("water2M")
+    n = w.n_atoms
+    dev = torch.device("cuda", 0)
+    pos32 = torch.tensor(w.pos, dtype=torch.float32, device=dev)
+    q32 = torch.tensor(w.charge, dtype=torch.float32, device=dev)
+    G32 = torch.randn((n, 3), dtype=torch.float32, device=dev, generator=torch.Generator(device=dev).manual_seed(8))
+    out, res = {}, {}
+    for prec in ("mixed", "fp64"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        pos, G = pos32.to(dt), G32.to(dt)
+        h = irbe.Handle(n, w.box, p_shell=100, p_kspace=500, precision=prec, device=dev)
+        h.set_system(torch.tensor(w.atom_type, device=dev), q32.to(dt), torch.tensor(w.molecule, device=dev),
+                     w.lj_sigma, w.lj_eps)
+
+        def fwd_bwd(step):
+            h.build_lists(pos, step)
+            h.compute_forces(pos, step)
+            h.compute_forces_backward(pos, step, G)
+
+        ms = timed_steps(fwd_bwd, 1, 3, 8000) * 1e3
+        h.build_lists(pos, 5)
+        f = h.compute_forces(pos, 5).double()
+        gp, gq, _ = h.compute_forces_backward(pos, 5, G)
+        res[prec] = (f, gp.double(), gq.double())
+        h.close()
+        out[prec] = {"ms_per_step_fwd_bwd": ms, "fwd_bwd_atom_steps_per_s": n / (ms * 1e-3)}
+    (f32, g32, q32g), (f64, g64, q64g) = res["mixed"], res["fp64"]
+    out["fp32_vs_fp64"] = {"force_rms_rel": rms(f32 - f64) / rms(f64), "grad_pos_rms_rel": rms(g32 - g64) / rms(g64),
+                           "grad_charge_rms_rel": float((q32g - q64g).pow(2).mean().sqrt()
+                                                        / q64g.pow(2).mean().sqrt())}
+    out["workload"] = "water2M: 2097152 waters (6291456 atoms), L=39.7 nm, P_s=100, P=500"
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -303,6 +345,10 @@ def main():
         roof["frac"] = roof["achieved"] / roof["peak"]
         log("accuracy: two-seed error estimates, matched-error full list, precision")
         acc = accuracy(make, pos, G, w, args, ms, timed_steps)
+        del pos, q, F, G
+        torch.cuda.empty_cache()
+        log("precision sweep on the 6.3M-atom box")
+        sweep = precision_sweep(timed_steps) if args.workload == "water1M" and args.precision == "mixed" else None
         extras = {
             "fwd_bwd_atom_steps_per_s": n / (ms_fb * 1e-3), "ms_per_step_fwd_bwd": ms_fb,
             "forces_only_reused_lists_atom_steps_per_s": n / (ms_f * 1e-3), "ms_per_forces_only": ms_f,
@@ -314,6 +360,7 @@ def main():
             "list_entries_per_atom": {"core": n_core / n, "shell": n_shell / n, "full_list": counts_full[1] / n},
             "roofline": roof,
             "accuracy": acc,
+            "precision_sweep": sweep,
         }
     else:
         if args.with_backward:
