@@ -131,6 +131,46 @@ def perturbed_parameters(seed: int = 4):
     return Q_O * f[0], SIGMA_OO * f[1], EPS_OO * f[2]
 
 
+@dataclasses.dataclass
+class IonSystem:
+    box: float
+    pos: np.ndarray        # [N, 3]
+    charge: np.ndarray     # [N]
+    atom_type: np.ndarray  # [N] 0 = cation, 1 = anion
+    molecule: np.ndarray   # [N] all -1: no excluded pairs
+    lj_sigma: np.ndarray   # [4]
+    lj_eps: np.ndarray     # [4]
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def electrolyte(valence: int = 1, seed: int = 2204, box: float = 80.0) -> IonSystem:
+    """Primitive-model electrolyte in reduced units (sigma = 1), the paper's
+    electrolyte sizes: 2560 monovalent cations and 2560 anions (valence 1), or
+    1280 divalent cations and 2560 monovalent anions (valence 2), L = 80 sigma.
+    Ions sit on the sites of the smallest cubic lattice that holds them (random
+    vacancies), jittered by U(-0.1 a, 0.1 a), in random species order. LJ with
+    sigma = eps = 1 for every pair (plain, truncated at the shell cutoff)."""
+    rng = np.random.default_rng(seed)
+    n_cat = 2560 if valence == 1 else 1280
+    n_an = 2560
+    n = n_cat + n_an
+    n_side = 1
+    while n_side ** 3 < n:
+        n_side += 1
+    a = box / n_side
+    sites = np.sort(rng.choice(n_side ** 3, size=n, replace=False))
+    iz, rem = np.divmod(sites, n_side * n_side)
+    iy, ix = np.divmod(rem, n_side)
+    pos = (np.stack([ix, iy, iz], axis=1) + 0.5) * a + rng.uniform(-0.1 * a, 0.1 * a, size=(n, 3))
+    species = rng.permutation(np.r_[np.zeros(n_cat, np.int32), np.ones(n_an, np.int32)])
+    charge = np.where(species == 0, float(valence), -1.0)
+    return IonSystem(float(box), pos, charge, species.astype(np.int32), np.full(n, -1, np.int32),
+                     np.ones(4), np.ones(4))
+
+
 def nacl_crystal(n_cells: int, d: float = 0.5, q: float = 1.0):
     """Rock-salt lattice of (2 n_cells)^3 ions, nearest-neighbour distance d."""
     m = 2 * n_cells
