@@ -94,6 +94,21 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 constexpr uint32_t kTagShell = 0u;
 constexpr uint32_t kTagKspace = 1u;
 
+// Value of v in lane t (t uniform across the wavefront): v_readlane into a scalar.
+__device__ __forceinline__ int bcast(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int t) { return (uint32_t)__builtin_amdgcn_readlane((int)v, t); }
+__device__ __forceinline__ float bcast(float v, int t)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
+}
+__device__ __forceinline__ double bcast(double v, int t)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), t);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), t);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // ---------------------------------------------------------------------------
 // Reductions (fixed order: deterministic for a fixed launch shape).
 // ---------------------------------------------------------------------------

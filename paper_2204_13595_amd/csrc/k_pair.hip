@@ -237,9 +237,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     // their own slot.
     constexpr bool kFold = !EV;
     auto first_level = [&](int64_t a, int t, int& jc, int& r0, int& r1, int& jx) {
-        const int nc = __shfl(h_nc, t, 64);
-        const int ns = __shfl(h_ns, t, 64);
-        const int2 xr = make_int2(__shfl(h_x.x, t, 64), __shfl(h_x.y, t, 64));
+        const int nc = bcast(h_nc, t);
+        const int ns = bcast(h_ns, t);
+        const int2 xr = make_int2(bcast(h_x.x, t), bcast(h_x.y, t));
         const bool sample = !FULL && ns > p_shell;
         const int cnt = sample ? p_shell : ns;
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
@@ -259,13 +259,13 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const int jc = n_jc, r0 = n_r0, r1 = n_r1, jx = n_jx;
         // the next atom's first-level loads go out before this atom's dependent ones
         if (a + 1 < a1) first_level(a + 1, t + 1, n_jc, n_r0, n_r1, n_jx);
-        const uint4 si = make_uint4(__shfl(h_s.x, t, 64), __shfl(h_s.y, t, 64), __shfl(h_s.z, t, 64),
-                                    __shfl(h_s.w, t, 64));
-        const real qi = __shfl(h_q, t, 64) * pp.ke;
+        const uint4 si = make_uint4(bcast(h_s.x, t), bcast(h_s.y, t), bcast(h_s.z, t),
+                                    bcast(h_s.w, t));
+        const real qi = bcast(h_q, t) * pp.ke;
         const LJ<real>* lrow = lj + (int)si.w * n_types;
-        const int nc = __shfl(h_nc, t, 64);
-        const int ns = __shfl(h_ns, t, 64);
-        const int2 xr = make_int2(__shfl(h_x.x, t, 64), __shfl(h_x.y, t, 64));
+        const int nc = bcast(h_nc, t);
+        const int ns = bcast(h_ns, t);
+        const int2 xr = make_int2(bcast(h_x.x, t), bcast(h_x.y, t));
         const int32_t* crow = core + a * (int64_t)cap_core;
         const int32_t* srow = shell + a * (int64_t)cap_shell;
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
@@ -312,16 +312,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
             const int j = srow[sample ? (int)rrow[c] : c];
             add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
         }
-        const real fx = wave_sum_r(pc.fx + w * ps.fx);
-        const real fy = wave_sum_r(pc.fy + w * ps.fy);
-        const real fz = wave_sum_r(pc.fz + w * ps.fz);
-        const real ex = wave_sum_r(px.fx);
-        const real ey = wave_sum_r(px.fy);
-        const real ez = wave_sum_r(px.fz);
+        // one set of sums: the excluded-pair forces cancel pairwise, so the momentum
+        // correction may sum them with the rest
+        const real fx = wave_sum_r(pc.fx + w * ps.fx + px.fx);
+        const real fy = wave_sum_r(pc.fy + w * ps.fy + px.fy);
+        const real fz = wave_sum_r(pc.fz + w * ps.fz + px.fz);
         if (lane == 0) {
-            fsr[3 * a + 0] = fx + ex;
-            fsr[3 * a + 1] = fy + ey;
-            fsr[3 * a + 2] = fz + ez;
+            fsr[3 * a + 0] = fx;
+            fsr[3 * a + 1] = fy;
+            fsr[3 * a + 2] = fz;
             fc_sum[0] += (double)fx;
             fc_sum[1] += (double)fy;
             fc_sum[2] += (double)fz;
@@ -673,9 +672,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     // first-level indices of one atom's first pass: the lane's first symmetric-list
     // entry, its two batch ranks (or shell positions) and its first excluded partner
     auto first_level = [&](int64_t a, int t, int& jc, int& r0, int& r1, int& jx) {
-        const int nsym = __shfl(h_nsym, t, 64);
-        const int ns = __shfl(h_ns, t, 64);
-        const int2 xr = make_int2(__shfl(h_x.x, t, 64), __shfl(h_x.y, t, 64));
+        const int nsym = bcast(h_nsym, t);
+        const int ns = bcast(h_ns, t);
+        const int2 xr = make_int2(bcast(h_x.x, t), bcast(h_x.y, t));
         const bool sample = ns > p_shell;
         const int cnt = sample ? p_shell : ns;
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
@@ -693,15 +692,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const int jc = n_jc, r0 = n_r0, r1 = n_r1, jx = n_jx;
         // the next atom's first-level loads go out before this atom's dependent ones
         if (a + 1 < a1) first_level(a + 1, t_a + 1, n_jc, n_r0, n_r1, n_jx);
-        const uint4 si = make_uint4(__shfl(h_s.x, t_a, 64), __shfl(h_s.y, t_a, 64), __shfl(h_s.z, t_a, 64),
-                                    __shfl(h_s.w, t_a, 64));
+        const uint4 si = make_uint4(bcast(h_s.x, t_a), bcast(h_s.y, t_a), bcast(h_s.z, t_a),
+                                    bcast(h_s.w, t_a));
         const int ti = (int)si.w;
-        const real qi = __shfl(h_q, t_a, 64);
-        const real gx = __shfl(h_gx, t_a, 64), gy = __shfl(h_gy, t_a, 64), gz = __shfl(h_gz, t_a, 64);
+        const real qi = bcast(h_q, t_a);
+        const real gx = bcast(h_gx, t_a), gy = bcast(h_gy, t_a), gz = bcast(h_gz, t_a);
         const real pgx = gx - mx, pgy = gy - my, pgz = gz - mz;  // G'_i
-        const int nsym = __shfl(h_nsym, t_a, 64);
-        const int ns = __shfl(h_ns, t_a, 64);
-        const int2 xr = make_int2(__shfl(h_x.x, t_a, 64), __shfl(h_x.y, t_a, 64));
+        const int nsym = bcast(h_nsym, t_a);
+        const int ns = bcast(h_ns, t_a);
+        const int2 xr = make_int2(bcast(h_x.x, t_a), bcast(h_x.y, t_a));
         real rx = 0, ry = 0, rz = 0, rq = 0;
         real acc_sig[kMaxTypesGrad], acc_eps[kMaxTypesGrad];
 #pragma unroll
