@@ -1,25 +1,42 @@
 // Core and shell lists (Sec. 2.3): C(i) = {j != i : r_ij <= r_core} and
 // S(i) = {j : r_core < r_ij <= r_shell}, same-molecule pairs removed, in the
 // canonical order "stencil cell offset (dz, dy, dx) lexicographic, then the
-// atoms of each cell in cell order (by fixed-point x coordinate, then id)". One traversal of the shell stencil yields both
-// lists: the 27 core cells are visited in their own lexicographic order
-// inside it. Membership is exact: uint64 squared separations in quanta of
-// L / 2^32 against integer thresholds (an FP32 estimate settles every
-// candidate that is not within 2^-19 of a threshold; the rest are tested
-// exactly).
+// atoms of each cell in cell order (by fixed-point x coordinate, then id)".
+// One traversal of the shell stencil yields both lists: the 27 core cells are
+// visited in their own lexicographic order inside it. Membership is exact:
+// it is that of the uint64 squared separation in quanta of L / 2^32 against
+// the integer thresholds.
 //
 // One wavefront handles the atoms of G consecutive cells of one cell row (one
 // lane per atom). For every stencil row (dz, dy) the union of the lanes' x
-// ranges is staged in LDS; each lane scans only the cells its own sphere can
+// ranges is staged in LDS; each lane keeps only the cells its own sphere can
 // reach (per-atom pruning of rows and of the x range from exact cell-boundary
 // distances; inside the first and last cell of the range, a binary search on
-// the x-sorted cell trims the range to the atom's exact x extent), which
-// leaves the member order unchanged.
+// the x-sorted cell drops the candidates that lie beyond the atom's x
+// extent), which leaves the member order unchanged. The atoms whose range is
+// not empty are then taken two at a time, one per half-wave: the 32 lanes of
+// a half run over the atom's candidates and its members are compacted in
+// candidate order.
+//
+// Candidate test. Atoms and staged candidates also carry their position
+// relative to an origin at the wavefront's cells, in units of 2^s quanta and
+// truncated to 16 bits per axis (s is the smallest shift at which every such
+// coordinate of the stencil fits). A packed 16-bit subtraction and two-term
+// integer dot products give a squared separation d2 whose components are off
+// by less than delta units each, so d2 below an inner bound proves
+// membership and d2 above an outer bound proves non-membership; only the
+// candidates in between (about one per atom) take the exact 64-bit test, on
+// positions read from memory. The LDS footprint (about 6 KB per wavefront)
+// leaves room for six or more wavefronts per SIMD.
 //
 // Layout: fixed-capacity rows (row k of atom k in cell order), entries are
-// cell-sorted atom indices, written four at a time. Counts beyond the capacity
-// are still counted, so the host can grow the rows and rebuild.
+// cell-sorted atom indices. Counts beyond the capacity are still counted, so
+// the host can grow the rows and rebuild; the stores of a pair of atoms go
+// through one buffer descriptor that spans just their rows, so an overflowing
+// row can only spill into rows that the rebuild rewrites.
 #include <algorithm>
+#include <cmath>
+#include <type_traits>
 
 #include "irbe_device.hpp"
 #include "irbe_internal.hpp"
@@ -28,14 +45,18 @@ namespace irbe {
 
 constexpr int kListWave = 64;
 constexpr int kTileCap = 256;  // staged candidates per pass
+constexpr int kTilePad = 32;   // slack after the staged candidates for the lanes past a range's end
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer descriptor, 32-bit data format
+constexpr int kNoStore = 0x7fffffff;      // buffer offset beyond any list descriptor's range
 
-__device__ __forceinline__ uint64_t dist2_exact(uint4 a, uint4 b)
-{
-    const int32_t dx = (int32_t)(b.x - a.x);
-    const int32_t dy = (int32_t)(b.y - a.y);
-    const int32_t dz = (int32_t)(b.z - a.z);
-    return (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
-}
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Integer bounds on the packed squared separation d2: d2 < *_in proves
+// membership of the ball, d2 > *_out proves the opposite.
+struct PackedBounds {
+    uint32_t core_in, core_out, shell_in, shell_out;
+};
 
 __device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
@@ -49,29 +70,56 @@ __device__ __forceinline__ uint32_t slab_gap(uint32_t s, int d, int c, const uin
     return 0u;
 }
 
-// Number of set bits of mask below this lane.
-__device__ __forceinline__ int lanes_below(uint64_t mask)
+// Coordinate c relative to origin o, in units of 2^sh quanta, as 16 bits.
+__device__ __forceinline__ uint32_t pack_rel(uint32_t c, uint32_t o, int sh)
 {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    return (uint32_t)(((int32_t)(c - o)) >> sh) & 0xffffu;
+}
+
+// Squared separation of two packed positions (x | y << 16, z): exact in the
+// 16-bit units; the sum of the three squares stays below 2^32.
+__device__ __forceinline__ uint32_t d2_packed(uint32_t cxy, uint32_t cz, uint32_t axy, uint32_t az)
+{
+    const s16x2 dxy = __builtin_bit_cast(s16x2, cxy) - __builtin_bit_cast(s16x2, axy);
+    const s16x2 dz = __builtin_bit_cast(s16x2, cz) - __builtin_bit_cast(s16x2, az);
+    return (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, __builtin_amdgcn_sdot2(dz, dz, 0, false), false);
+}
+
+__device__ __forceinline__ uint64_t dist2_exact(uint4 a, uint4 b)
+{
+    const int32_t dx = (int32_t)(b.x - a.x);
+    const int32_t dy = (int32_t)(b.y - a.y);
+    const int32_t dz = (int32_t)(b.z - a.z);
+    return (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
+}
+
+// Lanes with p set (a wave-uniform mask).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Position of this lane among the set lanes of its half-wave in the mask
+// (mlo | mhi << 32), plus base; lowm is all ones in the lower half-wave and
+// zero in the upper one, so that the upper lanes skip the lower half's bits.
+__device__ __forceinline__ int member_pos(uint32_t mlo, uint32_t mhi, uint32_t lowm, int base)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo & lowm, (uint32_t)base));
 }
 
 template <bool FULL>
 __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
-    int n_c, int lo, int hi, int G, int prune, uint64_t t_core, uint64_t t_shell, float tfc_lo, float tfc_hi,
-    float tfs_lo, float tfs_hi,
-    const uint4* __restrict__ spos, const int32_t* __restrict__ smol, const int32_t* __restrict__ cell_start,
-    const uint32_t* __restrict__ bound_g, int cap_core, int cap_shell, int32_t* __restrict__ core,
-    int32_t* __restrict__ ncore, int32_t* __restrict__ shell, int32_t* __restrict__ nshell,
-    int32_t* __restrict__ maxcnt)
+    int n_c, int lo, int hi, int G, int prune, int trim, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb, uint64_t t_core,
+    uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const int32_t* __restrict__ smol,
+    const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g, int cap_core, int cap_shell,
+    int32_t* __restrict__ core, int32_t* __restrict__ ncore, int32_t* __restrict__ shell,
+    int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt)
 {
-    __shared__ uint4 tile[kTileCap];      // staged candidates: fixed-point x, y, z and sorted index
-    __shared__ int32_t tmol[kTileCap];    // candidate's exclusion id (molecule, or -2 - index)
-    __shared__ uint4 apos[kListWave];     // atom's x, y, z and exclusion id
-    __shared__ int2 arng[kListWave];      // atom's candidate range in the tile
-    __shared__ int2 acnt[kListWave];      // atom's core / shell list lengths so far
+    __shared__ u32x4 trec[kTileCap + kTilePad];  // candidate: packed x | y, packed z, exclusion id, sorted index
+    __shared__ u32x4 apk[kListWave];             // atom: packed x | y, packed z, exclusion id, range start | length << 16
+    __shared__ int2 acnt[kListWave];             // atom: core / shell list lengths so far
     const uint32_t* bound = bound_g;  // indexed by wave-uniform cell coordinates
     const int lane = threadIdx.x;
-    const int half = lane >> 5, hl = lane & 31;
+    const int hl = lane & 31;
+    const int hsel = -(lane >> 5);  // all ones in the upper half-wave
+    const uint32_t lowm = ~(uint32_t)hsel;
     const int groups_per_row = (n_c + G - 1) / G;
     const int g = (int)xcd_block(blockIdx.x, gridDim.x);
     const int rowid = g / groups_per_row;
@@ -84,16 +132,19 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     const int span_u = gr - 1 + span_c;       // cells of the union x range
     const int xu0 = wrap(x0 + lo, n_c);       // first cell of the union
     const int lenA = min(span_u, n_c - xu0);  // cells before the wrap
+    const uint32_t orx = bound[x0] + ox, ory = bound[cy] + oyz, orz = bound[cz] + oyz;
     int maxc = 0, maxs = 0;
     for (int chunk = a0; chunk < a1; chunk += kListWave) {
         const int k = chunk + lane;
         const bool act = k < a1;
-        const int na = min(kListWave, a1 - chunk);
         const uint4 si = act ? spos[k] : make_uint4(0, 0, 0, 0);
         const int32_t mi = act ? smol[k] : -1;
         const int cx = (int)(((uint64_t)si.x * (uint32_t)n_c) >> 32);
         const int ti = act ? wrap(cx - x0, n_c) : 0;  // lane's home cell in [0, gr)
-        apos[lane] = make_uint4(si.x, si.y, si.z, (uint32_t)(mi >= 0 ? mi : -2 - k));
+        const uint32_t axy = pack_rel(si.x, orx, sh) | (pack_rel(si.y, ory, sh) << 16);
+        const uint32_t az = pack_rel(si.z, orz, sh);
+        const uint32_t amol = (uint32_t)(mi >= 0 ? mi : -2 - k);
+        const int axp = (int)(short)(axy & 0xffffu);  // packed x as a signed value
         acnt[lane] = make_int2(0, 0);
         for (int dz = lo; dz <= hi; ++dz) {
             const int z = wrap(cz + dz, n_c);
@@ -101,6 +152,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
             for (int dy = lo; dy <= hi; ++dy) {
                 const int y = wrap(cy + dy, n_c);
                 const int row = (z * n_c + y) * n_c;
+                // rows two or more cells away in y or z hold no core candidate:
+                // a whole cell edge (>= r_core) lies between them and the atom
                 const bool core_row = !FULL && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
                 // lane's candidate cells in this row: tile cells [u_lo, u_hi]
                 int u_lo = ti, u_hi = ti + span_c - 1;
@@ -125,7 +178,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         u_hi = ti + (min(oh, hi) - lo);
                     }
                 }
-                if (__ballot(need) == 0) continue;
+                if (ballot(need) == 0) continue;
                 // union of the x ranges: segment A (cells xu0 .. xu0+lenA-1), then B (cells 0 ..)
                 const int jA = cell_start[row + xu0];
                 const int eA = cell_start[row + xu0 + lenA];
@@ -153,16 +206,19 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         const int j = p < nA ? jA + p : jB + (p - nA);
                         const uint4 sj = spos[j];
                         const int32_t mj = smol[j];
-                        tile[t] = make_uint4(sj.x, sj.y, sj.z, (uint32_t)j);
-                        tmol[t] = mj >= 0 ? mj : -2 - j;
+                        trec[t] = u32x4{pack_rel(sj.x, orx, sh) | (pack_rel(sj.y, ory, sh) << 16),
+                                        pack_rel(sj.z, orz, sh), (uint32_t)(mj >= 0 ? mj : -2 - j), (uint32_t)j};
                     }
                     __syncthreads();
-                    if (prune && need && total <= kTileCap) {
-                        // the cells are x-sorted: trim the first and the last cell of the range
+                    if (trim && need && total <= kTileCap) {
+                        // the cells are x-sorted, so their packed x is non-decreasing: trim
+                        // the first and the last cell of the range of the candidates whose
+                        // packed x proves them farther than the sphere's x extent
+                        const int ext_u = (int)((uint32_t)ext_i >> sh) + 1;
                         int a = p_lo, b = pc1;
                         while (a < b) {
                             const int m = (a + b) >> 1;
-                            if ((int32_t)(tile[m].x - si.x) < -ext_i) a = m + 1;
+                            if ((int)(short)(trec[m].x & 0xffffu) - axp < -ext_u) a = m + 1;
                             else b = m;
                         }
                         p_lo = a;
@@ -170,75 +226,105 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         b = p_hi;
                         while (a < b) {
                             const int m = (a + b) >> 1;
-                            if ((int32_t)(tile[m].x - si.x) <= ext_i) a = m + 1;
+                            if ((int)(short)(trec[m].x & 0xffffu) - axp <= ext_u) a = m + 1;
                             else b = m;
                         }
                         p_hi = a;
                     }
                     // this tile's part of the lane's range, in tile coordinates
                     const int s0 = need ? max(p_lo, base) - base : 0;
-                    const int s1 = need ? min(p_hi, base + cnt) - base : 0;
-                    arng[lane] = make_int2(s0, max(s1, s0));
+                    const int len_l = need ? max(min(p_hi, base + cnt) - base - s0, 0) : 0;
+                    apk[lane] = u32x4{axy, az, amol, (uint32_t)s0 | ((uint32_t)len_l << 16)};
                     __syncthreads();
-                    // two atoms at a time, one per half-wave; the lanes of a half run over
-                    // the atom's candidates and the members are compacted in candidate order
-                    for (int pa = 0; pa < na; pa += 2) {
-                        const int ka = min(pa + half, na - 1);
-                        const bool hv = pa + half < na;
-                        const int2 rg = arng[ka];
-                        const int len = hv ? rg.y - rg.x : 0;
-                        const int maxlen = max(len, __shfl_xor(len, 32, 64));
-                        if (maxlen == 0) continue;
-                        const uint4 sa = apos[ka];
-                        const int32_t ma = (int32_t)sa.w;
-                        const int kk = chunk + ka;
-                        int2 c = acnt[ka];
-                        int32_t* srow = shell + (int64_t)kk * cap_shell;
-                        int32_t* crow = core + (int64_t)kk * cap_core;
-                        for (int c0 = 0; c0 < maxlen; c0 += 32) {
-                            const int q = (rg.x + c0 + hl) & (kTileCap - 1);
-                            const uint4 sj = tile[q];
-                            const int32_t mj = tmol[q];
-                            const int32_t ddx = (int32_t)(sj.x - sa.x);
-                            const int32_t ddy = (int32_t)(sj.y - sa.y);
-                            const int32_t ddz = (int32_t)(sj.z - sa.z);
-                            const float fx = (float)ddx, fy = (float)ddy, fz = (float)ddz;
-                            const float d2f = fx * fx + fy * fy + fz * fz;
-                            const bool keep = c0 + hl < len && mj != ma;
-                            bool in_core = !FULL && keep && d2f < tfc_lo;
-                            bool in_shell = keep && (FULL || d2f > tfc_hi) && d2f < tfs_lo;
-                            const bool amb = keep && d2f <= tfs_hi && !in_core && !in_shell;
-                            if (__ballot(amb)) {
-                                // within 2e-6 of a threshold: the exact integer test decides
-                                if (amb) {
-                                    const uint64_t d2 = (uint64_t)((int64_t)ddx * ddx) +
-                                                        (uint64_t)((int64_t)ddy * ddy) + (uint64_t)((int64_t)ddz * ddz);
-                                    in_core = !FULL && d2 <= t_core;
-                                    in_shell = !in_core && d2 <= t_shell;
+                    // atoms are paired with atoms of the same number of 32-candidate
+                    // chunks, so no half-wave reads past its own range (+ 31); a lone
+                    // atom of a chunk count takes both halves (the upper one idle)
+                    const int nch = (len_l + 31) >> 5;
+                    for (int chunks = 1; chunks <= kTileCap / 32; ++chunks) {
+                        uint64_t pend = ballot(nch == chunks);
+                        while (pend) {
+                            // the next two atoms: a in the lower half, b in the upper
+                            const int a = __builtin_ctzll(pend);
+                            pend &= pend - 1;
+                            const bool has_b = pend != 0;
+                            const int b = has_b ? __builtin_ctzll(pend) : a;
+                            if (has_b) pend &= pend - 1;
+                            const int drow = b - a;
+                            const int ka = a + (hsel & drow);  // this half's atom
+                            const u32x4 ap = apk[ka];
+                            const int2 cn = acnt[ka];
+                            const int lenm = (int)(ap.w >> 16) - hl;
+                            const int qb = (int)(ap.w & 0xffffu) + hl;
+                            int cs = cn.y, cc = cn.x;  // this half's atom: list lengths so far
+                            // rows a .. b of the list arrays; the upper half writes at row b
+                            const __amdgpu_buffer_rsrc_t rs_s = __builtin_amdgcn_make_buffer_rsrc(
+                                shell + (int64_t)(chunk + a) * cap_shell, (short)0, (drow + 1) * cap_shell * 4, kBufferWord3);
+                            const int hoff_s = hsel & (drow * cap_shell * 4);
+                            auto scan = [&](auto core_tag) {
+                                constexpr bool CORE = decltype(core_tag)::value;
+                                const __amdgpu_buffer_rsrc_t rs_c = __builtin_amdgcn_make_buffer_rsrc(
+                                    core + (int64_t)(chunk + a) * cap_core, (short)0, (drow + 1) * cap_core * 4, kBufferWord3);
+                                const int hoff_c = hsel & (drow * cap_core * 4);
+                                for (int c0 = 0; c0 < chunks * 32; c0 += 32) {
+                                    const u32x4 r = trec[qb + c0];
+                                    const uint32_t d2 = d2_packed(r.x, r.y, ap.x, ap.y);
+                                    // lane predicates and their wave masks, each mask the AND of
+                                    // ballots of single compares (scalar operations only)
+                                    const bool k_in = c0 < lenm, k_mol = r.z != ap.z;
+                                    const uint64_t m_keep = ballot(k_in) & ballot(k_mol);
+                                    bool in_core = false, in_shell;
+                                    uint64_t m_core = 0, m_shell, m_amb;
+                                    if (CORE) {
+                                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
+                                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
+                                        in_core = k_in & k_mol & c_in;
+                                        in_shell = k_in & k_mol & c_out & s_in;
+                                        m_core = m_keep & ballot(c_in);
+                                        m_shell = m_keep & ballot(c_out) & ballot(s_in);
+                                        m_amb = m_keep & ~ballot(s_out) & ~m_core & ~m_shell;
+                                    } else {
+                                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
+                                        in_shell = k_in & k_mol & s_in;
+                                        m_shell = m_keep & ballot(s_in);
+                                        m_amb = m_keep & ~ballot(s_out) & ~m_shell;
+                                    }
+                                    if (m_amb != 0) {
+                                        // between the bounds: the exact test decides (wave-uniform
+                                        // branch; only the lanes of m_amb take its result)
+                                        const bool amb = (m_amb >> lane) & 1u;
+                                        const uint64_t d2x = dist2_exact(spos[chunk + ka], spos[amb ? (int)r.w : chunk + ka]);
+                                        const bool xc = CORE && d2x <= t_core;
+                                        const bool xs = !xc && d2x <= t_shell;
+                                        in_core = amb ? xc : in_core;
+                                        in_shell = amb ? xs : in_shell;
+                                        m_core = (m_core & ~m_amb) | (ballot(xc) & m_amb);
+                                        m_shell = (m_shell & ~m_amb) | (ballot(xs) & m_amb);
+                                    }
+                                    const uint32_t ms_lo = (uint32_t)m_shell, ms_hi = (uint32_t)(m_shell >> 32);
+                                    const int ps_lo = __popc(ms_lo);
+                                    {
+                                        // non-members store past the descriptor's range (dropped)
+                                        const int pos = member_pos(ms_lo, ms_hi, lowm, cs);
+                                        const int off = in_shell ? hoff_s + (pos << 2) : kNoStore;
+                                        __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_s, off, 0, 0);
+                                    }
+                                    cs += ps_lo + (hsel & (__popc(ms_hi) - ps_lo));
+                                    if (CORE) {
+                                        const uint32_t mc_lo = (uint32_t)m_core, mc_hi = (uint32_t)(m_core >> 32);
+                                        const int pc_lo = __popc(mc_lo);
+                                        {
+                                            const int pos = member_pos(mc_lo, mc_hi, lowm, cc);
+                                            const int off = in_core ? hoff_c + (pos << 2) : kNoStore;
+                                            __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_c, off, 0, 0);
+                                        }
+                                        cc += pc_lo + (hsel & (__popc(mc_hi) - pc_lo));
+                                    }
                                 }
-                            }
-                            const uint64_t m_shell = __ballot(in_shell);
-                            // positions within the half: members below this lane, minus the
-                            // other half's members when this is the upper half
-                            const int s_lo = __popc((uint32_t)m_shell);
-                            const int s_hi = __popc((uint32_t)(m_shell >> 32));
-                            if (in_shell) {
-                                const int pos = c.y + lanes_below(m_shell) - (half ? s_lo : 0);
-                                if (pos < cap_shell) srow[pos] = (int32_t)sj.w;
-                            }
-                            c.y += half ? s_hi : s_lo;
-                            if (core_row) {
-                                const uint64_t m_core = __ballot(in_core);
-                                const int c_lo = __popc((uint32_t)m_core);
-                                const int c_hi = __popc((uint32_t)(m_core >> 32));
-                                if (in_core) {
-                                    const int pos = c.x + lanes_below(m_core) - (half ? c_lo : 0);
-                                    if (pos < cap_core) crow[pos] = (int32_t)sj.w;
-                                }
-                                c.x += half ? c_hi : c_lo;
-                            }
+                            };
+                            if (core_row) scan(std::true_type{});
+                            else scan(std::false_type{});
+                            if (lane == 0 || (lane == 32 && has_b)) acnt[ka] = make_int2(cc, cs);
                         }
-                        if (hv && hl == 0) acnt[ka] = c;
                     }
                 }
             }
@@ -265,6 +351,63 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     }
 }
 
+namespace {
+
+// Shift s and bounds of the packed candidate test. With a pruned stencil
+// every relative coordinate of a wavefront lies within
+// max(R + G/2, R + 1) cell edges (+ rounding) of its origin; s is the
+// smallest shift that fits that in 16 signed bits with two units to spare,
+// and each packed component is then off by less than delta = 1 unit. When
+// the stencil wraps the box, the top 16 bits of the coordinates are used
+// (s = 16, modular differences, delta = 3).
+// With e = sum of component errors: D <= d2 + 2 delta sqrt(3 d2) + 3 delta^2
+// and D >= d2 - 2 delta sqrt(3 d2) for the exact squared separation D in the
+// same units; the bounds follow, with one unit of margin for rounding here.
+struct PackedGeometry {
+    int sh = 16;
+    uint32_t ox = 0, oyz = 0;
+    PackedBounds tb{};
+};
+
+PackedGeometry packed_geometry(const Geometry& g, int G, bool prune)
+{
+    PackedGeometry p;
+    const double E = 4294967296.0 / (double)g.n_c;
+    double delta = 3.0;
+    if (prune) {
+        const double M = std::max(g.reach + 0.5 * G, g.reach + 1.0) * E + 4.0;
+        for (int s = 0; s <= 15; ++s) {
+            if (M <= std::ldexp(1.0, 15 + s) - std::ldexp(1.0, s + 1)) {
+                p.sh = s;
+                delta = 1.0;
+                p.ox = (uint32_t)(0.5 * G * E);
+                p.oyz = (uint32_t)(0.5 * E);
+                break;
+            }
+        }
+    }
+    const double unit2 = std::ldexp(1.0, 2 * p.sh);
+    auto inner = [&](uint64_t t) -> uint32_t {
+        const double T = (double)t / unit2;
+        const double v = std::floor(T - 2.0 * delta * std::sqrt(3.0 * T) - 3.0 * delta * delta - 1.0);
+        return v > 0.0 ? (uint32_t)v : 0u;
+    };
+    auto outer = [&](uint64_t t) -> uint32_t {
+        const double T = (double)t / unit2;
+        const double r = delta * std::sqrt(3.0) + std::sqrt(3.0 * delta * delta + T);
+        double o = std::ceil(r * r) + 2.0;
+        while ((o + 1.0) - 2.0 * delta * std::sqrt(3.0 * (o + 1.0)) <= T + 1.0) o += 1.0;
+        return o < 4294967295.0 ? (uint32_t)o : 4294967295u;
+    };
+    p.tb.core_in = inner(g.t_core);
+    p.tb.core_out = outer(g.t_core);
+    p.tb.shell_in = inner(g.t_shell);
+    p.tb.shell_out = outer(g.t_shell);
+    return p;
+}
+
+}  // namespace
+
 hipError_t launch_build_lists(irbe_ctx* h)
 {
     const Geometry& g = h->geo;
@@ -273,20 +416,20 @@ hipError_t launch_build_lists(irbe_ctx* h)
     const int G = narrow ? std::min(4, n_c - 2 * g.reach) : 1;
     const int prune = narrow ? 1 : 0;
     const int64_t groups = (int64_t)n_c * n_c * ((n_c + G - 1) / G);
-    // FP32 thresholds with a relative margin of 2e-6, far above the FP32
-    // rounding of the squared separations (< 3e-7): outside the bands the FP32
-    // decision equals the exact one, inside them the exact test decides.
-    const float tfc = (float)g.t_core, tfs = (float)g.t_shell;
-    const float tfc_lo = tfc * 0.999998f, tfc_hi = tfc * 1.000002f;
-    const float tfs_lo = tfs * 0.999998f, tfs_hi = tfs * 1.000002f;
+    const PackedGeometry pg = packed_geometry(g, G, narrow);
+    // packed x is monotone along a cell only when no relative coordinate wraps
+    const int trim = narrow && pg.sh < 16 ? 1 : 0;
+    // FP32 shell threshold with a relative margin of 2e-6, far above the FP32
+    // rounding of the row gaps: the row pruning never drops a member.
+    const float tfs_hi = (float)g.t_shell * 1.000002f;
     if (h->full_list)
         k_build_lists_tiled<true><<<(unsigned)groups, kListWave, 0, h->stream>>>(
-            n_c, g.lo, g.hi, G, prune, g.t_core, g.t_shell, tfc_lo, tfc_hi, tfs_lo, tfs_hi, h->spos, h->smol, h->cell_start, h->cell_bound,
-            h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt);
+            n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.t_core, g.t_shell, tfs_hi, h->spos, h->smol,
+            h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt);
     else
         k_build_lists_tiled<false><<<(unsigned)groups, kListWave, 0, h->stream>>>(
-            n_c, g.lo, g.hi, G, prune, g.t_core, g.t_shell, tfc_lo, tfc_hi, tfs_lo, tfs_hi, h->spos, h->smol, h->cell_start, h->cell_bound,
-            h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt);
+            n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.t_core, g.t_shell, tfs_hi, h->spos, h->smol,
+            h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt);
     return hipGetLastError();
 }
 
