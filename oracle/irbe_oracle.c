@@ -35,6 +35,7 @@
 #define ORC_PI 3.14159265358979323846
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ECAPACITY = -4, ORC_ENONFINITE = -7 };
+enum { ORC_LISTS_SPLIT = 0, ORC_LISTS_FULL = 1, ORC_LISTS_STENCIL = 2 };
 
 /* ------------------------------------------------------------------------ */
 /* Geometry                                                                  */
@@ -145,8 +146,14 @@ static inline int orc_excluded(const int32_t* mol, int64_t i, int64_t j)
  *
  * Rows are the atoms sel[0..n_sel) (all atoms, in id order, when sel is NULL).
  * Pass 1 (idx == NULL) writes the row counts into *_off[k+1]; pass 2 fills.
- * full_list != 0 merges the two sets into one list (core then shell members in
- * a single traversal of the shell stencil), written to the shell arrays.
+ * kind = ORC_LISTS_FULL merges the two sets into one list (core then shell
+ * members in a single traversal of the shell stencil), written to the shell
+ * arrays. kind = ORC_LISTS_STENCIL writes, in place of S(i), the stencil
+ * candidates K(i): every atom of the shell stencil's cells (i itself and its
+ * molecule included), in the same canonical order; the random batch is then
+ * drawn from K(i) directly (Algorithm 1 draws from the stencil; Sec. 2.3 notes
+ * that the filter step can be skipped) and a drawn atom counts only when it
+ * is a member of S(i).
  */
 static int64_t orc_list_row(int64_t i, const uint32_t* s, const int32_t* mol, int32_t n_c, int32_t R,
                             uint64_t t_core, uint64_t t_shell, const int64_t* cell_start,
@@ -173,12 +180,16 @@ static int64_t orc_list_row(int64_t i, const uint32_t* s, const int32_t* mol, in
                 int64_t c = (z * n_c + y) * n_c + x;
                 for (int64_t k = cell_start[c]; k < cell_start[c + 1]; ++k) {
                     int64_t j = cell_atoms[k];
-                    if (j == i || orc_excluded(mol, i, j)) continue;
-                    uint64_t d2 = orc_dist2(s, i, j);
                     int take;
-                    if (want_core) take = d2 <= t_core;
-                    else if (full_list) take = d2 <= t_shell;
-                    else take = d2 > t_core && d2 <= t_shell;
+                    if (!want_core && full_list == ORC_LISTS_STENCIL) {
+                        take = 1;
+                    } else {
+                        if (j == i || orc_excluded(mol, i, j)) continue;
+                        uint64_t d2 = orc_dist2(s, i, j);
+                        if (want_core) take = d2 <= t_core;
+                        else if (full_list == ORC_LISTS_FULL) take = d2 <= t_shell;
+                        else take = d2 > t_core && d2 <= t_shell;
+                    }
                     if (take) {
                         if (out) out[count] = (int32_t)j;
                         ++count;
@@ -212,12 +223,13 @@ int orc_build_lists(int64_t n, const uint32_t* s, const int32_t* mol, double L, 
     for (int64_t k = 0; k < rows; ++k) {
         int64_t i = sel ? sel[k] : k;
         if (!fill) {
-            core_off[k + 1] = full_list ? 0
-                              : orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 1, 0, NULL);
+            core_off[k + 1] = full_list == ORC_LISTS_FULL
+                                  ? 0
+                                  : orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 1, 0, NULL);
             shell_off[k + 1] = orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 0,
                                             full_list, NULL);
         } else {
-            if (!full_list && core_idx)
+            if (full_list != ORC_LISTS_FULL && core_idx)
                 orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 1, 0, core_idx + core_off[k]);
             if (shell_idx)
                 orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 0, full_list,
@@ -458,6 +470,7 @@ static inline int64_t orc_row_atom(const int64_t* rows, int64_t r) { return rows
  * for each row atom i. core_off/core_idx hold C(i) per row (may be NULL: empty);
  * shell_off/shell_idx hold S(i) per row; the batch B(i) is given as ranks into
  * S(i) (batch_off/batch_rank per row; NULL: every member); w per row (NULL: 1).
+ * accept (NULL: all) flags the batch entries that count (stencil sampling).
  * e8 accumulates [U_coul, U_lj, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz] with the
  * estimator U = 1/2 sum_i (sum_C u_ij + w_i sum_B u_ij), and likewise for the
  * pair virial W_ab = -1/2 sum_i sum_j w r_ij,a f_ij,b.
@@ -466,7 +479,7 @@ int orc_short_range(const orc_system* sy, int64_t n, const uint32_t* s, const do
                     const double* lj_sigma, const double* lj_eps, const int64_t* rows, int64_t n_rows,
                     const int64_t* core_off, const int32_t* core_idx, const int64_t* shell_off,
                     const int32_t* shell_idx, const int64_t* batch_off, const int32_t* batch_rank,
-                    const double* w, double* f_out, double* e8)
+                    const double* w, const uint8_t* accept, double* f_out, double* e8)
 {
     (void)n;
     const int nt = sy->n_types;
@@ -488,6 +501,7 @@ int orc_short_range(const orc_system* sy, int64_t n, const uint32_t* s, const do
                     int64_t j;
                     if (pass == 0) j = core_idx[core_off[r] + k];
                     else j = shell_idx[shell_off[r] + (batch_off ? batch_rank[batch_off[r] + k] : k)];
+                    if (pass == 1 && accept && !accept[(batch_off ? batch_off[r] : shell_off[r]) + k]) continue;
                     double dv[3], dist, phi, uc, ul;
                     orc_sep(s, i, j, sy->L, dv, &dist);
                     int tp = type[i] * nt + type[j];
@@ -653,8 +667,8 @@ int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, 
                             const int32_t* type, const double* lj_sigma, const double* lj_eps,
                             const int64_t* core_off, const int32_t* core_idx, const int64_t* shell_off,
                             const int32_t* shell_idx, const int64_t* batch_off, const int32_t* batch_rank,
-                            const double* w, int rbl, const double* G, double* g_pos, double* g_q,
-                            double* g_sigma, double* g_eps)
+                            const double* w, const uint8_t* accept, int rbl, const double* G, double* g_pos,
+                            double* g_q, double* g_sigma, double* g_eps)
 {
     const int nt = sy->n_types;
     const double b = sy->beta, ke = sy->ke, spi = sqrt(ORC_PI);
@@ -675,6 +689,7 @@ int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, 
                 int64_t j;
                 if (pass == 0) j = core_idx[core_off[i] + k];
                 else j = shell_idx[shell_off[i] + (batch_off ? batch_rank[batch_off[i] + k] : k)];
+                if (pass == 1 && accept && !accept[(batch_off ? batch_off[i] : shell_off[i]) + k]) continue;
                 double dv[3], r;
                 orc_sep(s, i, j, sy->L, dv, &r);
                 int tp = type[i] * nt + type[j];
@@ -822,6 +837,33 @@ int orc_shell_batches(uint64_t seed, uint64_t step, const int64_t* rows, int64_t
         int32_t n_s = (int32_t)(shell_off[r + 1] - shell_off[r]);
         orc_shell_ranks(seed, step, id, n_s, p_s, batch_rank + batch_off[r]);
         w[r] = n_s > p_s ? (double)n_s / (double)p_s : 1.0;
+    }
+    return ORC_OK;
+}
+
+/* Stencil sampling: accept[e] = 1 when batch entry e of row r (the atom of
+ * rank batch_rank[e] in the row's stencil candidates, or entry e itself when
+ * batch_off is NULL) is a member of S(i): not i, not of i's molecule, and
+ * T_c < D^2 <= T_s with the thresholds of O1. */
+int orc_batch_accept(const uint32_t* s, const int32_t* mol, double L, double r_core, double r_shell,
+                     const int64_t* rows, int64_t n_rows, const int64_t* shell_off, const int32_t* shell_idx,
+                     const int64_t* batch_off, const int32_t* batch_rank, uint8_t* accept)
+{
+    uint64_t t_core = orc_threshold(r_core, L);
+    uint64_t t_shell = orc_threshold(r_shell, L);
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t i = orc_row_atom(rows, r);
+        int64_t cnt = batch_off ? batch_off[r + 1] - batch_off[r] : shell_off[r + 1] - shell_off[r];
+        int64_t e0 = batch_off ? batch_off[r] : shell_off[r];
+        for (int64_t k = 0; k < cnt; ++k) {
+            int64_t j = shell_idx[shell_off[r] + (batch_off ? batch_rank[e0 + k] : k)];
+            int ok = j != i && !orc_excluded(mol, i, j);
+            if (ok) {
+                uint64_t d2 = orc_dist2(s, i, j);
+                ok = d2 > t_core && d2 <= t_shell;
+            }
+            accept[e0 + k] = (uint8_t)ok;
+        }
     }
     return ORC_OK;
 }

@@ -10,9 +10,12 @@ Liang, Xu, Zhao, arXiv:2204.13595:
   -> momentum correction -> k samples -> structure factor -> long-range force.
 
 Modes: ``rbl`` (random batch list + random batch Ewald, the IRBE force),
-``full`` (every pair within r_shell + random batch Ewald: the paper's "RBE"
-comparator) and ``ewald`` (every pair within r_shell + the full reciprocal sum:
-the deterministic Ewald reference whose expectation the estimators match).
+``stencil`` (the same, with the shell batch drawn from the atoms of the
+stencil's cells instead of from the shell list: weight = candidate count / p~,
+a drawn atom counts only when it is a shell member), ``full`` (every pair
+within r_shell + random batch Ewald: the paper's "RBE" comparator) and
+``ewald`` (every pair within r_shell + the full reciprocal sum: the
+deterministic Ewald reference whose expectation the estimators match).
 """
 from __future__ import annotations
 
@@ -33,6 +36,7 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _f64p = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
 class _System(ctypes.Structure):
@@ -80,7 +84,9 @@ def lib():
                                          _i64p, _i64p]
         L.orc_short_range.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i32p, _f64p, _f64p,
                                       _i64p, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _i64p, _i32p, _f64p,
-                                      _f64p, _f64p]
+                                      _u8p, _f64p, _f64p]
+        L.orc_batch_accept.argtypes = [_u32p, _i32p, ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64p,
+                                       ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _u8p]
         L.orc_exclusions.argtypes = [ctypes.POINTER(_System), _u32p, _f64p, _i64p, ctypes.c_int64, _i64p, _i64p,
                                      _f64p, _f64p]
         L.orc_structure_factor.argtypes = [_u32p, _f64p, _i64p, ctypes.c_int64, ctypes.c_int32, _i32p, _f64p]
@@ -89,7 +95,7 @@ def lib():
         L.orc_kspace_energy.argtypes = [ctypes.POINTER(_System), ctypes.c_int32, _i32p, _f64p, _f64p, _f64p]
         L.orc_short_range_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i32p,
                                               _f64p, _f64p, _i64p, _i32p, _i64p, _i32p, _i64p, _i32p, _f64p,
-                                              ctypes.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
+                                              _u8p, ctypes.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.orc_exclusions_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i64p, _i64p,
                                              _f64p, _f64p, _f64p]
         L.orc_kspace_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, ctypes.c_int32,
@@ -172,7 +178,10 @@ class Lists:
     rows: np.ndarray | None
 
 
-def build_lists(s, mol, box, r_core, r_shell, full=False, rows=None) -> Lists:
+def build_lists(s, mol, box, r_core, r_shell, full=False, rows=None, stencil=False) -> Lists:
+    """C(i) and S(i) per row (Sec. 2.3); ``full``: one list C(i) u S(i);
+    ``stencil``: C(i) and, in place of S(i), the stencil candidates K(i)."""
+    kind = 2 if stencil else (1 if full else 0)
     s = _c(s, np.uint32)
     mol = _c(mol, np.int32)
     n = s.shape[0]
@@ -181,13 +190,13 @@ def build_lists(s, mol, box, r_core, r_shell, full=False, rows=None) -> Lists:
     core_off = np.zeros(nr + 1, dtype=np.int64)
     shell_off = np.zeros(nr + 1, dtype=np.int64)
     L = lib()
-    rc = L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, int(full), _p(rows_a, _i64p),
+    rc = L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, kind, _p(rows_a, _i64p),
                            nr, _p(core_off, _i64p), None, _p(shell_off, _i64p), None)
     if rc != 0:
         raise ValueError(f"build_lists: invalid geometry ({rc})")
     core_idx = np.empty(max(int(core_off[-1]), 1), dtype=np.int32)
     shell_idx = np.empty(max(int(shell_off[-1]), 1), dtype=np.int32)
-    L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, int(full), _p(rows_a, _i64p), nr,
+    L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, kind, _p(rows_a, _i64p), nr,
                       _p(core_off, _i64p), _p(core_idx, _i32p), _p(shell_off, _i64p), _p(shell_idx, _i32p))
     return Lists(core_off, core_idx[:core_off[-1]], shell_off, shell_idx[:shell_off[-1]], rows_a)
 
@@ -244,6 +253,20 @@ def shell_batches(seed: int, step: int, lists: Lists, p_s: int):
     return off, rank[:off[-1]], w
 
 
+def batch_accept(s, mol, box, r_core, r_shell, lists: Lists, batches) -> np.ndarray:
+    """Per batch entry (stencil sampling): 1 when the drawn candidate is a member of S(i)."""
+    s = _c(s, np.uint32)
+    mol = _c(mol, np.int32)
+    b_off, b_rank, _ = batches
+    rows = None if lists.rows is None else _c(lists.rows, np.int64)
+    n_rows = lists.shell_off.shape[0] - 1
+    out = np.zeros(max(int(b_off[-1]), 1), dtype=np.uint8)
+    lib().orc_batch_accept(_p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, _p(rows, _i64p), n_rows,
+                           _p(lists.shell_off, _i64p), _p(_c(lists.shell_idx, np.int32), _i32p),
+                           _p(_c(b_off, np.int64), _i64p), _p(_c(b_rank, np.int32), _i32p), _p(out, _u8p))
+    return out
+
+
 def ktable(beta: float, box: float, max_m: int = 1 << 16):
     L = lib()
     H = ctypes.c_double()
@@ -297,6 +320,7 @@ class Result:
     weight: np.ndarray | None
     s: np.ndarray
     S: float
+    accept: np.ndarray | None = None
 
 
 def sample_kspace(params: Params, step: int):
@@ -319,9 +343,11 @@ def structure_factor(s, q, kvec, rows=None) -> np.ndarray:
 
 
 def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int = 0, mode: str = "rbl",
-            rows=None, s=None, lists: Lists | None = None, batches=None, kspace=None, rho=None) -> Result:
+            rows=None, s=None, lists: Lists | None = None, batches=None, kspace=None, rho=None,
+            accept=None) -> Result:
     """One force evaluation. ``s`` (quantized positions), ``lists``, ``batches``
-    ((off, rank, w)) and ``kspace`` ((m, W, S)) may be given to freeze them.
+    ((off, rank, w)), ``kspace`` ((m, W, S)) and, for ``stencil``, ``accept``
+    (which drawn candidates count) may be given to freeze them.
     With ``rows`` only those atoms are evaluated; ``rho`` (from
     :func:`structure_factor` over all atoms) then gives their exact long-range
     force, otherwise rho is summed over the rows only."""
@@ -336,12 +362,18 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
     rows_a = None if rows is None else _c(rows, np.int64)
     n_rows = n if rows is None else rows_a.shape[0]
     full = mode in ("full", "ewald")
+    sampled = mode in ("rbl", "stencil")
     if lists is None:
-        lists = build_lists(s, mol, params.box, params.r_core, params.r_shell, full=full, rows=rows_a)
-    if mode == "rbl":
+        lists = build_lists(s, mol, params.box, params.r_core, params.r_shell, full=full, rows=rows_a,
+                            stencil=mode == "stencil")
+    if mode != "stencil":
+        accept = None
+    if sampled:
         if batches is None:
             batches = shell_batches(params.seed, step, lists, params.p_shell)
         b_off, b_rank, w = batches
+        if mode == "stencil" and accept is None:
+            accept = batch_accept(s, mol, params.box, params.r_core, params.r_shell, lists, batches)
     else:
         b_off = b_rank = w = None
     if kspace is None:
@@ -363,8 +395,9 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
                       _p(_c(lists.core_idx, np.int32), _i32p), _p(lists.shell_off, _i64p),
                       _p(_c(lists.shell_idx, np.int32), _i32p), _p(b_off, _i64p),
                       _p(None if b_rank is None else _c(b_rank, np.int32), _i32p),
-                      _p(None if w is None else _c(w, np.float64), _f64p), _p(f_sr, _f64p), _p(e8, _f64p))
-    fcorr = f_sr.mean(axis=0) if (mode == "rbl" and n_rows > 0) else np.zeros(3)
+                      _p(None if w is None else _c(w, np.float64), _f64p), _p(accept, _u8p), _p(f_sr, _f64p),
+                      _p(e8, _f64p))
+    fcorr = f_sr.mean(axis=0) if (sampled and n_rows > 0) else np.zeros(3)
     x_off, x_idx = exclusion_lists(mol, rows_a)
     e7x = np.zeros(7)
     f_x = np.zeros((n_rows, 3))
@@ -392,7 +425,7 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
     energy[4] = e7x[0]
     energy[5:11] = e8[2:8] + e7x[1:7] + e7k[1:7]
     force = f_sr - fcorr + f_x + f_long
-    return Result(force, energy, f_sr, f_x, f_long, fcorr, rho, m, W, lists, b_off, b_rank, w, s, S)
+    return Result(force, energy, f_sr, f_x, f_long, fcorr, rho, m, W, lists, b_off, b_rank, w, s, S, accept)
 
 
 def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result, mode: str = "rbl"):
@@ -413,14 +446,15 @@ def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result
     g_q = np.zeros(n)
     g_sig = np.zeros(params.n_types ** 2)
     g_eps = np.zeros(params.n_types ** 2)
-    rbl = mode == "rbl"
+    rbl = mode in ("rbl", "stencil")
     L.orc_short_range_adjoint(ctypes.byref(sy), n, _p(s, _u32p), _p(q, _f64p), _p(atom_type, _i32p),
                               _p(lj_sigma, _f64p), _p(lj_eps, _f64p), _p(res.lists.core_off, _i64p),
                               _p(_c(res.lists.core_idx, np.int32), _i32p), _p(res.lists.shell_off, _i64p),
                               _p(_c(res.lists.shell_idx, np.int32), _i32p),
                               _p(res.batch_off if rbl else None, _i64p),
                               _p(_c(res.batch_rank, np.int32) if rbl else None, _i32p),
-                              _p(_c(res.weight, np.float64) if rbl else None, _f64p), int(rbl), _p(G, _f64p),
+                              _p(_c(res.weight, np.float64) if rbl else None, _f64p),
+                              _p(res.accept if mode == "stencil" else None, _u8p), int(rbl), _p(G, _f64p),
                               _p(g_pos, _f64p), _p(g_q, _f64p), _p(g_sig, _f64p), _p(g_eps, _f64p))
     x_off, x_idx = exclusion_lists(mol)
     L.orc_exclusions_adjoint(ctypes.byref(sy), n, _p(s, _u32p), _p(q, _f64p), _p(x_off, _i64p), _p(x_idx, _i64p),

@@ -174,6 +174,39 @@ def test_lists_match_brute_force(orc, name, nrows):
         assert np.array_equal(full.shell_idx[full.shell_off[k]:full.shell_off[k + 1]], ref_full[k][1])
 
 
+@pytest.mark.parametrize("name,nrows", [("water512", 200), ("water4k", 120)])
+def test_stencil_candidates_are_the_stencil_cells(orc, name, nrows):
+    """K(i) = every atom of the shell stencil's cells (brute force over all atoms,
+    canonical order), and it holds S(i) and C(i)."""
+    w = _water(name)
+    s = orc.quantize(w.pos, w.box)
+    rng = np.random.default_rng(2)
+    rows = np.sort(rng.choice(w.n_atoms, size=nrows, replace=False))
+    st = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2, rows=rows, stencil=True)
+    split = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2, rows=rows)
+    n_c = int(math.floor(w.box / 0.5))
+    R_ = int(math.floor(1.2 * n_c / w.box)) + 1
+    cell = ((s.astype(np.uint64) * n_c) >> np.uint64(32)).astype(np.int64)
+    for k, i in enumerate(rows):
+        off = (cell - cell[i]) % n_c
+        if 2 * R_ + 1 <= n_c:
+            off = np.where(off > R_, off - n_c, off)
+            inside = np.all(np.abs(off) <= R_, axis=1)
+        else:
+            h = (n_c - 1) // 2
+            off = (off + h) % n_c - h
+            inside = np.ones(len(s), bool)
+        js = np.flatnonzero(inside)
+        key = np.lexsort((js, s[js, 0], off[js, 0], off[js, 1], off[js, 2]))
+        ref = js[key]
+        got = st.shell_idx[st.shell_off[k]:st.shell_off[k + 1]]
+        assert np.array_equal(got, ref)
+        assert np.array_equal(st.core_idx[st.core_off[k]:st.core_off[k + 1]],
+                              split.core_idx[split.core_off[k]:split.core_off[k + 1]])
+        members = set(split.shell_idx[split.shell_off[k]:split.shell_off[k + 1]].tolist())
+        assert members <= set(got.tolist())
+
+
 def test_list_sizes_match_density(orc):
     """Mean list sizes against (4/3) pi r^3 rho (water: the paper's ~700 within 1.2 nm)."""
     w = _water("water4k")
@@ -321,6 +354,45 @@ def test_rbl_reduces_to_full_list(orc):
     assert np.allclose(rbl.energy, full.energy, rtol=1e-12, atol=1e-8)
 
 
+def test_stencil_sampling_reduces_to_full_list(orc):
+    """Stencil sampling with p~ above every candidate count takes all of K(i) with
+    weight 1; the acceptance test then keeps exactly S(i): the full-list short range."""
+    w = _water("water4k")
+    big = orc.Params(box=w.box, p_shell=100000)
+    st = orc.forward(*_args(w), big, mode="stencil")
+    full = orc.forward(*_args(w), big, mode="full")
+    assert np.all(st.weight == 1.0)
+    scale = np.abs(full.f_short).max()
+    assert np.abs(st.f_short - full.f_short).max() < 1e-12 * scale
+    assert np.allclose(st.energy[:2], full.energy[:2], rtol=1e-12)
+    # accepted entries per row = |S(i)|
+    lists = orc.build_lists(orc.quantize(w.pos, w.box), w.molecule, w.box, 0.5, 1.2)
+    acc = np.add.reduceat(st.accept.astype(np.int64), st.batch_off[:-1])
+    assert np.array_equal(acc, np.diff(lists.shell_off))
+
+
+@pytest.mark.slow
+def test_stencil_sampling_unbiased_over_seeds(orc):
+    """E[w_i sum_B f_ij 1(j in S(i))] with B drawn from K(i) and w_i = |K(i)|/p~
+    is the full shell sum: the mean short-range force over seeds matches the
+    full-list one (per-component z-scores)."""
+    w = _water("water4k")
+    s = orc.quantize(w.pos, w.box)
+    rows = np.arange(0, w.n_atoms, 97)
+    ref = orc.forward(None, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, orc.Params(box=w.box),
+                      mode="full", s=s, rows=rows)
+    lists = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2, rows=rows, stencil=True)
+    n_seed = 300
+    f = np.empty((n_seed,) + ref.f_short.shape)
+    for k in range(n_seed):
+        r = orc.forward(None, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps,
+                        orc.Params(box=w.box, seed=5000 + k), mode="stencil", s=s, rows=rows, lists=lists)
+        f[k] = r.f_short
+    z = (f.mean(axis=0) - ref.f_short) / (f.std(axis=0, ddof=1) / math.sqrt(n_seed))
+    assert abs((z ** 2).mean() - 1.0) < 0.15
+    assert np.abs(z).max() < 5.5
+
+
 def test_momentum_conservation(orc):
     w = _water()
     for mode in ("rbl", "full", "ewald"):
@@ -408,15 +480,16 @@ def test_shell_estimator_exact_variance(orc):
 # --------------------------------------------------------------------------- adjoint
 
 def _loss(orc, w, p, res, G, s=None, q=None, sig=None, eps=None, mode="rbl"):
+    sampled = mode in ("rbl", "stencil")
     r = orc.forward(None, w.charge if q is None else q, w.atom_type, w.molecule,
                     w.lj_sigma if sig is None else sig, w.lj_eps if eps is None else eps, p, mode=mode,
                     s=res.s if s is None else s, lists=res.lists,
-                    batches=(res.batch_off, res.batch_rank, res.weight) if mode == "rbl" else None,
-                    kspace=(res.kvec, res.wk, res.S))
+                    batches=(res.batch_off, res.batch_rank, res.weight) if sampled else None,
+                    kspace=(res.kvec, res.wk, res.S), accept=res.accept)
     return float((G * r.force).sum())
 
 
-@pytest.mark.parametrize("mode", ["rbl", "full"])
+@pytest.mark.parametrize("mode", ["rbl", "full", "stencil"])
 def test_adjoint_matches_central_differences(orc, mode):
     w = _water()
     p = orc.Params(box=w.box)
