@@ -76,6 +76,9 @@ typedef enum {
 
 enum { IRBE_MIXED_FP32 = 0, IRBE_FP64 = 1 };
 
+/* irbe_config.shell_source */
+enum { IRBE_SHELL_LIST = 0, IRBE_SHELL_STENCIL = 1 };
+
 /* compute_forces flags */
 enum { IRBE_ENERGY = 1u, IRBE_VIRIAL = 2u };
 
@@ -93,7 +96,15 @@ typedef struct {
     int32_t p_shell;       /* shell batch size p~ (> 0), or <= 0 for the full list   */
     int32_t p_kspace;      /* number of sampled k-vectors p (>= 1)                   */
     int32_t n_types;       /* LJ atom types, 1..16                                   */
-    int32_t reserved;      /* 0                                                      */
+    int32_t shell_source;  /* where the shell batch is drawn from (p_shell > 0 only):
+                              IRBE_SHELL_LIST: S(i), materialized by build_lists,
+                              weight N_S / p~ (Eq. (2.11)); IRBE_SHELL_STENCIL:
+                              every atom of the shell stencil's cells, K(i)
+                              (Algorithm 1 draws "from its stencils"; Sec. 2.3:
+                              the filter step may be skipped), weight |K(i)| / p~,
+                              a drawn atom counting only when it is in S(i) at
+                              the positions given to compute_forces; build_lists
+                              then builds no shell list                           */
     uint64_t seed;         /* Philox key                                             */
     double capacity_hint;  /* expected list entries per atom, 0 = from density       */
 } irbe_config;
@@ -183,8 +194,12 @@ irbe_status irbe_get_timing(irbe_handle h, double* ms_host, int64_t capacity, in
  *                                           in stencil-offset order, then cell order
  *   IRBE_DBG_SHELL_OFF   int64 [N + 1]      S(i) (or the full list), same layout
  *   IRBE_DBG_SHELL_IDX   int32 [..]
- *   IRBE_DBG_BATCH_OFF   int64 [N + 1]      batch ranks into S(i), draw order, for
- *   IRBE_DBG_BATCH_RANK  int32 [..]         the step of the last compute_forces
+ *   IRBE_DBG_BATCH_OFF   int64 [N + 1]      batch ranks into S(i) (K(i) with stencil
+ *   IRBE_DBG_BATCH_RANK  int32 [..]         sampling), draw order, for the step of
+ *                                           the last compute_forces
+ *   IRBE_DBG_BATCH_ATOMS int32 [..]         the atoms at those ranks (atom ids; -1
+ *                                           for i itself and i's molecule), per-row
+ *                                           read-back only
  *   IRBE_DBG_KVEC        int32 [3 P]        sampled m (k = 2 pi m / L)
  *   IRBE_DBG_RHO         double [2 P]       rho(k) (re, im)
  *   IRBE_DBG_FCORR       double [3]         F^corr
@@ -205,14 +220,15 @@ enum {
     IRBE_DBG_RHO = 10,
     IRBE_DBG_FCORR = 11,
     IRBE_DBG_SCALARS = 12,
-    IRBE_DBG_COUNTS = 13
+    IRBE_DBG_COUNTS = 13,
+    IRBE_DBG_BATCH_ATOMS = 14
 };
 irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written);
 
 /* The same read-back restricted to the atoms rows_host[0..n_rows) (caller ids,
  * host int64), for the per-atom selectors CORE_*, SHELL_* and BATCH_*: the
- * *_OFF selectors give n_rows + 1 offsets, the *_IDX / BATCH_RANK selectors the
- * concatenated rows. Meant for spot checks on systems too large to copy whole.
+ * *_OFF selectors give n_rows + 1 offsets, the *_IDX / BATCH_RANK / BATCH_ATOMS
+ * selectors the concatenated rows (BATCH_OFF gives the offsets of both). Meant for spot checks on systems too large to copy whole.
  * Waits. IRBE_EINVAL for an id outside [0, N). */
 irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows_host, int64_t n_rows, void* dst_host,
                                 int64_t capacity, int64_t* written);

@@ -302,6 +302,10 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     if (c.n_types < 1 || c.n_types > 16) return fail(nullptr, IRBE_EINVAL, "n_types must be in 1..16");
     if (!(c.capacity_hint >= 0.0) || !std::isfinite(c.capacity_hint))
         return fail(nullptr, IRBE_EINVAL, "bad capacity_hint");
+    if (c.shell_source != IRBE_SHELL_LIST && c.shell_source != IRBE_SHELL_STENCIL)
+        return fail(nullptr, IRBE_EINVAL, "bad shell_source");
+    if (c.shell_source == IRBE_SHELL_STENCIL && c.p_shell <= 0)
+        return fail(nullptr, IRBE_EINVAL, "stencil sampling needs p_shell > 0");
 
     irbe_ctx* h = new (std::nothrow) irbe_ctx();
     if (!h) return fail(nullptr, IRBE_ENOMEM, "host allocation failed");
@@ -310,10 +314,15 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     h->fp64 = c.precision == IRBE_FP64;
     h->real_size = h->fp64 ? 8 : 4;
     h->full_list = c.p_shell <= 0;
+    h->stencil = c.shell_source == IRBE_SHELL_STENCIL;
     geometry(c, h->geo);
     if (h->geo.n_c < 3) {
         delete h;
         return fail(nullptr, IRBE_EINVAL, "floor(L / r_core) must be >= 3");
+    }
+    if (h->stencil && (h->geo.hi - h->geo.lo + 1) * (h->geo.hi - h->geo.lo + 1) > 128) {
+        delete h;
+        return fail(nullptr, IRBE_EUNSUPPORTED, "stencil sampling supports at most 128 stencil rows");
     }
     if (h->geo.n_cells > kMaxCells || h->geo.n_c > 1000) {
         delete h;
@@ -375,6 +384,8 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc(h, &h->ncore, n));
     h->p_stride = c.p_shell > 0 ? (c.p_shell + 3) / 4 * 4 : 0;
     if (h->p_stride > 0) ALLOC(dalloc(h, &h->ranks, n * (size_t)h->p_stride));
+    if (h->stencil) ALLOC(dalloc(h, &h->batch_j, n * (size_t)h->p_stride));
+    if (h->stencil) ALLOC(dalloc(h, &h->scell, n));
     ALLOC(dalloc(h, &h->nshell, n));
     ALLOC(dalloc_bytes(h, &h->fsr, 3 * n * rs));
     ALLOC(dalloc(h, &h->pair_part, (size_t)nb64 * kPairPartials));
@@ -408,6 +419,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
         int32_t cap_s = round_up32(1.3 * rho_n * (h->full_list ? vs : vs - vc) + 32.0);
         if (c.capacity_hint > 0.0) cap_s = round_up32(c.capacity_hint);
         if (h->full_list) cap_c = 1;
+        if (h->stencil) cap_s = 1;  // no shell list
         cap_c = (int32_t)std::min<int64_t>(cap_c, c.n_atoms + 32);
         cap_s = (int32_t)std::min<int64_t>(cap_s, c.n_atoms + 32);
         e = alloc_lists(h, cap_c, cap_s);
@@ -541,14 +553,16 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
         IRBE_TRY(h, hipMemcpyAsync(mx, h->maxcnt, sizeof(mx), hipMemcpyDeviceToHost, h->stream), "read list sizes");
         const irbe_status st = check_device_error(h);
         if (st != IRBE_OK) return st;
-        if (mx[0] <= h->cap_core && mx[1] <= h->cap_shell) {
+        if (h->stencil && mx[1] > 65535)
+            return fail(h, IRBE_EUNSUPPORTED, "more than 65535 atoms in a shell stencil");
+        if (mx[0] <= h->cap_core && (h->stencil || mx[1] <= h->cap_shell)) {
             h->max_core = mx[0];
             h->max_shell = mx[1];
             h->have_lists = true;
             return IRBE_OK;
         }
         const int32_t nc = std::max(h->cap_core, round_up32(1.15 * mx[0] + 32.0));
-        const int32_t ns = std::max(h->cap_shell, round_up32(1.15 * mx[1] + 32.0));
+        const int32_t ns = h->stencil ? h->cap_shell : std::max(h->cap_shell, round_up32(1.15 * mx[1] + 32.0));
         if (ns > 65535) return fail(h, IRBE_ECAPACITY, "more than 65535 list entries per atom");
         IRBE_TRY(h, alloc_lists(h, nc, ns), "grow lists");
     }
@@ -644,6 +658,8 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
     case IRBE_DBG_SHELL_IDX:
     case IRBE_DBG_BATCH_OFF:
     case IRBE_DBG_BATCH_RANK: {
+        if (h->stencil && (what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_SHELL_IDX))
+            return fail(h, IRBE_ESTATE, "no shell list with stencil sampling");
         const bool is_core = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_CORE_IDX;
         const bool is_batch = what == IRBE_DBG_BATCH_OFF || what == IRBE_DBG_BATCH_RANK;
         const bool want_off = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_BATCH_OFF;
@@ -744,8 +760,10 @@ irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows
         return fail(h, IRBE_EINVAL, "bad debug buffer");
     const bool is_core = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_CORE_IDX;
     const bool is_shell = what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_SHELL_IDX;
-    const bool is_batch = what == IRBE_DBG_BATCH_OFF || what == IRBE_DBG_BATCH_RANK;
+    const bool is_atoms = what == IRBE_DBG_BATCH_ATOMS;
+    const bool is_batch = what == IRBE_DBG_BATCH_OFF || what == IRBE_DBG_BATCH_RANK || is_atoms;
     if (!is_core && !is_shell && !is_batch) return fail(h, IRBE_EINVAL, "selector is not per atom");
+    if (is_shell && h->stencil) return fail(h, IRBE_ESTATE, "no shell list with stencil sampling");
     if (!h->have_lists) return fail(h, IRBE_ESTATE, "no lists built");
     if (is_batch && !h->full_list && !(h->have_force_step && h->ranks_valid && h->ranks_step == h->last_force_step))
         return fail(h, IRBE_ESTATE, "batch ranks of the last force step are not available");
@@ -755,7 +773,7 @@ irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows
     IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
     const bool want_off = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_BATCH_OFF;
     std::vector<int32_t> perm;
-    if (!want_off && !is_batch) {
+    if (!want_off && (!is_batch || is_atoms)) {
         perm.resize((size_t)n);
         IRBE_TRY(h, hipMemcpy(perm.data(), h->perm, (size_t)n * 4, hipMemcpyDeviceToHost), "debug");
     }
@@ -770,15 +788,33 @@ irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows
         if (is_batch && !h->full_list) len = std::min<int64_t>(cnt, h->cfg.p_shell);
         off[r + 1] = off[r] + len;
         if (want_off || len == 0) continue;
-        if (is_batch) {
+        if (is_atoms && h->stencil) {
+            // the decoded atoms of the batch (sorted index, -1 for i and its molecule)
+            std::vector<int32_t> bj((size_t)len);
+            IRBE_TRY(h, hipMemcpy(bj.data(), h->batch_j + (int64_t)k * h->p_stride, (size_t)len * 4,
+                                  hipMemcpyDeviceToHost),
+                     "debug");
+            for (auto v : bj) idx.push_back(v < 0 ? -1 : perm[v]);
+        } else if (is_batch) {
+            std::vector<int32_t> rv;
             if (sampled) {
                 std::vector<uint16_t> rk((size_t)len);
                 IRBE_TRY(h, hipMemcpy(rk.data(), h->ranks + (int64_t)k * h->p_stride, (size_t)len * 2,
                                       hipMemcpyDeviceToHost),
                          "debug");
-                for (auto v : rk) idx.push_back((int32_t)v);
+                for (auto v : rk) rv.push_back((int32_t)v);
             } else {
-                for (int64_t t = 0; t < len; ++t) idx.push_back((int32_t)t);
+                for (int64_t t = 0; t < len; ++t) rv.push_back((int32_t)t);
+            }
+            if (is_atoms) {
+                // list sampling: the shell members at the ranks
+                std::vector<int32_t> row((size_t)cnt);
+                IRBE_TRY(h, hipMemcpy(row.data(), h->shell + (int64_t)k * h->cap_shell, (size_t)cnt * 4,
+                                      hipMemcpyDeviceToHost),
+                         "debug");
+                for (auto v : rv) idx.push_back(perm[row[v]]);
+            } else {
+                for (auto v : rv) idx.push_back(v);
             }
         } else {
             std::vector<int32_t> row((size_t)len);

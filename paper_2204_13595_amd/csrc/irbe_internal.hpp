@@ -71,6 +71,7 @@ struct irbe_ctx {
     int device = 0;
     bool fp64 = false;
     bool full_list = false;
+    bool stencil = false;             // shell batch drawn from the stencil's cells (no shell list)
     size_t real_size = 4;
     irbe::Geometry geo;
     std::string last_error;
@@ -154,6 +155,8 @@ struct irbe_ctx {
     uint16_t* bk_j = nullptr;         // [bk_total] record's atom, relative to its row's first atom
     int64_t bk_total = 0;             // allocated records
     uint16_t* ranks = nullptr;        // [N * p_stride] shell batch ranks of the current step
+    int32_t* batch_j = nullptr;       // [N * p_stride] stencil sampling: the drawn atoms (sorted index, -1: i or i's molecule)
+    int32_t* scell = nullptr;         // [N] stencil sampling: cell of each sorted atom at the last build
     int32_t p_stride = 0;
     bool ranks_valid = false;         // ranks hold the draw of ranks_step for the current lists
     uint64_t ranks_step = 0;

@@ -104,7 +104,11 @@ __device__ __forceinline__ int member_pos(uint32_t mlo, uint32_t mhi, uint32_t l
     return (int)__builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo & lowm, (uint32_t)base));
 }
 
-template <bool FULL>
+// MODE: split core and shell lists, one full list, or the core list alone (the
+// shell batch of stencil sampling is drawn from the stencil's cells).
+enum { kListsSplit = 0, kListsFull = 1, kListsCoreOnly = 2 };
+
+template <int MODE>
 __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     int n_c, int lo, int hi, int G, int prune, int trim, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb, uint64_t t_core,
     uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const int32_t* __restrict__ smol,
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                 const int row = (z * n_c + y) * n_c;
                 // rows two or more cells away in y or z hold no core candidate:
                 // a whole cell edge (>= r_core) lies between them and the atom
-                const bool core_row = !FULL && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
+                const bool core_row = MODE != kListsFull && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
                 // lane's candidate cells in this row: tile cells [u_lo, u_hi]
                 int u_lo = ti, u_hi = ti + span_c - 1;
                 bool need = act;
@@ -274,7 +278,14 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                     const uint64_t m_keep = ballot(k_in) & ballot(k_mol);
                                     bool in_core = false, in_shell;
                                     uint64_t m_core = 0, m_shell, m_amb;
-                                    if (CORE) {
+                                    if (CORE && MODE == kListsCoreOnly) {
+                                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
+                                        in_core = k_in & k_mol & c_in;
+                                        in_shell = false;
+                                        m_core = m_keep & ballot(c_in);
+                                        m_shell = 0;
+                                        m_amb = m_keep & ~ballot(c_out) & ~m_core;
+                                    } else if (CORE) {
                                         const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
                                         const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
                                         in_core = k_in & k_mol & c_in;
@@ -294,21 +305,21 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                         const bool amb = (m_amb >> lane) & 1u;
                                         const uint64_t d2x = dist2_exact(spos[chunk + ka], spos[amb ? (int)r.w : chunk + ka]);
                                         const bool xc = CORE && d2x <= t_core;
-                                        const bool xs = !xc && d2x <= t_shell;
+                                        const bool xs = MODE != kListsCoreOnly && !xc && d2x <= t_shell;
                                         in_core = amb ? xc : in_core;
                                         in_shell = amb ? xs : in_shell;
                                         m_core = (m_core & ~m_amb) | (ballot(xc) & m_amb);
                                         m_shell = (m_shell & ~m_amb) | (ballot(xs) & m_amb);
                                     }
-                                    const uint32_t ms_lo = (uint32_t)m_shell, ms_hi = (uint32_t)(m_shell >> 32);
-                                    const int ps_lo = __popc(ms_lo);
-                                    {
+                                    if (MODE != kListsCoreOnly) {
+                                        const uint32_t ms_lo = (uint32_t)m_shell, ms_hi = (uint32_t)(m_shell >> 32);
+                                        const int ps_lo = __popc(ms_lo);
                                         // non-members store past the descriptor's range (dropped)
                                         const int pos = member_pos(ms_lo, ms_hi, lowm, cs);
                                         const int off = in_shell ? hoff_s + (pos << 2) : kNoStore;
                                         __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_s, off, 0, 0);
+                                        cs += ps_lo + (hsel & (__popc(ms_hi) - ps_lo));
                                     }
-                                    cs += ps_lo + (hsel & (__popc(ms_hi) - ps_lo));
                                     if (CORE) {
                                         const uint32_t mc_lo = (uint32_t)m_core, mc_hi = (uint32_t)(m_core >> 32);
                                         const int pc_lo = __popc(mc_lo);
@@ -333,7 +344,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
         if (act) {
             const int2 c = acnt[lane];
             ncore[k] = c.x;
-            nshell[k] = c.y;
+            if (MODE != kListsCoreOnly) nshell[k] = c.y;
             maxc = max(maxc, c.x);
             maxs = max(maxs, c.y);
         }
@@ -349,6 +360,42 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
         atomicMax(&maxcnt[0], maxc);
         atomicMax(&maxcnt[1], maxs);
     }
+}
+
+// Stencil sampling: |K(i)|, the number of atoms in the shell stencil's cells
+// around atom i's cell (span^2 rows of span cells, each row at most two index
+// ranges of the cell-sorted atoms), written as the shell count of every atom
+// of the cell together with the cell itself (the build-time cell, which the
+// batch decode uses even after the atoms have moved); one thread per cell, and
+// the largest count raises maxcnt[1].
+__global__ __launch_bounds__(kBlock) void k_stencil_counts(int n_c, int lo, int span,
+                                                           const int32_t* __restrict__ cell_start,
+                                                           int32_t* __restrict__ nshell, int32_t* __restrict__ scell,
+                                                           int32_t* __restrict__ maxcnt)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cells = (int64_t)n_c * n_c * n_c;
+    int m = 0;
+    if (c < cells) {
+        const int cx = (int)(c % n_c), cy = (int)((c / n_c) % n_c), cz = (int)(c / ((int64_t)n_c * n_c));
+        const int x0 = wrap(cx + lo, n_c);
+        const int la = min(span, n_c - x0);  // cells before the wrap
+        for (int dz = 0; dz < span; ++dz) {
+            const int z = wrap(cz + lo + dz, n_c);
+            for (int dy = 0; dy < span; ++dy) {
+                const int row = (z * n_c + wrap(cy + lo + dy, n_c)) * n_c;
+                m += cell_start[row + x0 + la] - cell_start[row + x0];
+                if (span > la) m += cell_start[row + span - la] - cell_start[row];
+            }
+        }
+        for (int k = cell_start[c]; k < cell_start[c + 1]; ++k) {
+            nshell[k] = m;
+            scell[k] = (int32_t)c;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(&maxcnt[1], m);
 }
 
 namespace {
@@ -410,7 +457,13 @@ PackedGeometry packed_geometry(const Geometry& g, int G, bool prune)
 
 hipError_t launch_build_lists(irbe_ctx* h)
 {
-    const Geometry& g = h->geo;
+    Geometry g = h->geo;
+    if (h->stencil) {
+        // core list only: the core stencil, and rows pruned by the core radius
+        g.reach = 1;
+        g.lo = -1;
+        g.hi = 1;
+    }
     const int n_c = g.n_c;
     const bool narrow = 2 * g.reach + 1 <= n_c;
     const int G = narrow ? std::min(4, n_c - 2 * g.reach) : 1;
@@ -419,17 +472,26 @@ hipError_t launch_build_lists(irbe_ctx* h)
     const PackedGeometry pg = packed_geometry(g, G, narrow);
     // packed x is monotone along a cell only when no relative coordinate wraps
     const int trim = narrow && pg.sh < 16 ? 1 : 0;
-    // FP32 shell threshold with a relative margin of 2e-6, far above the FP32
-    // rounding of the row gaps: the row pruning never drops a member.
-    const float tfs_hi = (float)g.t_shell * 1.000002f;
+    // FP32 threshold of the outermost list with a relative margin of 2e-6, far
+    // above the FP32 rounding of the row gaps: the row pruning never drops a member.
+    const float tf_hi = (float)(h->stencil ? g.t_core : g.t_shell) * 1.000002f;
+#define IRBE_LISTS_ARGS                                                                                           \
+    n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.t_core, g.t_shell, tf_hi, h->spos, h->smol,   \
+        h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt
     if (h->full_list)
-        k_build_lists_tiled<true><<<(unsigned)groups, kListWave, 0, h->stream>>>(
-            n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.t_core, g.t_shell, tfs_hi, h->spos, h->smol,
-            h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt);
+        k_build_lists_tiled<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+    else if (h->stencil)
+        k_build_lists_tiled<kListsCoreOnly><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
     else
-        k_build_lists_tiled<false><<<(unsigned)groups, kListWave, 0, h->stream>>>(
-            n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.t_core, g.t_shell, tfs_hi, h->spos, h->smol,
-            h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt);
+        k_build_lists_tiled<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+#undef IRBE_LISTS_ARGS
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !h->stencil) return e;
+    // stencil sampling: |K(i)| (the atoms of the shell stencil's cells) as the shell count
+    const Geometry& gs = h->geo;
+    const int64_t cells = gs.n_cells;
+    k_stencil_counts<<<(unsigned)blocks_for(cells, kBlock), kBlock, 0, h->stream>>>(
+        gs.n_c, gs.lo, gs.hi - gs.lo + 1, h->cell_start, h->nshell, h->scell, h->maxcnt);
     return hipGetLastError();
 }
 

@@ -7,6 +7,11 @@
 // i), w_i = N_S / p_shell (all members and w_i = 1 when N_S <= p_shell). The
 // per-block FP64 sums of the uncorrected short-range force give F^corr.
 // Full-list mode: one list of every pair within r_shell, weight 1.
+// Stencil sampling (STENCIL): the ranks are drawn from K(i), the atoms of the
+// shell stencil's cells (N_S replaced by |K(i)|), turned into atom indices by
+// k_stencil_decode, and a drawn atom contributes only when it lies in the
+// shell annulus T_c < D^2 <= T_s at the current positions (i itself and i's
+// molecule come out of the decode as -1).
 #include <algorithm>
 
 #include "irbe_device.hpp"
@@ -21,6 +26,18 @@ struct PairParams {
     real cgauss;    // 2 beta / sqrt(pi)
     real ke;
 };
+
+// The shell-membership test of stencil sampling on exact squared separations
+// in quanta (O1/O5: T_c < D^2 <= T_s).
+__device__ __forceinline__ bool in_annulus(uint4 a, uint4 b, uint64_t t_lo, uint64_t t_hi)
+{
+    const int32_t dx = (int32_t)(b.x - a.x);
+    const int32_t dy = (int32_t)(b.y - a.y);
+    const int32_t dz = (int32_t)(b.z - a.z);
+    const uint64_t d2 =
+        (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
+    return d2 > t_lo && d2 <= t_hi;
+}
 
 template <typename real>
 __device__ __forceinline__ void separation(uint4 a, uint4 b, real quantum, real& dx, real& dy, real& dz)
@@ -141,6 +158,92 @@ __global__ __launch_bounds__(BLOCK) void k_draw_batches(int64_t n, const int32_t
     for (; c < p_shell; ++c) out[c] = (uint16_t)floyd_step<BLOCK>(st, bitmap, t0 + c);
 }
 
+// Stencil sampling: the ranks into K(i) (or 0 .. |K(i)|-1 when all are taken)
+// turned into sorted atom indices. K(i) runs over the stencil rows (dz, dy) in
+// order, each row being the cells cx + lo .. cx + lo + span - 1 (cyclic) around
+// the atom's cell at the build, i.e. at most two index ranges. One wavefront per apw consecutive atoms: the row
+// offsets of the current cell sit in the wavefront's LDS slice (rebuilt when
+// the cell changes: one row per lane and a wave prefix sum), and each lane
+// binary-searches its ranks. i itself and i's molecule give -1.
+constexpr int kDecodeBlock = 256;
+constexpr int kDecodeRows = 128;  // stencil rows (span^2) supported
+
+__device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+__global__ __launch_bounds__(kDecodeBlock) void k_stencil_decode(
+    int64_t n, int apw, int n_c, int lo, int span, const int32_t* __restrict__ cell_start,
+    const int32_t* __restrict__ scell, const int32_t* __restrict__ smol, const int32_t* __restrict__ nshell,
+    int p_shell, int p_stride, const uint16_t* __restrict__ ranks, int32_t* __restrict__ batch_j)
+{
+    constexpr int NW = kDecodeBlock / 64;
+    __shared__ int32_t t_pre[NW][kDecodeRows];   // first rank of each row
+    __shared__ int32_t t_a[NW][kDecodeRows];     // first atom of the row's first range
+    __shared__ int32_t t_la[NW][kDecodeRows];    // length of the first range
+    __shared__ int32_t t_b[NW][kDecodeRows];     // first atom of the second range (after the wrap)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t a0 = ((int64_t)blockIdx.x * NW + wave) * apw;
+    const int64_t a1 = min(n, a0 + apw);
+    const int nrows = span * span;
+    int cur = -1;
+    for (int64_t a = a0; a < a1; ++a) {
+        const int cell = scell[a];  // the cell of the build (positions may have moved since)
+        const int cx = cell % n_c, cy = (cell / n_c) % n_c, cz = cell / (n_c * n_c);
+        if (cell != cur) {
+            cur = cell;
+            const int x0 = wrap_cell(cx + lo, n_c);
+            const int la_c = min(span, n_c - x0);  // cells before the wrap
+            int base = 0;
+            for (int t0 = 0; t0 < nrows; t0 += 64) {
+                const int t = t0 + lane;
+                int len = 0, va = 0, vla = 0, vb = 0;
+                if (t < nrows) {
+                    const int z = wrap_cell(cz + t / span + lo, n_c);
+                    const int y = wrap_cell(cy + t % span + lo, n_c);
+                    const int row = (z * n_c + y) * n_c;
+                    va = cell_start[row + x0];
+                    vla = cell_start[row + x0 + la_c] - va;
+                    vb = cell_start[row];
+                    len = vla + (span > la_c ? cell_start[row + span - la_c] - vb : 0);
+                }
+                int incl = len;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int v = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl += v;
+                }
+                if (t < nrows) {
+                    t_pre[wave][t] = base + incl - len;
+                    t_a[wave][t] = va;
+                    t_la[wave][t] = vla;
+                    t_b[wave][t] = vb;
+                }
+                base += __shfl(incl, 63, 64);
+            }
+        }
+        const int m = nshell[a];
+        const bool sample = m > p_shell;
+        const int cnt = sample ? p_shell : m;
+        const int mi = smol[a];
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        int32_t* out = batch_j + a * (int64_t)p_stride;
+        for (int c = lane; c < cnt; c += 64) {
+            const int r = sample ? (int)rrow[c] : c;
+            // the row holding rank r: the last row whose first rank is <= r
+            int lo_k = 0, hi_k = nrows - 1;
+            while (lo_k < hi_k) {
+                const int mid = (lo_k + hi_k + 1) >> 1;
+                if (t_pre[wave][mid] <= r) lo_k = mid;
+                else hi_k = mid - 1;
+            }
+            const int o = r - t_pre[wave][lo_k];
+            const int la = t_la[wave][lo_k];
+            int j = o < la ? t_a[wave][lo_k] + o : t_b[wave][lo_k] + (o - la);
+            if (j == (int)a || (mi >= 0 && smol[j] == mi)) j = -1;
+            out[c] = j;
+        }
+    }
+}
+
 template <typename real>
 __device__ __forceinline__ real wave_sum_r(real v)
 {
@@ -203,13 +306,14 @@ __device__ __forceinline__ void add_excl(PairSum<real>& px, uint4 si, real qi, u
     }
 }
 
-template <typename real, bool FULL, bool EV>
+template <typename real, bool FULL, bool EV, bool STENCIL>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
-    int p_stride, const uint16_t* __restrict__ ranks, real* __restrict__ fsr, double* __restrict__ part)
+    int p_stride, const uint16_t* __restrict__ ranks, const int32_t* __restrict__ batch_j, uint64_t t_core,
+    uint64_t t_shell, real* __restrict__ fsr, double* __restrict__ part)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -248,8 +352,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
                            : (lane < nc + xr.y ? sxidx[xr.x + lane - nc] : -1);
         else
             jc = lane < nc ? core[a * (int64_t)cap_core + lane] : -1;
-        r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
-        r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+        if (STENCIL) {
+            // the decoded batch: atom indices (or -1) in place of ranks
+            const int32_t* brow = batch_j + a * (int64_t)p_stride;
+            r0 = lane < cnt ? brow[lane] : -1;
+            r1 = lane + 64 < cnt ? brow[lane + 64] : -1;
+        } else {
+            r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
+            r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+        }
         jx = (!kFold && lane < xr.y) ? sxidx[xr.x + lane] : -1;
     };
     int n_jc = -1, n_r0 = -1, n_r1 = -1, n_jx = -1;
@@ -273,8 +384,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const int cnt = sample ? p_shell : ns;
         const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
         PairSum<real> pc, ps, px;
-        const int js0 = r0 >= 0 ? srow[r0] : -1;
-        const int js1 = r1 >= 0 ? srow[r1] : -1;
+        const int js0 = STENCIL ? r0 : (r0 >= 0 ? srow[r0] : -1);
+        const int js1 = STENCIL ? r1 : (r1 >= 0 ? srow[r1] : -1);
         // (unused slots load atom 0, so that every position is one 16-byte load)
         const uint4 pjc = spos[max(jc, 0)];
         const real qjc = sqr[max(jc, 0)];
@@ -290,8 +401,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
             if (jc >= 0) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
             if (jx >= 0) add_excl<real, EV>(px, si, qi, pjx, qjx, pp);
         }
-        if (js0 >= 0) add_pair<real, EV>(ps, si, qi, pj0, qj0, lrow, pp);
-        if (js1 >= 0) add_pair<real, EV>(ps, si, qi, pj1, qj1, lrow, pp);
+        if (js0 >= 0 && (!STENCIL || in_annulus(si, pj0, t_core, t_shell)))
+            add_pair<real, EV>(ps, si, qi, pj0, qj0, lrow, pp);
+        if (js1 >= 0 && (!STENCIL || in_annulus(si, pj1, t_core, t_shell)))
+            add_pair<real, EV>(ps, si, qi, pj1, qj1, lrow, pp);
         // the rest (long lists and large batches)
         if (kFold) {
             for (int c = lane + 64; c < nc + xr.y; c += 64) {
@@ -309,8 +422,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
             }
         }
         for (int c = lane + 128; c < cnt; c += 64) {
-            const int j = srow[sample ? (int)rrow[c] : c];
-            add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
+            if (STENCIL) {
+                const int j = batch_j[a * (int64_t)p_stride + c];
+                if (j < 0) continue;
+                const uint4 sj = spos[j];
+                if (in_annulus(si, sj, t_core, t_shell)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
+            } else {
+                const int j = srow[sample ? (int)rrow[c] : c];
+                add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
+            }
         }
         // one set of sums: the excluded-pair forces cancel pairwise, so the momentum
         // correction may sum them with the rest
@@ -371,7 +491,18 @@ static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
     else
         k_draw_batches<64><<<nb, 64, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
                                                        h->cfg.seed, step, h->ranks);
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && h->stencil) {
+        const Geometry& g = h->geo;
+        const int span = g.hi - g.lo + 1;
+        if (span * span > kDecodeRows) return hipErrorInvalidValue;
+        const int apw = 16;
+        const int64_t waves = blocks_for(n, apw);
+        k_stencil_decode<<<(unsigned)blocks_for(waves, kDecodeBlock / 64), kDecodeBlock, 0, h->stream>>>(
+            n, apw, g.n_c, g.lo, span, h->cell_start, h->scell, h->smol, h->nshell, h->cfg.p_shell, h->p_stride,
+            h->ranks, h->batch_j);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         h->ranks_valid = true;
         h->ranks_step = step;
@@ -379,7 +510,7 @@ static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
     return e;
 }
 
-template <typename real, bool FULL, bool EV>
+template <typename real, bool FULL, bool EV, bool STENCIL>
 static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
 {
     const int64_t n = h->cfg.n_atoms;
@@ -393,10 +524,10 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     const int64_t waves = blocks_for(n, kAtomsPerWave);
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
-    k_pair_coop<real, FULL, EV><<<nb, kCoopBlock, 0, h->stream>>>(
+    k_pair_coop<real, FULL, EV, STENCIL><<<nb, kCoopBlock, 0, h->stream>>>(
         n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
-        h->ranks, (real*)h->fsr, h->pair_part);
+        h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
     return hipGetLastError();
 }
@@ -404,8 +535,11 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
 template <typename real>
 static hipError_t launch_coop_r(irbe_ctx* h, uint64_t step, bool ev)
 {
-    if (h->full_list) return ev ? launch_coop_t<real, true, true>(h, step) : launch_coop_t<real, true, false>(h, step);
-    return ev ? launch_coop_t<real, false, true>(h, step) : launch_coop_t<real, false, false>(h, step);
+    if (h->full_list)
+        return ev ? launch_coop_t<real, true, true, false>(h, step) : launch_coop_t<real, true, false, false>(h, step);
+    if (h->stencil)
+        return ev ? launch_coop_t<real, false, true, true>(h, step) : launch_coop_t<real, false, false, true>(h, step);
+    return ev ? launch_coop_t<real, false, true, false>(h, step) : launch_coop_t<real, false, false, false>(h, step);
 }
 
 // Reduce the per-block partials in a fixed order, in two stages: stage 1 sums
@@ -610,14 +744,14 @@ __device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_
 // One wavefront per atom (cell order), lanes over the atom's lists. BK: the
 // shell scatter goes through the LDS-staged buckets (dynamic LDS: rec_cap
 // records of 4 reals + j + key, then 7 ints per key).
-template <typename real, bool FULL, bool WANT_LJ, bool BK>
+template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const real* __restrict__ ljraw_g, int n_types, int p_shell,
-    int p_stride,
-    const uint16_t* __restrict__ ranks, const real* __restrict__ gs, const double* __restrict__ gmean_d,
+    int p_stride, const uint16_t* __restrict__ ranks, const int32_t* __restrict__ batch_j, uint64_t t_core,
+    uint64_t t_shell, const real* __restrict__ gs, const double* __restrict__ gmean_d,
     real* __restrict__ gself, real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat,
     double* __restrict__ ljpart, BucketArgs bk, int rec_cap)
 {
@@ -681,8 +815,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const int32_t* srow_sym = FULL ? shell + a * (int64_t)cap_shell : core + a * (int64_t)cap_core;
         // the excluded partners follow the symmetric list (entries nsym .. nsym + nx - 1)
         jc = lane < nsym ? srow_sym[lane] : (lane < nsym + xr.y ? sxidx[xr.x + lane - nsym] : -1);
-        r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
-        r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+        if (STENCIL) {
+            // the decoded batch: atom indices (or -1) in place of ranks
+            const int32_t* brow = batch_j + a * (int64_t)p_stride;
+            r0 = lane < cnt ? brow[lane] : -1;
+            r1 = lane + 64 < cnt ? brow[lane + 64] : -1;
+        } else {
+            r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
+            r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+        }
         jx = -1;
     };
     int n_jc = -1, n_r0 = -1, n_r1 = -1, n_jx = -1;
@@ -800,8 +941,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         };
         // first pass, every load of the dependent levels issued together (unused
         // slots load atom 0)
-        const int js0 = (!FULL && r0 >= 0) ? srow[r0] : -1;
-        const int js1 = (!FULL && r1 >= 0) ? srow[r1] : -1;
+        const int js0 = STENCIL ? r0 : ((!FULL && r0 >= 0) ? srow[r0] : -1);
+        const int js1 = STENCIL ? r1 : ((!FULL && r1 >= 0) ? srow[r1] : -1);
         const int ic = max(jc, 0), i0 = max(js0, 0), i1 = max(js1, 0), ix = max(jx, 0);
         const uint4 pjc = spos[ic];
         const real qjc = sqr[ic];
@@ -813,8 +954,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         (void)jx;
         (void)ix;
         if (jc >= 0) sym_pair(pjc, qjc, gcx, gcy, gcz, lane >= nsym);
-        if (js0 >= 0) shell_pair(js0, pj0, qj0);
-        if (js1 >= 0) shell_pair(js1, pj1, qj1);
+        if (js0 >= 0 && (!STENCIL || in_annulus(si, pj0, t_core, t_shell))) shell_pair(js0, pj0, qj0);
+        if (js1 >= 0 && (!STENCIL || in_annulus(si, pj1, t_core, t_shell))) shell_pair(js1, pj1, qj1);
         // the rest (long lists and large batches)
         for (int c = lane + 64; c < nsym + xr.y; c += 64) {
             const int j = c < nsym ? srow_sym[c] : sxidx[xr.x + c - nsym];
@@ -822,8 +963,15 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         }
         if (!FULL)
             for (int c = lane + 128; c < cnt; c += 64) {
-                const int j = srow[sample ? (int)rrow[c] : c];
-                shell_pair(j, spos[j], sqr[j]);
+                if (STENCIL) {
+                    const int j = batch_j[a * (int64_t)p_stride + c];
+                    if (j < 0) continue;
+                    const uint4 sj = spos[j];
+                    if (in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, sqr[j]);
+                } else {
+                    const int j = srow[sample ? (int)rrow[c] : c];
+                    shell_pair(j, spos[j], sqr[j]);
+                }
             }
         rx = wave_sum_r(rx);
         ry = wave_sum_r(ry);
@@ -990,7 +1138,7 @@ __global__ __launch_bounds__(512) void k_bucket_reduce(BucketArgs bk, real* __re
     }
 }
 
-template <typename real, bool FULL, bool WANT_LJ, bool BK>
+template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL>
 static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const BucketArgs& bk, int rec_cap, size_t lds)
 {
     const int64_t n = h->cfg.n_atoms;
@@ -1005,10 +1153,10 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     h->adj_nb = nb;
-    k_pair_adjoint<real, FULL, WANT_LJ, BK><<<nb, kCoopBlock, lds, h->stream>>>(
+    k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL><<<nb, kCoopBlock, lds, h->stream>>>(
         n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
-        h->p_stride, h->ranks, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
+        h->p_stride, h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
         (real*)h->gqscat, h->ljpart, bk, rec_cap);
     e = hipGetLastError();
     if (e != hipSuccess || !BK) return e;
@@ -1022,10 +1170,13 @@ static hipError_t launch_adj_r(irbe_ctx* h, uint64_t step, bool want_lj, int apw
                                size_t lds)
 {
     if (h->full_list)
-        return want_lj ? launch_adj_t<real, true, true, false>(h, step, apw, bk, 0, 0)
-                       : launch_adj_t<real, true, false, false>(h, step, apw, bk, 0, 0);
-    return want_lj ? launch_adj_t<real, false, true, BK>(h, step, apw, bk, rec_cap, lds)
-                   : launch_adj_t<real, false, false, BK>(h, step, apw, bk, rec_cap, lds);
+        return want_lj ? launch_adj_t<real, true, true, false, false>(h, step, apw, bk, 0, 0)
+                       : launch_adj_t<real, true, false, false, false>(h, step, apw, bk, 0, 0);
+    if (h->stencil)
+        return want_lj ? launch_adj_t<real, false, true, BK, true>(h, step, apw, bk, rec_cap, lds)
+                       : launch_adj_t<real, false, false, BK, true>(h, step, apw, bk, rec_cap, lds);
+    return want_lj ? launch_adj_t<real, false, true, BK, false>(h, step, apw, bk, rec_cap, lds)
+                   : launch_adj_t<real, false, false, BK, false>(h, step, apw, bk, rec_cap, lds);
 }
 
 hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool want_lj)
