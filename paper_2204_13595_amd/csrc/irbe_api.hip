@@ -102,6 +102,12 @@ hipError_t ensure_buckets(irbe_ctx* h, int64_t records)
     return e;
 }
 
+hipError_t ensure_batch_atoms(irbe_ctx* h)
+{
+    if (h->batch_j) return hipSuccess;
+    return dalloc(h, &h->batch_j, (size_t)h->cfg.n_atoms * (size_t)h->p_stride);
+}
+
 }  // namespace irbe
 
 namespace {
@@ -384,7 +390,6 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc(h, &h->ncore, n));
     h->p_stride = c.p_shell > 0 ? (c.p_shell + 3) / 4 * 4 : 0;
     if (h->p_stride > 0) ALLOC(dalloc(h, &h->ranks, n * (size_t)h->p_stride));
-    if (h->stencil) ALLOC(dalloc(h, &h->batch_j, n * (size_t)h->p_stride));
     if (h->stencil) ALLOC(dalloc(h, &h->scell, n));
     ALLOC(dalloc(h, &h->nshell, n));
     ALLOC(dalloc_bytes(h, &h->fsr, 3 * n * rs));
@@ -545,6 +550,7 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
     if (!h->have_system) return fail(h, IRBE_ESTATE, "irbe_build_lists before irbe_set_system");
     h->have_lists = false;
     h->ranks_valid = false;
+    h->batch_j_valid = false;
     IRBE_STAGE(h, IRBE_STAGE_BIN, launch_bin(h, pos), "binning");
     for (int attempt = 0; attempt < 3; ++attempt) {
         IRBE_TRY(h, launch_fill_i32(h->stream, h->maxcnt, 0, 2), "list build");
@@ -770,6 +776,7 @@ irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows
     const int64_t n = h->cfg.n_atoms;
     for (int64_t r = 0; r < n_rows; ++r)
         if (rows_host[r] < 0 || rows_host[r] >= n) return fail(h, IRBE_EINVAL, "row id out of range");
+    if (is_atoms && h->stencil) IRBE_TRY(h, launch_stencil_decode(h), "decode the batch");
     IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
     const bool want_off = what == IRBE_DBG_CORE_OFF || what == IRBE_DBG_SHELL_OFF || what == IRBE_DBG_BATCH_OFF;
     std::vector<int32_t> perm;

@@ -155,7 +155,9 @@ struct irbe_ctx {
     uint16_t* bk_j = nullptr;         // [bk_total] record's atom, relative to its row's first atom
     int64_t bk_total = 0;             // allocated records
     uint16_t* ranks = nullptr;        // [N * p_stride] shell batch ranks of the current step
-    int32_t* batch_j = nullptr;       // [N * p_stride] stencil sampling: the drawn atoms (sorted index, -1: i or i's molecule)
+    int32_t* batch_j = nullptr;       // [N * p_stride] stencil sampling: the drawn atoms (sorted index, -1: i or
+                                      // i's molecule), for the adjoint and read-back, allocated on first use
+    bool batch_j_valid = false;       // batch_j holds the decode of the current ranks
     int32_t* scell = nullptr;         // [N] stencil sampling: cell of each sorted atom at the last build
     int32_t p_stride = 0;
     bool ranks_valid = false;         // ranks hold the draw of ranks_step for the current lists
@@ -197,6 +199,9 @@ hipError_t launch_gather_grad(irbe_ctx* h, const void* grad);
 hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool want_lj);
 // Grow the shell-adjoint record buckets to hold `records` records (and create the row cursors).
 hipError_t ensure_buckets(irbe_ctx* h, int64_t records);
+// Stencil sampling: allocate the read-back array of the decoded batch, and fill it.
+hipError_t ensure_batch_atoms(irbe_ctx* h);
+hipError_t launch_stencil_decode(irbe_ctx* h);
 hipError_t launch_kspace_adjoint(irbe_ctx* h, const void* grad, void* grad_pos, void* grad_q, double* grad_lj);
 
 }  // namespace irbe

@@ -158,88 +158,121 @@ __global__ __launch_bounds__(BLOCK) void k_draw_batches(int64_t n, const int32_t
     for (; c < p_shell; ++c) out[c] = (uint16_t)floyd_step<BLOCK>(st, bitmap, t0 + c);
 }
 
-// Stencil sampling: the ranks into K(i) (or 0 .. |K(i)|-1 when all are taken)
-// turned into sorted atom indices. K(i) runs over the stencil rows (dz, dy) in
-// order, each row being the cells cx + lo .. cx + lo + span - 1 (cyclic) around
-// the atom's cell at the build, i.e. at most two index ranges. One wavefront per apw consecutive atoms: the row
-// offsets of the current cell sit in the wavefront's LDS slice (rebuilt when
-// the cell changes: one row per lane and a wave prefix sum), and each lane
-// binary-searches its ranks. i itself and i's molecule give -1.
-constexpr int kDecodeBlock = 256;
+// Stencil sampling: K(i), the atoms of the shell stencil's cells around atom
+// i's cell at the build, runs over the stencil rows (dz, dy) in order, each row
+// being the cells cx + lo .. cx + lo + span - 1 (cyclic), i.e. at most two
+// index ranges of the cell-sorted atoms. A wavefront keeps the rows of one cell
+// in LDS (one row per lane, prefix sums by wave scan) and turns a rank of K(i)
+// into an atom with a binary search over the rows' first ranks.
 constexpr int kDecodeRows = 128;  // stencil rows (span^2) supported
+
+template <int ROWS>
+struct StencilRows {
+    int32_t pre[ROWS];  // first rank of each row
+    int32_t a[ROWS];    // first atom of the row's first range
+    int32_t la[ROWS];   // length of the first range
+    int32_t b[ROWS];    // first atom of the second range (after the wrap)
+};
+
+struct StencilArgs {
+    const int32_t* cell_start;
+    const int32_t* scell;  // cell of each sorted atom at the build
+    const int32_t* smol;   // molecule of each sorted atom
+    int n_c, lo, span;
+};
 
 __device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-__global__ __launch_bounds__(kDecodeBlock) void k_stencil_decode(
-    int64_t n, int apw, int n_c, int lo, int span, const int32_t* __restrict__ cell_start,
-    const int32_t* __restrict__ scell, const int32_t* __restrict__ smol, const int32_t* __restrict__ nshell,
-    int p_shell, int p_stride, const uint16_t* __restrict__ ranks, int32_t* __restrict__ batch_j)
+// The rows of build cell `cell` into T (every lane of the wavefront takes part).
+template <int ROWS>
+__device__ void stencil_rows_build(StencilRows<ROWS>& T, int cell, const StencilArgs& sa, int lane)
 {
-    constexpr int NW = kDecodeBlock / 64;
-    __shared__ int32_t t_pre[NW][kDecodeRows];   // first rank of each row
-    __shared__ int32_t t_a[NW][kDecodeRows];     // first atom of the row's first range
-    __shared__ int32_t t_la[NW][kDecodeRows];    // length of the first range
-    __shared__ int32_t t_b[NW][kDecodeRows];     // first atom of the second range (after the wrap)
+    const int n_c = sa.n_c, span = sa.span, nrows = span * span;
+    const int cx = cell % n_c, cy = (cell / n_c) % n_c, cz = cell / (n_c * n_c);
+    const int x0 = wrap_cell(cx + sa.lo, n_c);
+    const int la_c = min(span, n_c - x0);  // cells before the wrap
+    int base = 0;
+    for (int t0 = 0; t0 < nrows; t0 += 64) {
+        const int t = t0 + lane;
+        int len = 0, va = 0, vla = 0, vb = 0;
+        if (t < nrows) {
+            const int z = wrap_cell(cz + t / span + sa.lo, n_c);
+            const int y = wrap_cell(cy + t % span + sa.lo, n_c);
+            const int row = (z * n_c + y) * n_c;
+            va = sa.cell_start[row + x0];
+            vla = sa.cell_start[row + x0 + la_c] - va;
+            vb = sa.cell_start[row];
+            len = vla + (span > la_c ? sa.cell_start[row + span - la_c] - vb : 0);
+        }
+        int incl = len;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        if (t < nrows) {
+            T.pre[t] = base + incl - len;
+            T.a[t] = va;
+            T.la[t] = vla;
+            T.b[t] = vb;
+        }
+        base += __shfl(incl, 63, 64);
+    }
+}
+
+// Atom (sorted index) of rank r of K(i) for a cell whose rows are in T: the row
+// is the last one whose first rank is <= r.
+template <int ROWS>
+__device__ __forceinline__ int stencil_rows_atom(const StencilRows<ROWS>& T, int nrows, int r)
+{
+    int lo_k = 0, hi_k = nrows - 1;
+    while (lo_k < hi_k) {
+        const int mid = (lo_k + hi_k + 1) >> 1;
+        if (T.pre[mid] <= r) lo_k = mid;
+        else hi_k = mid - 1;
+    }
+    const int o = r - T.pre[lo_k];
+    const int la = T.la[lo_k];
+    return o < la ? T.a[lo_k] + o : T.b[lo_k] + (o - la);
+}
+
+// A drawn atom j of atom a (sorted indices) counts as a shell pair: not a
+// itself, not of a's molecule, and in the shell annulus.
+__device__ __forceinline__ bool stencil_member(int64_t a, int j, int mi, int mj, uint4 si, uint4 sj, uint64_t t_core,
+                                               uint64_t t_shell)
+{
+    return j >= 0 && j != (int)a && !(mi >= 0 && mj == mi) && in_annulus(si, sj, t_core, t_shell);
+}
+
+// Read-back of the decoded batch (the atoms at the drawn ranks, -1 for i itself
+// and i's molecule): one wavefront per apw consecutive atoms.
+constexpr int kDecodeBlock = 256;
+
+__global__ __launch_bounds__(kDecodeBlock) void k_stencil_decode(int64_t n, int apw, StencilArgs sa,
+                                                                 const int32_t* __restrict__ nshell, int p_shell,
+                                                                 int p_stride, const uint16_t* __restrict__ ranks,
+                                                                 int32_t* __restrict__ batch_j)
+{
+    __shared__ StencilRows<kDecodeRows> rows[kDecodeBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t a0 = ((int64_t)blockIdx.x * NW + wave) * apw;
+    const int64_t a0 = ((int64_t)blockIdx.x * (kDecodeBlock / 64) + wave) * apw;
     const int64_t a1 = min(n, a0 + apw);
-    const int nrows = span * span;
+    const int nrows = sa.span * sa.span;
     int cur = -1;
     for (int64_t a = a0; a < a1; ++a) {
-        const int cell = scell[a];  // the cell of the build (positions may have moved since)
-        const int cx = cell % n_c, cy = (cell / n_c) % n_c, cz = cell / (n_c * n_c);
+        const int cell = sa.scell[a];
         if (cell != cur) {
+            stencil_rows_build(rows[wave], cell, sa, lane);
             cur = cell;
-            const int x0 = wrap_cell(cx + lo, n_c);
-            const int la_c = min(span, n_c - x0);  // cells before the wrap
-            int base = 0;
-            for (int t0 = 0; t0 < nrows; t0 += 64) {
-                const int t = t0 + lane;
-                int len = 0, va = 0, vla = 0, vb = 0;
-                if (t < nrows) {
-                    const int z = wrap_cell(cz + t / span + lo, n_c);
-                    const int y = wrap_cell(cy + t % span + lo, n_c);
-                    const int row = (z * n_c + y) * n_c;
-                    va = cell_start[row + x0];
-                    vla = cell_start[row + x0 + la_c] - va;
-                    vb = cell_start[row];
-                    len = vla + (span > la_c ? cell_start[row + span - la_c] - vb : 0);
-                }
-                int incl = len;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int v = __shfl_up(incl, off, 64);
-                    if (lane >= off) incl += v;
-                }
-                if (t < nrows) {
-                    t_pre[wave][t] = base + incl - len;
-                    t_a[wave][t] = va;
-                    t_la[wave][t] = vla;
-                    t_b[wave][t] = vb;
-                }
-                base += __shfl(incl, 63, 64);
-            }
         }
         const int m = nshell[a];
         const bool sample = m > p_shell;
         const int cnt = sample ? p_shell : m;
-        const int mi = smol[a];
-        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
-        int32_t* out = batch_j + a * (int64_t)p_stride;
+        const int mi = sa.smol[a];
         for (int c = lane; c < cnt; c += 64) {
-            const int r = sample ? (int)rrow[c] : c;
-            // the row holding rank r: the last row whose first rank is <= r
-            int lo_k = 0, hi_k = nrows - 1;
-            while (lo_k < hi_k) {
-                const int mid = (lo_k + hi_k + 1) >> 1;
-                if (t_pre[wave][mid] <= r) lo_k = mid;
-                else hi_k = mid - 1;
-            }
-            const int o = r - t_pre[wave][lo_k];
-            const int la = t_la[wave][lo_k];
-            int j = o < la ? t_a[wave][lo_k] + o : t_b[wave][lo_k] + (o - la);
-            if (j == (int)a || (mi >= 0 && smol[j] == mi)) j = -1;
-            out[c] = j;
+            int j = stencil_rows_atom(rows[wave], nrows, sample ? (int)ranks[a * p_stride + c] : c);
+            if (j == (int)a || (mi >= 0 && sa.smol[j] == mi)) j = -1;
+            batch_j[a * (int64_t)p_stride + c] = j;
         }
     }
 }
@@ -312,11 +345,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
-    int p_stride, const uint16_t* __restrict__ ranks, const int32_t* __restrict__ batch_j, uint64_t t_core,
-    uint64_t t_shell, real* __restrict__ fsr, double* __restrict__ part)
+    int p_stride, const uint16_t* __restrict__ ranks, StencilArgs sa, uint64_t t_core, uint64_t t_shell,
+    real* __restrict__ fsr, double* __restrict__ part)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
+    __shared__ StencilRows<STENCIL ? kDecodeRows : 1> srows[kCoopBlock / 64];  // stencil rows of one cell per wave
     const int nt2 = n_types * n_types;
     for (int t = threadIdx.x; t < nt2; t += kCoopBlock) lj[t] = lj_g[t];
     __syncthreads();
@@ -334,6 +368,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int h_nc = FULL ? 0 : ncore[ah];
     const int h_ns = nshell[ah];
     const int2 h_x = sxr[ah];
+    const int h_mol = STENCIL ? sa.smol[ah] : 0;
+    const int wave = threadIdx.x >> 6;
+    const int nrows = sa.span * sa.span;
+    int tcell = -1;  // the cell whose stencil rows sit in srows[wave]
     // first-level indices of one atom's first pass: the lane's first core entry,
     // its two batch ranks (or shell positions) and its first excluded partner
     // Without energies the excluded partners follow the core entries in one slot
@@ -352,14 +390,17 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
                            : (lane < nc + xr.y ? sxidx[xr.x + lane - nc] : -1);
         else
             jc = lane < nc ? core[a * (int64_t)cap_core + lane] : -1;
+        r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
+        r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
         if (STENCIL) {
-            // the decoded batch: atom indices (or -1) in place of ranks
-            const int32_t* brow = batch_j + a * (int64_t)p_stride;
-            r0 = lane < cnt ? brow[lane] : -1;
-            r1 = lane + 64 < cnt ? brow[lane + 64] : -1;
-        } else {
-            r0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
-            r1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+            // ranks of K(i) -> atoms, through the rows of the atom's build cell
+            const int cell = sa.scell[a];
+            if (cell != tcell) {
+                stencil_rows_build(srows[wave], cell, sa, lane);
+                tcell = cell;
+            }
+            if (r0 >= 0) r0 = stencil_rows_atom(srows[wave], nrows, r0);
+            if (r1 >= 0) r1 = stencil_rows_atom(srows[wave], nrows, r1);
         }
         jx = (!kFold && lane < xr.y) ? sxidx[xr.x + lane] : -1;
     };
@@ -386,6 +427,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         PairSum<real> pc, ps, px;
         const int js0 = STENCIL ? r0 : (r0 >= 0 ? srow[r0] : -1);
         const int js1 = STENCIL ? r1 : (r1 >= 0 ? srow[r1] : -1);
+        const int mi = STENCIL ? bcast(h_mol, t) : 0;
+        const int mj0 = STENCIL ? sa.smol[max(js0, 0)] : 0;
+        const int mj1 = STENCIL ? sa.smol[max(js1, 0)] : 0;
         // (unused slots load atom 0, so that every position is one 16-byte load)
         const uint4 pjc = spos[max(jc, 0)];
         const real qjc = sqr[max(jc, 0)];
@@ -401,9 +445,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
             if (jc >= 0) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
             if (jx >= 0) add_excl<real, EV>(px, si, qi, pjx, qjx, pp);
         }
-        if (js0 >= 0 && (!STENCIL || in_annulus(si, pj0, t_core, t_shell)))
+        if (STENCIL ? stencil_member(a, js0, mi, mj0, si, pj0, t_core, t_shell) : js0 >= 0)
             add_pair<real, EV>(ps, si, qi, pj0, qj0, lrow, pp);
-        if (js1 >= 0 && (!STENCIL || in_annulus(si, pj1, t_core, t_shell)))
+        if (STENCIL ? stencil_member(a, js1, mi, mj1, si, pj1, t_core, t_shell) : js1 >= 0)
             add_pair<real, EV>(ps, si, qi, pj1, qj1, lrow, pp);
         // the rest (long lists and large batches)
         if (kFold) {
@@ -421,12 +465,20 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
                 add_excl<real, EV>(px, si, qi, spos[j], sqr[j], pp);
             }
         }
+        if (STENCIL && cnt > 128) {
+            // the next atom's first pass may have put another cell's rows in place
+            const int cell = sa.scell[a];
+            if (cell != tcell) {
+                stencil_rows_build(srows[wave], cell, sa, lane);
+                tcell = cell;
+            }
+        }
         for (int c = lane + 128; c < cnt; c += 64) {
             if (STENCIL) {
-                const int j = batch_j[a * (int64_t)p_stride + c];
-                if (j < 0) continue;
+                const int j = stencil_rows_atom(srows[wave], nrows, sample ? (int)rrow[c] : c);
                 const uint4 sj = spos[j];
-                if (in_annulus(si, sj, t_core, t_shell)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
+                if (stencil_member(a, j, mi, sa.smol[j], si, sj, t_core, t_shell))
+                    add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
             } else {
                 const int j = srow[sample ? (int)rrow[c] : c];
                 add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
@@ -471,6 +523,35 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     if (threadIdx.x < 12) part[blk * (int64_t)kPairPartials + threadIdx.x] = out;
 }
 
+static StencilArgs stencil_args(const irbe_ctx* h)
+{
+    StencilArgs sa;
+    sa.cell_start = h->cell_start;
+    sa.scell = h->scell;
+    sa.smol = h->smol;
+    sa.n_c = h->geo.n_c;
+    sa.lo = h->geo.lo;
+    sa.span = h->geo.hi - h->geo.lo + 1;
+    return sa;
+}
+
+// Stencil sampling: the drawn atoms of the current batch into h->batch_j (for
+// read-back; the pair kernels decode the ranks themselves).
+hipError_t launch_stencil_decode(irbe_ctx* h)
+{
+    if (!h->stencil) return hipErrorInvalidValue;
+    const StencilArgs sa = stencil_args(h);
+    if (sa.span * sa.span > kDecodeRows) return hipErrorInvalidValue;
+    const int64_t n = h->cfg.n_atoms;
+    const hipError_t e = ensure_batch_atoms(h);
+    if (e != hipSuccess) return e;
+    const int apw = 16;
+    const int64_t waves = blocks_for(n, apw);
+    k_stencil_decode<<<(unsigned)blocks_for(waves, kDecodeBlock / 64), kDecodeBlock, 0, h->stream>>>(
+        n, apw, sa, h->nshell, h->cfg.p_shell, h->p_stride, h->ranks, h->batch_j);
+    return hipGetLastError();
+}
+
 // Batch ranks of every atom for `step` (kept until the lists or the step change).
 static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
 {
@@ -491,21 +572,11 @@ static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
     else
         k_draw_batches<64><<<nb, 64, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
                                                        h->cfg.seed, step, h->ranks);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && h->stencil) {
-        const Geometry& g = h->geo;
-        const int span = g.hi - g.lo + 1;
-        if (span * span > kDecodeRows) return hipErrorInvalidValue;
-        const int apw = 16;
-        const int64_t waves = blocks_for(n, apw);
-        k_stencil_decode<<<(unsigned)blocks_for(waves, kDecodeBlock / 64), kDecodeBlock, 0, h->stream>>>(
-            n, apw, g.n_c, g.lo, span, h->cell_start, h->scell, h->smol, h->nshell, h->cfg.p_shell, h->p_stride,
-            h->ranks, h->batch_j);
-        e = hipGetLastError();
-    }
+    const hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         h->ranks_valid = true;
         h->ranks_step = step;
+        h->batch_j_valid = false;
     }
     return e;
 }
@@ -527,7 +598,7 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     k_pair_coop<real, FULL, EV, STENCIL><<<nb, kCoopBlock, 0, h->stream>>>(
         n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
-        h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part);
+        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
     return hipGetLastError();
 }
@@ -816,7 +887,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         // the excluded partners follow the symmetric list (entries nsym .. nsym + nx - 1)
         jc = lane < nsym ? srow_sym[lane] : (lane < nsym + xr.y ? sxidx[xr.x + lane - nsym] : -1);
         if (STENCIL) {
-            // the decoded batch: atom indices (or -1) in place of ranks
+            // the decoded batch (atoms, -1 for i itself and i's molecule) in place of ranks
             const int32_t* brow = batch_j + a * (int64_t)p_stride;
             r0 = lane < cnt ? brow[lane] : -1;
             r1 = lane + 64 < cnt ? brow[lane + 64] : -1;
@@ -1149,6 +1220,13 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
     pp.ke = (real)h->cfg.coulomb_k;
     hipError_t e = launch_draw(h, step);
     if (e != hipSuccess) return e;
+    if (STENCIL && !h->batch_j_valid) {
+        // the adjoint reads the batch decoded once (its blocks hold too few atoms
+        // for the per-wavefront decode of the forward kernel to pay)
+        e = launch_stencil_decode(h);
+        if (e != hipSuccess) return e;
+        h->batch_j_valid = true;
+    }
     const int64_t waves = blocks_for(n, apw);
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
