@@ -269,10 +269,22 @@ __global__ __launch_bounds__(kDecodeBlock) void k_stencil_decode(int64_t n, int 
         const bool sample = m > p_shell;
         const int cnt = sample ? p_shell : m;
         const int mi = sa.smol[a];
-        for (int c = lane; c < cnt; c += 64) {
-            int j = stencil_rows_atom(rows[wave], nrows, sample ? (int)ranks[a * p_stride + c] : c);
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        int32_t* out = batch_j + a * (int64_t)p_stride;
+        // the lane's first two slots with their loads issued together
+        const int q0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
+        const int q1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+        int j0 = q0 >= 0 ? stencil_rows_atom(rows[wave], nrows, q0) : -1;
+        int j1 = q1 >= 0 ? stencil_rows_atom(rows[wave], nrows, q1) : -1;
+        const int m0 = sa.smol[max(j0, 0)], m1 = sa.smol[max(j1, 0)];
+        if (j0 == (int)a || (mi >= 0 && m0 == mi)) j0 = -1;
+        if (j1 == (int)a || (mi >= 0 && m1 == mi)) j1 = -1;
+        if (q0 >= 0) out[lane] = j0;
+        if (q1 >= 0) out[lane + 64] = j1;
+        for (int c = lane + 128; c < cnt; c += 64) {
+            int j = stencil_rows_atom(rows[wave], nrows, sample ? (int)rrow[c] : c);
             if (j == (int)a || (mi >= 0 && sa.smol[j] == mi)) j = -1;
-            batch_j[a * (int64_t)p_stride + c] = j;
+            out[c] = j;
         }
     }
 }
