@@ -1283,7 +1283,16 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
     bk.n_c = h->geo.n_c;
     bk.lo = h->geo.lo;
     bk.span = h->geo.hi - h->geo.lo + 1;
-    const int p_eff = std::max(1, std::min(h->cfg.p_shell, std::max(h->max_shell, 1)));
+    int p_eff = std::max(1, std::min(h->cfg.p_shell, std::max(h->max_shell, 1)));
+    if (h->stencil) {
+        // records only for the drawn atoms inside the shell: p~ times the shell's
+        // share of the stencil volume, with a margin (the rest take the atomics)
+        const double L = h->cfg.box_length, edge = L / h->geo.n_c;
+        const double span = (double)(h->geo.hi - h->geo.lo + 1) * edge;
+        const double rs = h->cfg.r_shell, rc = h->cfg.r_core;
+        const double frac = std::min(1.0, 4.0 / 3.0 * 3.14159265358979323846 * (rs * rs * rs - rc * rc * rc) / (span * span * span));
+        p_eff = std::max(1, std::min(p_eff, (int)std::ceil(1.3 * frac * h->cfg.p_shell)));
+    }
     const int rec_cap = h->fp64 ? kBucketRecD : kBucketRecF;
     const int apw = std::min(kAtomsPerWave, rec_cap / (4 * p_eff));
     const int nkeys = 2 * bk.span * bk.span;
