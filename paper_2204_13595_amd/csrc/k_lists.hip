@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     for (int chunk = a0; chunk < a1; chunk += kListWave) {
         const int k = chunk + lane;
         const bool act = k < a1;
+        const int na = min(kListWave, a1 - chunk);  // atoms of this chunk
         const uint4 si = act ? spos[k] : make_uint4(0, 0, 0, 0);
         const int32_t mi = act ? smol[k] : -1;
         const int cx = (int)(((uint64_t)si.x * (uint32_t)n_c) >> 32);
@@ -149,6 +150,12 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
         const uint32_t az = pack_rel(si.z, orz, sh);
         const uint32_t amol = (uint32_t)(mi >= 0 ? mi : -2 - k);
         const int axp = (int)(short)(axy & 0xffffu);  // packed x as a signed value
+        // the rows of this chunk's atoms, one buffer descriptor per list: stores of an
+        // overflowing row stay within them (and the rebuild that follows rewrites them)
+        const __amdgpu_buffer_rsrc_t rs_s = __builtin_amdgcn_make_buffer_rsrc(
+            shell + (int64_t)chunk * cap_shell, (short)0, na * cap_shell * 4, kBufferWord3);
+        const __amdgpu_buffer_rsrc_t rs_c = __builtin_amdgcn_make_buffer_rsrc(
+            core + (int64_t)chunk * cap_core, (short)0, na * cap_core * 4, kBufferWord3);
         acnt[lane] = make_int2(0, 0);
         for (int dz = lo; dz <= hi; ++dz) {
             const int z = wrap(cz + dz, n_c);
@@ -244,8 +251,12 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                     // chunks, so no half-wave reads past its own range (+ 31); a lone
                     // atom of a chunk count takes both halves (the upper one idle)
                     const int nch = (len_l + 31) >> 5;
-                    for (int chunks = 1; chunks <= kTileCap / 32; ++chunks) {
-                        uint64_t pend = ballot(nch == chunks);
+                    uint64_t left = ballot(nch > 0);
+                    while (left) {
+                        // the chunk counts present, one at a time
+                        const int chunks = __builtin_amdgcn_readlane(nch, __builtin_ctzll(left));
+                        uint64_t pend = left & ballot(nch == chunks);
+                        left &= ~pend;
                         while (pend) {
                             // the next two atoms: a in the lower half, b in the upper
                             const int a = __builtin_ctzll(pend);
@@ -260,15 +271,11 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                             const int lenm = (int)(ap.w >> 16) - hl;
                             const int qb = (int)(ap.w & 0xffffu) + hl;
                             int cs = cn.y, cc = cn.x;  // this half's atom: list lengths so far
-                            // rows a .. b of the list arrays; the upper half writes at row b
-                            const __amdgpu_buffer_rsrc_t rs_s = __builtin_amdgcn_make_buffer_rsrc(
-                                shell + (int64_t)(chunk + a) * cap_shell, (short)0, (drow + 1) * cap_shell * 4, kBufferWord3);
-                            const int hoff_s = hsel & (drow * cap_shell * 4);
+                            // byte offsets of this half's atom's rows in the wave's list rows
+                            const int hoff_s = __mul24(ka, cap_shell * 4);
                             auto scan = [&](auto core_tag) {
                                 constexpr bool CORE = decltype(core_tag)::value;
-                                const __amdgpu_buffer_rsrc_t rs_c = __builtin_amdgcn_make_buffer_rsrc(
-                                    core + (int64_t)(chunk + a) * cap_core, (short)0, (drow + 1) * cap_core * 4, kBufferWord3);
-                                const int hoff_c = hsel & (drow * cap_core * 4);
+                                const int hoff_c = __mul24(ka, cap_core * 4);
                                 for (int c0 = 0; c0 < chunks * 32; c0 += 32) {
                                     const u32x4 r = trec[qb + c0];
                                     const uint32_t d2 = d2_packed(r.x, r.y, ap.x, ap.y);
