@@ -154,9 +154,16 @@ static inline int orc_excluded(const int32_t* mol, int64_t i, int64_t j)
  * drawn from K(i) directly (Algorithm 1 draws from the stencil; Sec. 2.3 notes
  * that the filter step can be skipped) and a drawn atom counts only when it
  * is a member of S(i).
+ *
+ * skin > 0 (lists kept over several steps, Sec. 2.3: cells slightly larger
+ * than r_core): the cells have edge >= r_core + skin, C(i) takes
+ * r <= r_core + skin, S(i) takes r_core - skin < r <= r_shell + skin (the two
+ * overlap), and the full list r <= r_shell + skin; a force evaluation then
+ * counts an entry only when the pair is a member at its own positions. skin = 0
+ * gives the sets above exactly.
  */
 static int64_t orc_list_row(int64_t i, const uint32_t* s, const int32_t* mol, int32_t n_c, int32_t R,
-                            uint64_t t_core, uint64_t t_shell, const int64_t* cell_start,
+                            uint64_t t_core, uint64_t t_lo, uint64_t t_shell, const int64_t* cell_start,
                             const int64_t* cell_atoms, int want_core, int full_list, int32_t* out)
 {
     int64_t count = 0;
@@ -188,7 +195,7 @@ static int64_t orc_list_row(int64_t i, const uint32_t* s, const int32_t* mol, in
                         uint64_t d2 = orc_dist2(s, i, j);
                         if (want_core) take = d2 <= t_core;
                         else if (full_list == ORC_LISTS_FULL) take = d2 <= t_shell;
-                        else take = d2 > t_core && d2 <= t_shell;
+                        else take = d2 > t_lo && d2 <= t_shell;
                     }
                     if (take) {
                         if (out) out[count] = (int32_t)j;
@@ -200,14 +207,16 @@ static int64_t orc_list_row(int64_t i, const uint32_t* s, const int32_t* mol, in
 }
 
 int orc_build_lists(int64_t n, const uint32_t* s, const int32_t* mol, double L, double r_core,
-                    double r_shell, int full_list, const int64_t* sel, int64_t n_sel,
+                    double r_shell, double skin, int full_list, const int64_t* sel, int64_t n_sel,
                     int64_t* core_off, int32_t* core_idx, int64_t* shell_off, int32_t* shell_idx)
 {
-    int32_t n_c = orc_n_cells(L, r_core);
-    if (n_c < 3 || !(r_shell > r_core) || !(r_shell < 0.5 * L)) return ORC_EINVAL;
-    int32_t R = orc_shell_reach(L, r_shell, n_c);
-    uint64_t t_core = orc_threshold(r_core, L);
-    uint64_t t_shell = orc_threshold(r_shell, L);
+    if (!(skin >= 0.0)) return ORC_EINVAL;
+    int32_t n_c = orc_n_cells(L, r_core + skin);
+    if (n_c < 3 || !(r_shell > r_core) || !(r_shell + skin < 0.5 * L)) return ORC_EINVAL;
+    int32_t R = orc_shell_reach(L, r_shell + skin, n_c);
+    uint64_t t_core = orc_threshold(r_core + skin, L);
+    uint64_t t_lo = r_core > skin ? orc_threshold(r_core - skin, L) : 0;
+    uint64_t t_shell = orc_threshold(r_shell + skin, L);
     int64_t n_cells = (int64_t)n_c * n_c * n_c;
     int64_t* cell_start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_cells + 1));
     int64_t* cell_atoms = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
@@ -225,14 +234,14 @@ int orc_build_lists(int64_t n, const uint32_t* s, const int32_t* mol, double L, 
         if (!fill) {
             core_off[k + 1] = full_list == ORC_LISTS_FULL
                                   ? 0
-                                  : orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 1, 0, NULL);
-            shell_off[k + 1] = orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 0,
+                                  : orc_list_row(i, s, mol, n_c, R, t_core, t_lo, t_shell, cell_start, cell_atoms, 1, 0, NULL);
+            shell_off[k + 1] = orc_list_row(i, s, mol, n_c, R, t_core, t_lo, t_shell, cell_start, cell_atoms, 0,
                                             full_list, NULL);
         } else {
             if (full_list != ORC_LISTS_FULL && core_idx)
-                orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 1, 0, core_idx + core_off[k]);
+                orc_list_row(i, s, mol, n_c, R, t_core, t_lo, t_shell, cell_start, cell_atoms, 1, 0, core_idx + core_off[k]);
             if (shell_idx)
-                orc_list_row(i, s, mol, n_c, R, t_core, t_shell, cell_start, cell_atoms, 0, full_list,
+                orc_list_row(i, s, mol, n_c, R, t_core, t_lo, t_shell, cell_start, cell_atoms, 0, full_list,
                              shell_idx + shell_off[k]);
         }
     }
@@ -470,7 +479,8 @@ static inline int64_t orc_row_atom(const int64_t* rows, int64_t r) { return rows
  * for each row atom i. core_off/core_idx hold C(i) per row (may be NULL: empty);
  * shell_off/shell_idx hold S(i) per row; the batch B(i) is given as ranks into
  * S(i) (batch_off/batch_rank per row; NULL: every member); w per row (NULL: 1).
- * accept (NULL: all) flags the batch entries that count (stencil sampling).
+ * core_accept / accept (NULL: all) flag the core and batch entries that count
+ * (stencil sampling, skin lists).
  * e8 accumulates [U_coul, U_lj, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz] with the
  * estimator U = 1/2 sum_i (sum_C u_ij + w_i sum_B u_ij), and likewise for the
  * pair virial W_ab = -1/2 sum_i sum_j w r_ij,a f_ij,b.
@@ -479,7 +489,7 @@ int orc_short_range(const orc_system* sy, int64_t n, const uint32_t* s, const do
                     const double* lj_sigma, const double* lj_eps, const int64_t* rows, int64_t n_rows,
                     const int64_t* core_off, const int32_t* core_idx, const int64_t* shell_off,
                     const int32_t* shell_idx, const int64_t* batch_off, const int32_t* batch_rank,
-                    const double* w, const uint8_t* accept, double* f_out, double* e8)
+                    const double* w, const uint8_t* core_accept, const uint8_t* accept, double* f_out, double* e8)
 {
     (void)n;
     const int nt = sy->n_types;
@@ -501,6 +511,7 @@ int orc_short_range(const orc_system* sy, int64_t n, const uint32_t* s, const do
                     int64_t j;
                     if (pass == 0) j = core_idx[core_off[r] + k];
                     else j = shell_idx[shell_off[r] + (batch_off ? batch_rank[batch_off[r] + k] : k)];
+                    if (pass == 0 && core_accept && !core_accept[core_off[r] + k]) continue;
                     if (pass == 1 && accept && !accept[(batch_off ? batch_off[r] : shell_off[r]) + k]) continue;
                     double dv[3], dist, phi, uc, ul;
                     orc_sep(s, i, j, sy->L, dv, &dist);
@@ -667,8 +678,8 @@ int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, 
                             const int32_t* type, const double* lj_sigma, const double* lj_eps,
                             const int64_t* core_off, const int32_t* core_idx, const int64_t* shell_off,
                             const int32_t* shell_idx, const int64_t* batch_off, const int32_t* batch_rank,
-                            const double* w, const uint8_t* accept, int rbl, const double* G, double* g_pos,
-                            double* g_q, double* g_sigma, double* g_eps)
+                            const double* w, const uint8_t* core_accept, const uint8_t* accept, int rbl,
+                            const double* G, double* g_pos, double* g_q, double* g_sigma, double* g_eps)
 {
     const int nt = sy->n_types;
     const double b = sy->beta, ke = sy->ke, spi = sqrt(ORC_PI);
@@ -689,6 +700,7 @@ int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, 
                 int64_t j;
                 if (pass == 0) j = core_idx[core_off[i] + k];
                 else j = shell_idx[shell_off[i] + (batch_off ? batch_rank[batch_off[i] + k] : k)];
+                if (pass == 0 && core_accept && !core_accept[core_off[i] + k]) continue;
                 if (pass == 1 && accept && !accept[(batch_off ? batch_off[i] : shell_off[i]) + k]) continue;
                 double dv[3], r;
                 orc_sep(s, i, j, sy->L, dv, &r);
@@ -841,11 +853,14 @@ int orc_shell_batches(uint64_t seed, uint64_t step, const int64_t* rows, int64_t
     return ORC_OK;
 }
 
-/* Stencil sampling: accept[e] = 1 when batch entry e of row r (the atom of
- * rank batch_rank[e] in the row's stencil candidates, or entry e itself when
- * batch_off is NULL) is a member of S(i): not i, not of i's molecule, and
- * T_c < D^2 <= T_s with the thresholds of O1. */
-int orc_batch_accept(const uint32_t* s, const int32_t* mol, double L, double r_core, double r_shell,
+/* Membership of list or batch entries at the positions s: accept[e] = 1 when
+ * entry e of row r (the atom of rank batch_rank[e] in the row's list, or entry
+ * e itself when batch_off is NULL) is a member, with the thresholds of O1:
+ * kind 0: of C(i) (D^2 <= T_c); kind 1: of S(i) (T_c < D^2 <= T_s);
+ * kind 2: of the full list (D^2 <= T_s); never i itself or i's molecule.
+ * Used by stencil sampling (the batch is drawn from candidates) and by lists
+ * built with a skin (entries may have left their set). */
+int orc_batch_accept(const uint32_t* s, const int32_t* mol, double L, double r_core, double r_shell, int kind,
                      const int64_t* rows, int64_t n_rows, const int64_t* shell_off, const int32_t* shell_idx,
                      const int64_t* batch_off, const int32_t* batch_rank, uint8_t* accept)
 {
@@ -860,7 +875,7 @@ int orc_batch_accept(const uint32_t* s, const int32_t* mol, double L, double r_c
             int ok = j != i && !orc_excluded(mol, i, j);
             if (ok) {
                 uint64_t d2 = orc_dist2(s, i, j);
-                ok = d2 > t_core && d2 <= t_shell;
+                ok = kind == 0 ? d2 <= t_core : (kind == 1 ? d2 > t_core && d2 <= t_shell : d2 <= t_shell);
             }
             accept[e0 + k] = (uint8_t)ok;
         }

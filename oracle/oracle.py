@@ -69,7 +69,7 @@ def lib():
         L.orc_threshold.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_cell_lists.argtypes = [ctypes.c_int64, ctypes.c_int32, _u32p, _i64p, _i64p]
         L.orc_build_lists.argtypes = [ctypes.c_int64, _u32p, _i32p, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_double, ctypes.c_int, _i64p, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, _i64p, ctypes.c_int64,
                                       _i64p, _i32p, _i64p, _i32p]
         L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
         L.orc_shell_ranks.restype = ctypes.c_int32
@@ -84,9 +84,9 @@ def lib():
                                          _i64p, _i64p]
         L.orc_short_range.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i32p, _f64p, _f64p,
                                       _i64p, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _i64p, _i32p, _f64p,
-                                      _u8p, _f64p, _f64p]
-        L.orc_batch_accept.argtypes = [_u32p, _i32p, ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64p,
-                                       ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _u8p]
+                                      _u8p, _u8p, _f64p, _f64p]
+        L.orc_batch_accept.argtypes = [_u32p, _i32p, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       _i64p, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _u8p]
         L.orc_exclusions.argtypes = [ctypes.POINTER(_System), _u32p, _f64p, _i64p, ctypes.c_int64, _i64p, _i64p,
                                      _f64p, _f64p]
         L.orc_structure_factor.argtypes = [_u32p, _f64p, _i64p, ctypes.c_int64, ctypes.c_int32, _i32p, _f64p]
@@ -95,7 +95,7 @@ def lib():
         L.orc_kspace_energy.argtypes = [ctypes.POINTER(_System), ctypes.c_int32, _i32p, _f64p, _f64p, _f64p]
         L.orc_short_range_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i32p,
                                               _f64p, _f64p, _i64p, _i32p, _i64p, _i32p, _i64p, _i32p, _f64p,
-                                              _u8p, ctypes.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
+                                              _u8p, _u8p, ctypes.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.orc_exclusions_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i64p, _i64p,
                                              _f64p, _f64p, _f64p]
         L.orc_kspace_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, ctypes.c_int32,
@@ -128,6 +128,7 @@ class Params:
     seed: int = 13595
     ke: float = COULOMB_K
     n_types: int = 2
+    skin: float = 0.0      # lists kept over steps: cells and list radii enlarged by the skin
 
     @property
     def alpha(self) -> float:
@@ -178,9 +179,10 @@ class Lists:
     rows: np.ndarray | None
 
 
-def build_lists(s, mol, box, r_core, r_shell, full=False, rows=None, stencil=False) -> Lists:
+def build_lists(s, mol, box, r_core, r_shell, full=False, rows=None, stencil=False, skin=0.0) -> Lists:
     """C(i) and S(i) per row (Sec. 2.3); ``full``: one list C(i) u S(i);
-    ``stencil``: C(i) and, in place of S(i), the stencil candidates K(i)."""
+    ``stencil``: C(i) and, in place of S(i), the stencil candidates K(i);
+    ``skin``: the radii (and the cell edge) enlarged for lists kept over steps."""
     kind = 2 if stencil else (1 if full else 0)
     s = _c(s, np.uint32)
     mol = _c(mol, np.int32)
@@ -190,13 +192,13 @@ def build_lists(s, mol, box, r_core, r_shell, full=False, rows=None, stencil=Fal
     core_off = np.zeros(nr + 1, dtype=np.int64)
     shell_off = np.zeros(nr + 1, dtype=np.int64)
     L = lib()
-    rc = L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, kind, _p(rows_a, _i64p),
+    rc = L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, skin, kind, _p(rows_a, _i64p),
                            nr, _p(core_off, _i64p), None, _p(shell_off, _i64p), None)
     if rc != 0:
         raise ValueError(f"build_lists: invalid geometry ({rc})")
     core_idx = np.empty(max(int(core_off[-1]), 1), dtype=np.int32)
     shell_idx = np.empty(max(int(shell_off[-1]), 1), dtype=np.int32)
-    L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, kind, _p(rows_a, _i64p), nr,
+    L.orc_build_lists(n, _p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, skin, kind, _p(rows_a, _i64p), nr,
                       _p(core_off, _i64p), _p(core_idx, _i32p), _p(shell_off, _i64p), _p(shell_idx, _i32p))
     return Lists(core_off, core_idx[:core_off[-1]], shell_off, shell_idx[:shell_off[-1]], rows_a)
 
@@ -253,17 +255,29 @@ def shell_batches(seed: int, step: int, lists: Lists, p_s: int):
     return off, rank[:off[-1]], w
 
 
-def batch_accept(s, mol, box, r_core, r_shell, lists: Lists, batches) -> np.ndarray:
-    """Per batch entry (stencil sampling): 1 when the drawn candidate is a member of S(i)."""
+def batch_accept(s, mol, box, r_core, r_shell, lists: Lists, batches, kind: int = 1) -> np.ndarray:
+    """Per batch entry (``batches`` = (off, rank, w)), or per list entry when
+    ``batches`` is None: 1 when the atom is a member at the positions ``s`` of
+    C(i) (kind 0, tested on the core list), S(i) (kind 1) or the full list
+    (kind 2, on the shell arrays)."""
     s = _c(s, np.uint32)
     mol = _c(mol, np.int32)
-    b_off, b_rank, _ = batches
     rows = None if lists.rows is None else _c(lists.rows, np.int64)
-    n_rows = lists.shell_off.shape[0] - 1
-    out = np.zeros(max(int(b_off[-1]), 1), dtype=np.uint8)
-    lib().orc_batch_accept(_p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, _p(rows, _i64p), n_rows,
-                           _p(lists.shell_off, _i64p), _p(_c(lists.shell_idx, np.int32), _i32p),
-                           _p(_c(b_off, np.int64), _i64p), _p(_c(b_rank, np.int32), _i32p), _p(out, _u8p))
+    if kind == 0:
+        off, idx = lists.core_off, lists.core_idx
+    else:
+        off, idx = lists.shell_off, lists.shell_idx
+    n_rows = off.shape[0] - 1
+    if batches is not None:
+        b_off, b_rank = _c(batches[0], np.int64), _c(batches[1], np.int32)
+        total = int(b_off[-1])
+    else:
+        b_off = b_rank = None
+        total = int(off[-1])
+    out = np.zeros(max(total, 1), dtype=np.uint8)
+    lib().orc_batch_accept(_p(s, _u32p), _p(mol, _i32p), box, r_core, r_shell, kind, _p(rows, _i64p), n_rows,
+                           _p(_c(off, np.int64), _i64p), _p(_c(idx, np.int32), _i32p), _p(b_off, _i64p),
+                           _p(b_rank, _i32p), _p(out, _u8p))
     return out
 
 
@@ -321,6 +335,7 @@ class Result:
     s: np.ndarray
     S: float
     accept: np.ndarray | None = None
+    core_accept: np.ndarray | None = None
 
 
 def sample_kspace(params: Params, step: int):
@@ -344,10 +359,11 @@ def structure_factor(s, q, kvec, rows=None) -> np.ndarray:
 
 def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int = 0, mode: str = "rbl",
             rows=None, s=None, lists: Lists | None = None, batches=None, kspace=None, rho=None,
-            accept=None) -> Result:
+            accept=None, core_accept=None) -> Result:
     """One force evaluation. ``s`` (quantized positions), ``lists``, ``batches``
-    ((off, rank, w)), ``kspace`` ((m, W, S)) and, for ``stencil``, ``accept``
-    (which drawn candidates count) may be given to freeze them.
+    ((off, rank, w)), ``kspace`` ((m, W, S)) and ``accept`` / ``core_accept``
+    (which drawn candidates and core entries count: stencil sampling, skin
+    lists) may be given to freeze them.
     With ``rows`` only those atoms are evaluated; ``rho`` (from
     :func:`structure_factor` over all atoms) then gives their exact long-range
     force, otherwise rho is summed over the rows only."""
@@ -365,17 +381,23 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
     sampled = mode in ("rbl", "stencil")
     if lists is None:
         lists = build_lists(s, mol, params.box, params.r_core, params.r_shell, full=full, rows=rows_a,
-                            stencil=mode == "stencil")
-    if mode != "stencil":
-        accept = None
+                            stencil=mode == "stencil", skin=params.skin)
+    masked = mode == "stencil" or params.skin > 0
+    if not masked:
+        accept = core_accept = None
     if sampled:
         if batches is None:
             batches = shell_batches(params.seed, step, lists, params.p_shell)
         b_off, b_rank, w = batches
-        if mode == "stencil" and accept is None:
-            accept = batch_accept(s, mol, params.box, params.r_core, params.r_shell, lists, batches)
     else:
         b_off = b_rank = w = None
+    if masked:
+        # entries count only when members at these positions
+        if accept is None:
+            accept = batch_accept(s, mol, params.box, params.r_core, params.r_shell, lists,
+                                  batches if sampled else None, kind=1 if sampled else 2)
+        if core_accept is None and not full:
+            core_accept = batch_accept(s, mol, params.box, params.r_core, params.r_shell, lists, None, kind=0)
     if kspace is None:
         if mode == "ewald":
             m, W = ewald_kvectors(params.beta, params.box)
@@ -395,8 +417,8 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
                       _p(_c(lists.core_idx, np.int32), _i32p), _p(lists.shell_off, _i64p),
                       _p(_c(lists.shell_idx, np.int32), _i32p), _p(b_off, _i64p),
                       _p(None if b_rank is None else _c(b_rank, np.int32), _i32p),
-                      _p(None if w is None else _c(w, np.float64), _f64p), _p(accept, _u8p), _p(f_sr, _f64p),
-                      _p(e8, _f64p))
+                      _p(None if w is None else _c(w, np.float64), _f64p), _p(core_accept, _u8p), _p(accept, _u8p),
+                      _p(f_sr, _f64p), _p(e8, _f64p))
     fcorr = f_sr.mean(axis=0) if (sampled and n_rows > 0) else np.zeros(3)
     x_off, x_idx = exclusion_lists(mol, rows_a)
     e7x = np.zeros(7)
@@ -425,7 +447,8 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
     energy[4] = e7x[0]
     energy[5:11] = e8[2:8] + e7x[1:7] + e7k[1:7]
     force = f_sr - fcorr + f_x + f_long
-    return Result(force, energy, f_sr, f_x, f_long, fcorr, rho, m, W, lists, b_off, b_rank, w, s, S, accept)
+    return Result(force, energy, f_sr, f_x, f_long, fcorr, rho, m, W, lists, b_off, b_rank, w, s, S, accept,
+                  core_accept)
 
 
 def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result, mode: str = "rbl"):
@@ -454,7 +477,7 @@ def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result
                               _p(res.batch_off if rbl else None, _i64p),
                               _p(_c(res.batch_rank, np.int32) if rbl else None, _i32p),
                               _p(_c(res.weight, np.float64) if rbl else None, _f64p),
-                              _p(res.accept if mode == "stencil" else None, _u8p), int(rbl), _p(G, _f64p),
+                              _p(res.core_accept, _u8p), _p(res.accept, _u8p), int(rbl), _p(G, _f64p),
                               _p(g_pos, _f64p), _p(g_q, _f64p), _p(g_sig, _f64p), _p(g_eps, _f64p))
     x_off, x_idx = exclusion_lists(mol)
     L.orc_exclusions_adjoint(ctypes.byref(sy), n, _p(s, _u32p), _p(q, _f64p), _p(x_off, _i64p), _p(x_idx, _i64p),

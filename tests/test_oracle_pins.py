@@ -207,6 +207,42 @@ def test_stencil_candidates_are_the_stencil_cells(orc, name, nrows):
         assert members <= set(got.tolist())
 
 
+def test_skin_lists_match_brute_force(orc):
+    """Lists with a skin: cells of edge >= r_core + skin, C(i) within r_core + skin,
+    S(i) within (r_core - skin, r_shell + skin], canonical order (brute force)."""
+    w = _water("water4k")
+    skin = 0.1
+    s = orc.quantize(w.pos, w.box)
+    rows = np.sort(np.random.default_rng(5).choice(w.n_atoms, size=150, replace=False))
+    lists = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2, rows=rows, skin=skin)
+    n_c = int(math.floor(w.box / (0.5 + skin)))
+    R_ = int(math.floor((1.2 + skin) * n_c / w.box)) + 1
+    t = lambda r: math.floor((r * 2 ** 32 / w.box) ** 2)
+    d = (s[None, :, :].astype(np.int64) - s[rows, None, :].astype(np.int64))
+    d = (d + 2 ** 31) % 2 ** 32 - 2 ** 31
+    d2 = (d * d).sum(axis=2).astype(np.uint64)
+    cell = ((s.astype(np.uint64) * n_c) >> np.uint64(32)).astype(np.int64)
+    for k, i in enumerate(rows):
+        same = (w.molecule == w.molecule[i]) & (w.molecule[i] >= 0)
+        same[i] = True
+
+        def order(js, reach):
+            off = (cell[js] - cell[i]) % n_c
+            off = np.where(off > reach, off - n_c, off)
+            return js[np.lexsort((js, s[js, 0], off[:, 0], off[:, 1], off[:, 2]))]
+
+        core = order(np.flatnonzero((d2[k] <= t(0.5 + skin)) & ~same), 1)
+        shell = order(np.flatnonzero((d2[k] > t(0.5 - skin)) & (d2[k] <= t(1.2 + skin)) & ~same), R_)
+        assert np.array_equal(lists.core_idx[lists.core_off[k]:lists.core_off[k + 1]], core)
+        assert np.array_equal(lists.shell_idx[lists.shell_off[k]:lists.shell_off[k + 1]], shell)
+
+
+def _moved(w, skin, seed=8):
+    """Positions displaced by less than skin / 2 per atom."""
+    h = skin / (2.0 * math.sqrt(3.0)) * 0.999
+    return w.pos + np.random.default_rng(seed).uniform(-h, h, size=w.pos.shape)
+
+
 def test_list_sizes_match_density(orc):
     """Mean list sizes against (4/3) pi r^3 rho (water: the paper's ~700 within 1.2 nm)."""
     w = _water("water4k")
@@ -371,6 +407,49 @@ def test_stencil_sampling_reduces_to_full_list(orc):
     assert np.array_equal(acc, np.diff(lists.shell_off))
 
 
+@pytest.mark.parametrize("mode", ["rbl", "full", "stencil"])
+def test_skin_lists_exact_after_moves(orc, mode):
+    """Lists built with a skin, positions then moved by less than skin / 2: with
+    every list entry taken (p~ above every list length) the short-range force at
+    the new positions is the full-list one of lists built there without a skin."""
+    w = _water("water4k")
+    skin = 0.1
+    big = orc.Params(box=w.box, p_shell=100000, skin=skin)
+    s0 = orc.quantize(w.pos, w.box)
+    s1 = orc.quantize(_moved(w, skin), w.box)
+    lists = orc.build_lists(s0, w.molecule, w.box, 0.5, 1.2, full=mode == "full", stencil=mode == "stencil",
+                            skin=skin)
+    r = orc.forward(None, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, big, mode=mode, s=s1,
+                    lists=lists)
+    ref = orc.forward(None, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, orc.Params(box=w.box),
+                      mode="full", s=s1)
+    assert np.all(r.weight == 1.0) if r.weight is not None else True
+    assert np.abs(r.f_short - ref.f_short).max() < 1e-12 * np.abs(ref.f_short).max()
+
+
+@pytest.mark.slow
+def test_skin_lists_unbiased_over_seeds(orc):
+    """Random batch list over skin lists at moved positions: the mean short-range
+    force over seeds is the full-list one at those positions (z-scores)."""
+    w = _water("water4k")
+    skin = 0.1
+    s0 = orc.quantize(w.pos, w.box)
+    s1 = orc.quantize(_moved(w, skin), w.box)
+    rows = np.arange(0, w.n_atoms, 97)
+    lists = orc.build_lists(s0, w.molecule, w.box, 0.5, 1.2, rows=rows, skin=skin)
+    ref = orc.forward(None, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, orc.Params(box=w.box),
+                      mode="full", s=s1, rows=rows)
+    n_seed = 300
+    f = np.empty((n_seed,) + ref.f_short.shape)
+    for k in range(n_seed):
+        r = orc.forward(None, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps,
+                        orc.Params(box=w.box, seed=7000 + k, skin=skin), mode="rbl", s=s1, rows=rows, lists=lists)
+        f[k] = r.f_short
+    z = (f.mean(axis=0) - ref.f_short) / (f.std(axis=0, ddof=1) / math.sqrt(n_seed))
+    assert abs((z ** 2).mean() - 1.0) < 0.15
+    assert np.abs(z).max() < 5.5
+
+
 @pytest.mark.slow
 def test_stencil_sampling_unbiased_over_seeds(orc):
     """E[w_i sum_B f_ij 1(j in S(i))] with B drawn from K(i) and w_i = |K(i)|/p~
@@ -485,15 +564,20 @@ def _loss(orc, w, p, res, G, s=None, q=None, sig=None, eps=None, mode="rbl"):
                     w.lj_sigma if sig is None else sig, w.lj_eps if eps is None else eps, p, mode=mode,
                     s=res.s if s is None else s, lists=res.lists,
                     batches=(res.batch_off, res.batch_rank, res.weight) if sampled else None,
-                    kspace=(res.kvec, res.wk, res.S), accept=res.accept)
+                    kspace=(res.kvec, res.wk, res.S), accept=res.accept, core_accept=res.core_accept)
     return float((G * r.force).sum())
 
 
-@pytest.mark.parametrize("mode", ["rbl", "full", "stencil"])
-def test_adjoint_matches_central_differences(orc, mode):
-    w = _water()
-    p = orc.Params(box=w.box)
-    res = orc.forward(*_args(w), p, mode=mode)
+@pytest.mark.parametrize("mode,skin", [("rbl", 0.0), ("full", 0.0), ("stencil", 0.0), ("rbl", 0.1)])
+def test_adjoint_matches_central_differences(orc, mode, skin):
+    w = _water() if skin == 0.0 else _water("water4k")
+    p = orc.Params(box=w.box, skin=skin)
+    if skin > 0.0:
+        lists = orc.build_lists(orc.quantize(w.pos, w.box), w.molecule, w.box, 0.5, 1.2, skin=skin)
+        res = orc.forward(_moved(w, skin), w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, mode=mode,
+                          lists=lists)
+    else:
+        res = orc.forward(*_args(w), p, mode=mode)
     G = np.random.default_rng(3).standard_normal(res.force.shape)
     g_pos, g_q, g_sig, g_eps = orc.backward(G, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, res,
                                             mode=mode)
