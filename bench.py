@@ -113,10 +113,10 @@ def rms(a):
     return float(a.double().pow(2).sum(dim=1).mean().sqrt())
 
 
-def forces(make, pos, p_shell, p_kspace, seed, step=7, shell_source="list"):
-    h = make(p_shell, p_kspace, seed, shell_source)
+def forces(make, pos, p_shell, p_kspace, seed, step=7, shell_source="list", skin=0.0, pos_eval=None):
+    h = make(p_shell, p_kspace, seed, shell_source, skin)
     h.build_lists(pos, step)
-    f = h.compute_forces(pos, step).clone()
+    f = h.compute_forces(pos if pos_eval is None else pos_eval, step).clone()
     h.close()
     return f
 
@@ -261,6 +261,61 @@ def stencil_sampling(make, pos, G, w, args, acc, ms_full, timed_steps):
     return out
 
 
+def skin_lists(make, pos, G, w, args, ms_full, timed_steps, every=10):
+    """Lists built with a skin (cells of edge >= r_core + skin, core lists within
+    r_core + skin, shell lists within (r_core - skin, r_shell + skin]) and
+    rebuilt every `every` steps; each force evaluation counts an entry only when
+    it is a member at the evaluation positions. The positions evaluated are the
+    build positions displaced by just under skin / 2 per atom (the largest move
+    the lists allow), so that the membership tests take effect. Per-step rates
+    include the amortized list build. The same is timed for the full list with
+    the same skin (the usual Verlet-list practice), and the shell-sampling error
+    against the full list at the displaced positions, same k-vectors."""
+    import torch
+    n = w.n_atoms
+    P0 = args.p_kspace
+    out = {}
+    gen = torch.Generator(device=pos.device).manual_seed(21)
+    for skin in (0.05, 0.1):
+        half = skin / (2.0 * math.sqrt(3.0)) * 0.999
+        pos_m = pos + (torch.rand(pos.shape, generator=gen, device=pos.device, dtype=torch.float64) * 2.0 - 1.0
+                       ).to(pos.dtype) * half
+        row = {}
+        for kind, ps in (("rbl", args.p_shell), ("full_list", 0)):
+            h = make(ps, P0, 13595, "list", skin)
+
+            def fwd(step):
+                if step % every == 0:
+                    h.build_lists(pos, step)
+                h.compute_forces(pos_m, step)
+
+            def fwd_bwd(step):
+                fwd(step)
+                h.compute_forces_backward(pos_m, step, G)
+
+            ms_f = timed_steps(fwd, every, 3 * every, 9000) * 1e3
+            r = {"atom_steps_per_s": n / (ms_f * 1e-3), "ms_per_step": ms_f}
+            if kind == "rbl":
+                ms_fb = timed_steps(fwd_bwd, every, 2 * every, 9500) * 1e3
+                r.update({"fwd_bwd_atom_steps_per_s": n / (ms_fb * 1e-3), "ms_per_step_fwd_bwd": ms_fb})
+                st = stage_times(h, fwd_bwd, every, 9700)
+                r["stage_ms"] = {k: round(v[0], 4) for k, v in st.items() if v[1]}
+                counts = h.debug("counts")
+                r["list_entries_per_atom"] = {"core": int(counts[0]) / n, "shell": int(counts[1]) / n}
+            h.close()
+            row[kind] = r
+        f_full = forces(make, pos_m, 0, P0, 13595)
+        row["rbl"]["shell_sampling_err"] = rms(forces(make, pos, args.p_shell, P0, 13595, skin=skin,
+                                                      pos_eval=pos_m) - f_full)
+        row["rbl"]["speedup_vs_full_list_every_step"] = ms_full / row["rbl"]["ms_per_step"]
+        row["rbl"]["speedup_vs_full_list_same_skin"] = row["full_list"]["ms_per_step"] / row["rbl"]["ms_per_step"]
+        out[str(skin)] = row
+    out["note"] = (f"skin in nm; lists rebuilt every {every} steps, forces evaluated at positions displaced by just "
+                   f"under skin/2; shell_sampling_err in kJ/mol/nm, RMS over atoms, against the full list at the "
+                   f"displaced positions with the same k-vectors")
+    return out
+
+
 def precision_sweep(timed_steps):
     """FP64 against mixed precision, forward + backward, on the 6,291,456-atom box
     (2,097,152 waters, L = 39.7 nm, p_shell = 100, p = 500): atom-steps/s of
@@ -325,9 +380,9 @@ def main():
     at = torch.tensor(w.atom_type, device=dev)
     mol = torch.tensor(w.molecule, device=dev)
 
-    def make(p_shell, p_kspace, seed=13595, shell_source="list"):
+    def make(p_shell, p_kspace, seed=13595, shell_source="list", skin=0.0):
         h = irbe.Handle(n, w.box, p_shell=p_shell, p_kspace=p_kspace, seed=seed, precision=args.precision,
-                        shell_source=shell_source, device=dev)
+                        shell_source=shell_source, skin=skin, device=dev)
         h.set_system(at, q, mol, w.lj_sigma, w.lj_eps)
         return h
 
@@ -392,6 +447,8 @@ def main():
         acc = accuracy(make, pos, G, w, args, ms, timed_steps)
         log("stencil sampling")
         stencil = stencil_sampling(make, pos, G, w, args, acc, ms_full, timed_steps)
+        log("skin lists")
+        skin = skin_lists(make, pos, G, w, args, ms_full, timed_steps)
         del pos, q, F, G
         torch.cuda.empty_cache()
         log("precision sweep on the 6.3M-atom box")
@@ -408,6 +465,7 @@ def main():
             "roofline": roof,
             "accuracy": acc,
             "stencil_sampling": stencil,
+            "skin_lists": skin,
             "precision_sweep": sweep,
         }
     else:

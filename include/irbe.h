@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define IRBE_ABI_VERSION 1
+#define IRBE_ABI_VERSION 2
 
 typedef struct irbe_ctx* irbe_handle;
 
@@ -107,6 +107,22 @@ typedef struct {
                               then builds no shell list                           */
     uint64_t seed;         /* Philox key                                             */
     double capacity_hint;  /* expected list entries per atom, 0 = from density       */
+    double skin;           /* >= 0: lists kept over several steps (Sec. 2.3 lets the
+                              cells be slightly larger than r_core so that the lists
+                              need not follow every step). Cells of edge
+                              >= r_core + skin, C(i) within r_core + skin, S(i)
+                              within (r_core - skin, r_shell + skin], the full list
+                              within r_shell + skin; compute_forces and
+                              compute_gradients count a core entry only at
+                              r <= r_core and a shell entry only at
+                              r_core < r <= r_shell (full list: r <= r_shell), at
+                              the positions they are given. The result equals that
+                              of lists built at those positions while no atom has
+                              moved more than skin / 2 since build_lists (the caller
+                              tracks that and rebuilds); the shell weight uses the
+                              list length. floor(L / (r_core + skin)) >= 3 and
+                              r_shell + skin < L/2. 0: the lists of Sec. 2.3 as they
+                              are, no membership test at force time.            */
 } irbe_config;
 
 /* Create a handle for one system size and parameter set; work is queued on

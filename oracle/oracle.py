@@ -382,9 +382,13 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
     if lists is None:
         lists = build_lists(s, mol, params.box, params.r_core, params.r_shell, full=full, rows=rows_a,
                             stencil=mode == "stencil", skin=params.skin)
+    # stencil draws are always tested at these positions; list entries only when
+    # the lists were built with a skin (without one they count as built)
     masked = mode == "stencil" or params.skin > 0
     if not masked:
-        accept = core_accept = None
+        accept = None
+    if params.skin <= 0:
+        core_accept = None
     if sampled:
         if batches is None:
             batches = shell_batches(params.seed, step, lists, params.p_shell)
@@ -396,7 +400,7 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
         if accept is None:
             accept = batch_accept(s, mol, params.box, params.r_core, params.r_shell, lists,
                                   batches if sampled else None, kind=1 if sampled else 2)
-        if core_accept is None and not full:
+        if core_accept is None and not full and params.skin > 0:
             core_accept = batch_accept(s, mol, params.box, params.r_core, params.r_shell, lists, None, kind=0)
     if kspace is None:
         if mode == "ewald":

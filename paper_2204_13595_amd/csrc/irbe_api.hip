@@ -102,6 +102,17 @@ hipError_t ensure_buckets(irbe_ctx* h, int64_t records)
     return e;
 }
 
+hipError_t ensure_draw_bits(irbe_ctx* h, size_t words)
+{
+    if (h->draw_bits_words >= words) return hipSuccess;
+    dfree(h, h->draw_bits);
+    h->draw_bits = nullptr;
+    h->draw_bits_words = 0;
+    const hipError_t e = dalloc(h, &h->draw_bits, words);
+    if (e == hipSuccess) h->draw_bits_words = words;
+    return e;
+}
+
 hipError_t ensure_batch_atoms(irbe_ctx* h)
 {
     if (h->batch_j) return hipSuccess;
@@ -113,14 +124,15 @@ hipError_t ensure_batch_atoms(irbe_ctx* h)
 namespace {
 
 // Quantized-geometry constants, in the FP64 operation order that fixes them:
-// n_c = floor(L / r_core), R = floor(r_shell n_c / L) + 1,
-// T = floor(t * t) with t = r 2^32 / L.
+// n_c = floor(L / (r_core + skin)), R = floor((r_shell + skin) n_c / L) + 1,
+// T(r) = floor(t * t) with t = r 2^32 / L.
 void geometry(const irbe_config& c, Geometry& g)
 {
 #pragma clang fp contract(off)
     const double L = c.box_length;
-    g.n_c = (int32_t)std::floor(L / c.r_core);
-    g.reach = (int32_t)std::floor(c.r_shell * (double)g.n_c / L) + 1;
+    const double rc_l = c.r_core + c.skin, rs_l = c.r_shell + c.skin;
+    g.n_c = (int32_t)std::floor(L / rc_l);
+    g.reach = (int32_t)std::floor(rs_l * (double)g.n_c / L) + 1;
     if (2 * g.reach + 1 <= g.n_c) {
         g.lo = -g.reach;
         g.hi = g.reach;
@@ -128,10 +140,16 @@ void geometry(const irbe_config& c, Geometry& g)
         g.lo = -((g.n_c - 1) / 2);
         g.hi = g.lo + g.n_c - 1;
     }
-    const double tc = c.r_core * kTwo32 / L;
-    const double ts = c.r_shell * kTwo32 / L;
-    g.t_core = (uint64_t)std::floor(tc * tc);
-    g.t_shell = (uint64_t)std::floor(ts * ts);
+    auto threshold = [L](double r) {
+        const double t = r * kTwo32 / L;
+        return (uint64_t)std::floor(t * t);
+    };
+    g.t_core = threshold(c.r_core);
+    g.t_shell = threshold(c.r_shell);
+    g.skin = c.skin > 0.0;
+    g.tl_core = threshold(rc_l);
+    g.tl_lo = !g.skin ? g.t_core : (c.r_core > c.skin ? threshold(c.r_core - c.skin) : 0);
+    g.tl_shell = threshold(rs_l);
     g.inv_l = 1.0 / L;
     g.quantum = L / kTwo32;
     g.n_cells = (int64_t)g.n_c * g.n_c * g.n_c;
@@ -308,6 +326,8 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     if (c.n_types < 1 || c.n_types > 16) return fail(nullptr, IRBE_EINVAL, "n_types must be in 1..16");
     if (!(c.capacity_hint >= 0.0) || !std::isfinite(c.capacity_hint))
         return fail(nullptr, IRBE_EINVAL, "bad capacity_hint");
+    if (!(c.skin >= 0.0) || !std::isfinite(c.skin) || !(c.r_shell + c.skin < 0.5 * c.box_length))
+        return fail(nullptr, IRBE_EINVAL, "need skin >= 0 and r_shell + skin < L/2");
     if (c.shell_source != IRBE_SHELL_LIST && c.shell_source != IRBE_SHELL_STENCIL)
         return fail(nullptr, IRBE_EINVAL, "bad shell_source");
     if (c.shell_source == IRBE_SHELL_STENCIL && c.p_shell <= 0)
@@ -324,7 +344,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     geometry(c, h->geo);
     if (h->geo.n_c < 3) {
         delete h;
-        return fail(nullptr, IRBE_EINVAL, "floor(L / r_core) must be >= 3");
+        return fail(nullptr, IRBE_EINVAL, "floor(L / (r_core + skin)) must be >= 3");
     }
     if (h->stencil && (h->geo.hi - h->geo.lo + 1) * (h->geo.hi - h->geo.lo + 1) > 128) {
         delete h;
@@ -418,10 +438,12 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     if (e == hipSuccess) {
         const double L = c.box_length;
         const double rho_n = (double)c.n_atoms / (L * L * L);
-        const double vc = 4.0 / 3.0 * kPi * c.r_core * c.r_core * c.r_core;
-        const double vs = 4.0 / 3.0 * kPi * c.r_shell * c.r_shell * c.r_shell;
+        auto ball = [](double r) { return 4.0 / 3.0 * kPi * r * r * r; };
+        const double vc = ball(c.r_core + c.skin);
+        const double vlo = ball(std::max(c.r_core - c.skin, 0.0));
+        const double vs = ball(c.r_shell + c.skin);
         int32_t cap_c = round_up32(1.3 * rho_n * vc + 32.0);
-        int32_t cap_s = round_up32(1.3 * rho_n * (h->full_list ? vs : vs - vc) + 32.0);
+        int32_t cap_s = round_up32(1.3 * rho_n * (h->full_list ? vs : vs - vlo) + 32.0);
         if (c.capacity_hint > 0.0) cap_s = round_up32(c.capacity_hint);
         if (h->full_list) cap_c = 1;
         if (h->stencil) cap_s = 1;  // no shell list

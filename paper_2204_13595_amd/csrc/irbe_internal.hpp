@@ -57,7 +57,11 @@ struct Geometry {
     int32_t n_c = 0;
     int32_t reach = 0;      // R: shell stencil half-width in cells
     int32_t lo = 0, hi = 0; // shell stencil offsets per axis, inclusive
-    uint64_t t_core = 0, t_shell = 0;
+    uint64_t t_core = 0, t_shell = 0;  // membership at force time: r <= r_core, r <= r_shell
+    // list thresholds: C(i) D^2 <= tl_core, S(i) tl_lo < D^2 <= tl_shell (the
+    // above without a skin; with one, r_core + skin, r_core - skin, r_shell + skin)
+    uint64_t tl_core = 0, tl_lo = 0, tl_shell = 0;
+    bool skin = false;      // lists built with a skin: entries tested at force time
     double inv_l = 0.0;
     double quantum = 0.0;   // L / 2^32
     int64_t n_cells = 0;
@@ -159,6 +163,8 @@ struct irbe_ctx {
                                       // i's molecule), for the adjoint and read-back, allocated on first use
     bool batch_j_valid = false;       // batch_j holds the decode of the current ranks
     int32_t* scell = nullptr;         // [N] stencil sampling: cell of each sorted atom at the last build
+    uint32_t* draw_bits = nullptr;    // Floyd bitmaps in device memory for lists too long for LDS
+    size_t draw_bits_words = 0;
     int32_t p_stride = 0;
     bool ranks_valid = false;         // ranks hold the draw of ranks_step for the current lists
     uint64_t ranks_step = 0;
@@ -201,6 +207,8 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
 hipError_t ensure_buckets(irbe_ctx* h, int64_t records);
 // Stencil sampling: allocate the read-back array of the decoded batch, and fill it.
 hipError_t ensure_batch_atoms(irbe_ctx* h);
+// Device-memory Floyd bitmaps of at least `words` 32-bit words.
+hipError_t ensure_draw_bits(irbe_ctx* h, size_t words);
 hipError_t launch_stencil_decode(irbe_ctx* h);
 hipError_t launch_kspace_adjoint(irbe_ctx* h, const void* grad, void* grad_pos, void* grad_q, double* grad_lj);
 

@@ -55,7 +55,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Integer bounds on the packed squared separation d2: d2 < *_in proves
 // membership of the ball, d2 > *_out proves the opposite.
 struct PackedBounds {
-    uint32_t core_in, core_out, shell_in, shell_out;
+    uint32_t core_in, core_out, shell_in, shell_out, lo_in, lo_out;
 };
 
 __device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
@@ -104,14 +104,16 @@ __device__ __forceinline__ int member_pos(uint32_t mlo, uint32_t mhi, uint32_t l
     return (int)__builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo & lowm, (uint32_t)base));
 }
 
-// MODE: split core and shell lists, one full list, or the core list alone (the
-// shell batch of stencil sampling is drawn from the stencil's cells).
-enum { kListsSplit = 0, kListsFull = 1, kListsCoreOnly = 2 };
+// MODE: split core and shell lists, one full list, the core list alone (the
+// shell batch of stencil sampling is drawn from the stencil's cells), or split
+// lists with a skin, where S(i) starts at its own threshold t_lo below C(i)'s
+// end (the two lists overlap).
+enum { kListsSplit = 0, kListsFull = 1, kListsCoreOnly = 2, kListsSplitSkin = 3 };
 
 template <int MODE>
 __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     int n_c, int lo, int hi, int G, int prune, int trim, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb, uint64_t t_core,
-    uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const int32_t* __restrict__ smol,
+    uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const int32_t* __restrict__ smol,
     const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g, int cap_core, int cap_shell,
     int32_t* __restrict__ core, int32_t* __restrict__ ncore, int32_t* __restrict__ shell,
     int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt)
@@ -164,7 +166,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                 const int y = wrap(cy + dy, n_c);
                 const int row = (z * n_c + y) * n_c;
                 // rows two or more cells away in y or z hold no core candidate:
-                // a whole cell edge (>= r_core) lies between them and the atom
+                // a whole cell edge (>= the core list radius) lies between them and
+                // the atom, and every candidate there lies beyond S(i)'s inner radius
                 const bool core_row = MODE != kListsFull && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
                 // lane's candidate cells in this row: tile cells [u_lo, u_hi]
                 int u_lo = ti, u_hi = ti + span_c - 1;
@@ -292,6 +295,19 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                         m_core = m_keep & ballot(c_in);
                                         m_shell = 0;
                                         m_amb = m_keep & ~ballot(c_out) & ~m_core;
+                                    } else if (CORE && MODE == kListsSplitSkin) {
+                                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
+                                        const bool l_in = d2 < tb.lo_in, l_out = d2 > tb.lo_out;
+                                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
+                                        in_core = k_in & k_mol & c_in;
+                                        in_shell = k_in & k_mol & l_out & s_in;
+                                        const uint64_t b_cin = ballot(c_in), b_lout = ballot(l_out), b_sin = ballot(s_in);
+                                        m_core = m_keep & b_cin;
+                                        m_shell = m_keep & b_lout & b_sin;
+                                        // settled: C(i) either way, and S(i) below t_lo, inside, or beyond t_shell
+                                        const uint64_t set_c = b_cin | ballot(c_out);
+                                        const uint64_t set_s = ballot(l_in) | (b_lout & b_sin) | ballot(s_out);
+                                        m_amb = m_keep & ~(set_c & set_s);
                                     } else if (CORE) {
                                         const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
                                         const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
@@ -312,7 +328,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                         const bool amb = (m_amb >> lane) & 1u;
                                         const uint64_t d2x = dist2_exact(spos[chunk + ka], spos[amb ? (int)r.w : chunk + ka]);
                                         const bool xc = CORE && d2x <= t_core;
-                                        const bool xs = MODE != kListsCoreOnly && !xc && d2x <= t_shell;
+                                        const bool xs = MODE != kListsCoreOnly &&
+                                                        (MODE == kListsSplitSkin ? d2x > t_lo : !xc) && d2x <= t_shell;
                                         in_core = amb ? xc : in_core;
                                         in_shell = amb ? xs : in_shell;
                                         m_core = (m_core & ~m_amb) | (ballot(xc) & m_amb);
@@ -453,10 +470,12 @@ PackedGeometry packed_geometry(const Geometry& g, int G, bool prune)
         while ((o + 1.0) - 2.0 * delta * std::sqrt(3.0 * (o + 1.0)) <= T + 1.0) o += 1.0;
         return o < 4294967295.0 ? (uint32_t)o : 4294967295u;
     };
-    p.tb.core_in = inner(g.t_core);
-    p.tb.core_out = outer(g.t_core);
-    p.tb.shell_in = inner(g.t_shell);
-    p.tb.shell_out = outer(g.t_shell);
+    p.tb.core_in = inner(g.tl_core);
+    p.tb.core_out = outer(g.tl_core);
+    p.tb.shell_in = inner(g.tl_shell);
+    p.tb.shell_out = outer(g.tl_shell);
+    p.tb.lo_in = inner(g.tl_lo);
+    p.tb.lo_out = outer(g.tl_lo);
     return p;
 }
 
@@ -481,14 +500,17 @@ hipError_t launch_build_lists(irbe_ctx* h)
     const int trim = narrow && pg.sh < 16 ? 1 : 0;
     // FP32 threshold of the outermost list with a relative margin of 2e-6, far
     // above the FP32 rounding of the row gaps: the row pruning never drops a member.
-    const float tf_hi = (float)(h->stencil ? g.t_core : g.t_shell) * 1.000002f;
+    const float tf_hi = (float)(h->stencil ? g.tl_core : g.tl_shell) * 1.000002f;
 #define IRBE_LISTS_ARGS                                                                                           \
-    n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.t_core, g.t_shell, tf_hi, h->spos, h->smol,   \
+    n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos, \
+        h->smol,                                                                                                  \
         h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt
     if (h->full_list)
         k_build_lists_tiled<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
     else if (h->stencil)
         k_build_lists_tiled<kListsCoreOnly><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+    else if (g.skin)
+        k_build_lists_tiled<kListsSplitSkin><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
     else
         k_build_lists_tiled<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
 #undef IRBE_LISTS_ARGS

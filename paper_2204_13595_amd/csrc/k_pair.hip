@@ -12,6 +12,9 @@
 // k_stencil_decode, and a drawn atom contributes only when it lies in the
 // shell annulus T_c < D^2 <= T_s at the current positions (i itself and i's
 // molecule come out of the decode as -1).
+// Lists built with a skin (skin): every list entry is tested at the current
+// positions, core entries counting only at D^2 <= T_c, shell entries only at
+// T_c < D^2 <= T_s and full-list entries only at D^2 <= T_s.
 #include <algorithm>
 
 #include "irbe_device.hpp"
@@ -27,15 +30,20 @@ struct PairParams {
     real ke;
 };
 
-// The shell-membership test of stencil sampling on exact squared separations
-// in quanta (O1/O5: T_c < D^2 <= T_s).
-__device__ __forceinline__ bool in_annulus(uint4 a, uint4 b, uint64_t t_lo, uint64_t t_hi)
+// Exact squared separation in quanta (minimum image through 32-bit wrap-around).
+__device__ __forceinline__ uint64_t dist2_q(uint4 a, uint4 b)
 {
     const int32_t dx = (int32_t)(b.x - a.x);
     const int32_t dy = (int32_t)(b.y - a.y);
     const int32_t dz = (int32_t)(b.z - a.z);
-    const uint64_t d2 =
-        (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
+    return (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
+}
+
+// The shell-membership test on exact squared separations in quanta
+// (T_c < D^2 <= T_s), used by stencil sampling and by lists built with a skin.
+__device__ __forceinline__ bool in_annulus(uint4 a, uint4 b, uint64_t t_lo, uint64_t t_hi)
+{
+    const uint64_t d2 = dist2_q(a, b);
     return d2 > t_lo && d2 <= t_hi;
 }
 
@@ -112,15 +120,37 @@ __device__ __forceinline__ void add_pair(PairSum<real>& a, uint4 si, real qi, ui
     }
 }
 
-// One Floyd step: draw r in [0, t], insert r or (if taken) t into the bitmap.
-template <int BLOCK>
-__device__ __forceinline__ int floyd_step(WordStream& st, uint32_t* bitmap, int t)
+// One Floyd step: draw r in [0, t], insert r or (if taken) t into the bitmap
+// (word w of this thread's bitmap at bits[w * stride]).
+__device__ __forceinline__ int floyd_step(WordStream& st, uint32_t* bits, int stride, int t)
 {
     const int r = (int)st.below((uint32_t)t + 1u);
-    const bool taken = (bitmap[(r >> 5) * BLOCK + threadIdx.x] >> (r & 31)) & 1u;
+    const bool taken = (bits[(r >> 5) * stride] >> (r & 31)) & 1u;
     const int v = taken ? t : r;
-    bitmap[(v >> 5) * BLOCK + threadIdx.x] |= 1u << (v & 31);
+    bits[(v >> 5) * stride] |= 1u << (v & 31);
     return v;
+}
+
+// Floyd's algorithm for atom k (sorted index) when N_S > p~: p~ ranks of
+// [0, N_S) without replacement, from the word stream of its caller id.
+__device__ __forceinline__ void floyd_row(int64_t k, int ns, const int32_t* __restrict__ perm, int p_shell,
+                                          int p_stride, uint64_t seed, uint64_t step, uint32_t* bits, int stride,
+                                          uint16_t* __restrict__ ranks)
+{
+    const int words = (ns + 31) >> 5;
+    for (int t = 0; t < words; ++t) bits[t * stride] = 0u;
+    WordStream st(seed, step, (uint32_t)perm[k], kTagShell);
+    uint16_t* out = ranks + k * (int64_t)p_stride;
+    const int t0 = ns - p_shell;
+    int c = 0;
+    for (; c + 4 <= p_shell; c += 4) {
+        const uint32_t v0 = (uint32_t)floyd_step(st, bits, stride, t0 + c);
+        const uint32_t v1 = (uint32_t)floyd_step(st, bits, stride, t0 + c + 1);
+        const uint32_t v2 = (uint32_t)floyd_step(st, bits, stride, t0 + c + 2);
+        const uint32_t v3 = (uint32_t)floyd_step(st, bits, stride, t0 + c + 3);
+        *(uint2*)(out + c) = make_uint2(v0 | (v1 << 16), v2 | (v3 << 16));
+    }
+    for (; c < p_shell; ++c) out[c] = (uint16_t)floyd_step(st, bits, stride, t0 + c);
 }
 
 // ---------------------------------------------------------------------------
@@ -142,20 +172,24 @@ __global__ __launch_bounds__(BLOCK) void k_draw_batches(int64_t n, const int32_t
     if (k >= n) return;
     const int ns = nshell[k];
     if (ns <= p_shell) return;
-    const int words = (ns + 31) >> 5;
-    for (int t = 0; t < words; ++t) bitmap[t * BLOCK + threadIdx.x] = 0u;
-    WordStream st(seed, step, (uint32_t)perm[k], kTagShell);
-    uint16_t* out = ranks + k * (int64_t)p_stride;
-    const int t0 = ns - p_shell;
-    int c = 0;
-    for (; c + 4 <= p_shell; c += 4) {
-        const uint32_t v0 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c);
-        const uint32_t v1 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c + 1);
-        const uint32_t v2 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c + 2);
-        const uint32_t v3 = (uint32_t)floyd_step<BLOCK>(st, bitmap, t0 + c + 3);
-        *(uint2*)(out + c) = make_uint2(v0 | (v1 << 16), v2 | (v3 << 16));
+    floyd_row(k, ns, perm, p_shell, p_stride, seed, step, bitmap + threadIdx.x, BLOCK, ranks);
+}
+
+// The same with the bitmaps in device memory, for lists too long for LDS: a
+// grid of `threads` threads takes the atoms in turn, thread t's bitmap word w
+// at bits[w * threads + t].
+__global__ __launch_bounds__(256) void k_draw_batches_global(int64_t n, const int32_t* __restrict__ perm,
+                                                             const int32_t* __restrict__ nshell, int p_shell,
+                                                             int p_stride, uint64_t seed, uint64_t step,
+                                                             uint32_t* __restrict__ bits, int threads,
+                                                             uint16_t* __restrict__ ranks)
+{
+    const int t = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (t >= threads) return;
+    for (int64_t k = t; k < n; k += threads) {
+        const int ns = nshell[k];
+        if (ns > p_shell) floyd_row(k, ns, perm, p_shell, p_stride, seed, step, bits + t, threads, ranks);
     }
-    for (; c < p_shell; ++c) out[c] = (uint16_t)floyd_step<BLOCK>(st, bitmap, t0 + c);
 }
 
 // Stencil sampling: K(i), the atoms of the shell stencil's cells around atom
@@ -358,7 +392,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
     int p_stride, const uint16_t* __restrict__ ranks, StencilArgs sa, uint64_t t_core, uint64_t t_shell,
-    real* __restrict__ fsr, double* __restrict__ part)
+    bool skin, real* __restrict__ fsr, double* __restrict__ part)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -451,26 +485,36 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const real qj1 = sqr[max(js1, 0)];
         const uint4 pjx = kFold ? pjc : spos[max(jx, 0)];
         const real qjx = kFold ? qjc : sqr[max(jx, 0)];
+        // skin: a core entry counts inside r_core, a list shell entry inside the annulus
+        // (the whole ball in full-list mode), at these positions
+        auto core_ok = [&](uint4 sj) { return !skin || dist2_q(si, sj) <= t_core; };
+        auto shell_ok = [&](uint4 sj) {
+            if (!skin) return true;
+            const uint64_t d2 = dist2_q(si, sj);
+            return d2 <= t_shell && (FULL || d2 > t_core);
+        };
         if (kFold) {
-            if (jc >= 0) add_pair_or_excl(pc, px, si, qi, pjc, qjc, lrow, pp, lane >= nc);
+            if (jc >= 0 && (lane >= nc || core_ok(pjc))) add_pair_or_excl(pc, px, si, qi, pjc, qjc, lrow, pp, lane >= nc);
         } else {
-            if (jc >= 0) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
+            if (jc >= 0 && core_ok(pjc)) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
             if (jx >= 0) add_excl<real, EV>(px, si, qi, pjx, qjx, pp);
         }
-        if (STENCIL ? stencil_member(a, js0, mi, mj0, si, pj0, t_core, t_shell) : js0 >= 0)
+        if (STENCIL ? stencil_member(a, js0, mi, mj0, si, pj0, t_core, t_shell) : (js0 >= 0 && shell_ok(pj0)))
             add_pair<real, EV>(ps, si, qi, pj0, qj0, lrow, pp);
-        if (STENCIL ? stencil_member(a, js1, mi, mj1, si, pj1, t_core, t_shell) : js1 >= 0)
+        if (STENCIL ? stencil_member(a, js1, mi, mj1, si, pj1, t_core, t_shell) : (js1 >= 0 && shell_ok(pj1)))
             add_pair<real, EV>(ps, si, qi, pj1, qj1, lrow, pp);
         // the rest (long lists and large batches)
         if (kFold) {
             for (int c = lane + 64; c < nc + xr.y; c += 64) {
                 const int j = c < nc ? crow[c] : sxidx[xr.x + c - nc];
-                add_pair_or_excl(pc, px, si, qi, spos[j], sqr[j], lrow, pp, c >= nc);
+                const uint4 sj = spos[j];
+                if (c >= nc || core_ok(sj)) add_pair_or_excl(pc, px, si, qi, sj, sqr[j], lrow, pp, c >= nc);
             }
         } else {
             for (int c = lane + 64; c < nc; c += 64) {
                 const int j = crow[c];
-                add_pair<real, EV>(pc, si, qi, spos[j], sqr[j], lrow, pp);
+                const uint4 sj = spos[j];
+                if (core_ok(sj)) add_pair<real, EV>(pc, si, qi, sj, sqr[j], lrow, pp);
             }
             for (int c = lane + 64; c < xr.y; c += 64) {
                 const int j = sxidx[xr.x + c];
@@ -493,7 +537,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
                     add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
             } else {
                 const int j = srow[sample ? (int)rrow[c] : c];
-                add_pair<real, EV>(ps, si, qi, spos[j], sqr[j], lrow, pp);
+                const uint4 sj = spos[j];
+                if (shell_ok(sj)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
             }
         }
         // one set of sums: the excluded-pair forces cancel pairwise, so the momentum
@@ -572,17 +617,28 @@ static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
     const int words = (h->max_shell + 31) / 32;
     int block = 256;
     while (block > 64 && (size_t)words * block * 4 > 32 * 1024) block /= 2;
+    if (block == 64 && (size_t)words * block * 4 > 64 * 1024) block = 32;
     const size_t lds = (size_t)words * block * 4;
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)blocks_for(n, block);
-    if (block == 256)
+    if (lds > 64 * 1024) {
+        // bitmaps in device memory: as many threads as fit 1 GiB of bitmaps
+        const int64_t threads = std::max<int64_t>(256, std::min<int64_t>(n, ((int64_t)1 << 28) / words) / 256 * 256);
+        hipError_t e = ensure_draw_bits(h, (size_t)threads * (size_t)words);
+        if (e != hipSuccess) return e;
+        k_draw_batches_global<<<(unsigned)(threads / 256), 256, 0, h->stream>>>(
+            n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride, h->cfg.seed, step, h->draw_bits, (int)threads,
+            h->ranks);
+    } else if (block == 256)
         k_draw_batches<256><<<nb, 256, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
                                                          h->cfg.seed, step, h->ranks);
     else if (block == 128)
         k_draw_batches<128><<<nb, 128, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
                                                          h->cfg.seed, step, h->ranks);
-    else
+    else if (block == 64)
         k_draw_batches<64><<<nb, 64, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
+                                                       h->cfg.seed, step, h->ranks);
+    else
+        k_draw_batches<32><<<nb, 32, lds, h->stream>>>(n, h->perm, h->nshell, h->cfg.p_shell, h->p_stride,
                                                        h->cfg.seed, step, h->ranks);
     const hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
@@ -610,7 +666,7 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     k_pair_coop<real, FULL, EV, STENCIL><<<nb, kCoopBlock, 0, h->stream>>>(
         n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
-        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part);
+        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
     return hipGetLastError();
 }
@@ -834,7 +890,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const real* __restrict__ ljraw_g, int n_types, int p_shell,
     int p_stride, const uint16_t* __restrict__ ranks, const int32_t* __restrict__ batch_j, uint64_t t_core,
-    uint64_t t_shell, const real* __restrict__ gs, const double* __restrict__ gmean_d,
+    uint64_t t_shell, bool skin, const real* __restrict__ gs, const double* __restrict__ gmean_d,
     real* __restrict__ gself, real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat,
     double* __restrict__ ljpart, BucketArgs bk, int rec_cap)
 {
@@ -1036,13 +1092,20 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const real qj1 = sqr[i1];
         (void)jx;
         (void)ix;
-        if (jc >= 0) sym_pair(pjc, qjc, gcx, gcy, gcz, lane >= nsym);
-        if (js0 >= 0 && (!STENCIL || in_annulus(si, pj0, t_core, t_shell))) shell_pair(js0, pj0, qj0);
-        if (js1 >= 0 && (!STENCIL || in_annulus(si, pj1, t_core, t_shell))) shell_pair(js1, pj1, qj1);
+        // skin: a symmetric-list entry counts inside r_core (r_shell for the full
+        // list), a list shell entry inside the annulus, at these positions
+        const uint64_t t_sym = FULL ? t_shell : t_core;
+        auto sym_ok = [&](uint4 sj) { return !skin || dist2_q(si, sj) <= t_sym; };
+        const bool shell_test = STENCIL || skin;
+        if (jc >= 0 && (lane >= nsym || sym_ok(pjc))) sym_pair(pjc, qjc, gcx, gcy, gcz, lane >= nsym);
+        if (js0 >= 0 && (!shell_test || in_annulus(si, pj0, t_core, t_shell))) shell_pair(js0, pj0, qj0);
+        if (js1 >= 0 && (!shell_test || in_annulus(si, pj1, t_core, t_shell))) shell_pair(js1, pj1, qj1);
         // the rest (long lists and large batches)
         for (int c = lane + 64; c < nsym + xr.y; c += 64) {
             const int j = c < nsym ? srow_sym[c] : sxidx[xr.x + c - nsym];
-            sym_pair(spos[j], sqr[j], gs[3 * (int64_t)j], gs[3 * (int64_t)j + 1], gs[3 * (int64_t)j + 2], c >= nsym);
+            const uint4 sj = spos[j];
+            if (c >= nsym || sym_ok(sj))
+                sym_pair(sj, sqr[j], gs[3 * (int64_t)j], gs[3 * (int64_t)j + 1], gs[3 * (int64_t)j + 2], c >= nsym);
         }
         if (!FULL)
             for (int c = lane + 128; c < cnt; c += 64) {
@@ -1053,7 +1116,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                     if (in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, sqr[j]);
                 } else {
                     const int j = srow[sample ? (int)rrow[c] : c];
-                    shell_pair(j, spos[j], sqr[j]);
+                    const uint4 sj = spos[j];
+                    if (!skin || in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, sqr[j]);
                 }
             }
         rx = wave_sum_r(rx);
@@ -1246,7 +1310,7 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
     k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL><<<nb, kCoopBlock, lds, h->stream>>>(
         n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
-        h->p_stride, h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
+        h->p_stride, h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, h->geo.skin, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
         (real*)h->gqscat, h->ljpart, bk, rec_cap);
     e = hipGetLastError();
     if (e != hipSuccess || !BK) return e;

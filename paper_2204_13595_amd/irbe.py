@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libirbe.so")
 
-IRBE_ABI_VERSION = 1
+IRBE_ABI_VERSION = 2
 IRBE_MIXED_FP32 = 0
 IRBE_FP64 = 1
 IRBE_ENERGY = 1
@@ -54,7 +54,7 @@ class Config(ctypes.Structure):
         ("box_length", ctypes.c_double), ("ewald_beta", ctypes.c_double), ("coulomb_k", ctypes.c_double),
         ("r_core", ctypes.c_double), ("r_shell", ctypes.c_double), ("p_shell", ctypes.c_int32),
         ("p_kspace", ctypes.c_int32), ("n_types", ctypes.c_int32), ("shell_source", ctypes.c_int32),
-        ("seed", ctypes.c_uint64), ("capacity_hint", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("capacity_hint", ctypes.c_double), ("skin", ctypes.c_double),
     ]
 
 
@@ -107,7 +107,7 @@ class Handle:
     def __init__(self, n_atoms: int, box: float, *, beta: float = 3.0, r_core: float = 0.5, r_shell: float = 1.2,
                  p_shell: int = 100, p_kspace: int = 100, seed: int = 13595, n_types: int = 2,
                  precision: str = "mixed", coulomb_k: float = 138.935458, capacity_hint: float = 0.0,
-                 shell_source: str = "list", device: torch.device | str | None = None):
+                 shell_source: str = "list", skin: float = 0.0, device: torch.device | str | None = None):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the IRBE HIP library needs a GPU")
@@ -117,7 +117,8 @@ class Handle:
         self.n_types = int(n_types)
         self.cfg = Config(IRBE_ABI_VERSION, IRBE_FP64 if precision == "fp64" else IRBE_MIXED_FP32, self.n_atoms,
                           float(box), float(beta), float(coulomb_k), float(r_core), float(r_shell), int(p_shell),
-                          int(p_kspace), self.n_types, SHELL_SOURCE[shell_source], int(seed), float(capacity_hint))
+                          int(p_kspace), self.n_types, SHELL_SOURCE[shell_source], int(seed), float(capacity_hint),
+                          float(skin))
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             h = ctypes.c_void_p()

@@ -38,8 +38,9 @@ def test_config_layout_matches_header():
 #include <stdio.h>
 #include "irbe.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(irbe_config), offsetof(irbe_config, n_atoms),
-         offsetof(irbe_config, p_shell), offsetof(irbe_config, seed), offsetof(irbe_config, capacity_hint));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(irbe_config), offsetof(irbe_config, n_atoms),
+         offsetof(irbe_config, p_shell), offsetof(irbe_config, seed), offsetof(irbe_config, capacity_hint),
+         offsetof(irbe_config, skin));
   return 0;
 }
 '''
@@ -51,7 +52,7 @@ int main(void) {
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     C = irbe.Config
     assert [int(x) for x in out] == [ctypes.sizeof(C), C.n_atoms.offset, C.p_shell.offset, C.seed.offset,
-                                     C.capacity_hint.offset]
+                                     C.capacity_hint.offset, C.skin.offset]
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

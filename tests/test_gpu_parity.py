@@ -330,3 +330,30 @@ def test_electrolyte_parity(orc, valence, precision, tol_f, tol_g):
     assert np.abs(gl[:4] - r_sig).max() < tol_g * np.abs(r_sig).max() * 10
     assert np.abs(gl[4:] - r_eps).max() < tol_g * np.abs(r_eps).max() * 10
     h.close()
+
+
+def test_long_shell_lists_draw_bit_exact(orc):
+    """Shell lists longer than 16384 entries (r_shell = 3.5 nm on water32k):
+    the Floyd bitmaps of the batch draw no longer fit LDS and live in device
+    memory; N_S and the drawn ranks of sampled rows against the oracle."""
+    from paper_2204_13595_amd import irbe
+    w = inputs.workload("water32k")
+    dev = torch.device("cuda", 0)
+    step = 4
+    h = irbe.Handle(w.n_atoms, w.box, r_shell=3.5, p_shell=100, p_kspace=10, device=dev)
+    pos = torch.tensor(w.pos, dtype=torch.float32, device=dev)
+    h.set_system(torch.tensor(w.atom_type, device=dev), torch.tensor(w.charge, dtype=torch.float32, device=dev),
+                 torch.tensor(w.molecule, device=dev), w.lj_sigma, w.lj_eps)
+    h.build_lists(pos, step)
+    h.compute_forces(pos, step)
+    rows = np.sort(np.random.default_rng(6).choice(w.n_atoms, size=200, replace=False))
+    got_off = h.debug_rows("shell_off", rows)
+    got_rank = h.debug_rows("batch_rank", rows)
+    h.close()
+    s = orc.quantize(pos.double().cpu().numpy(), w.box)
+    lists = orc.build_lists(s, w.molecule, w.box, 0.5, 3.5, rows=rows)
+    assert np.array_equal(got_off, lists.shell_off)
+    ns = np.diff(lists.shell_off)
+    assert ns.min() > 16384
+    ref = np.concatenate([orc.shell_ranks(13595, step, int(i), int(n), 100) for i, n in zip(rows, ns)])
+    assert np.array_equal(got_rank, ref)
