@@ -314,6 +314,20 @@ static uint32_t orc_stream_next(orc_stream* st)
     return st->buf[st->pos++];
 }
 
+/* Words of the Langevin thermostat noise: for atom c0 = 0 .. n-1 the four
+ * words of the Philox block with counter (c0, 2^31, step low, 2 * step high)
+ * under the key seed. The shell batch streams use blocks below 2^31 (a row
+ * would need 2^33 draws to reach it) and the k draw has tag 1 in c3, so the
+ * three never share a counter. */
+void orc_noise_words(uint64_t seed, uint64_t step, int64_t n, uint32_t* out)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t ctr[4] = {(uint32_t)i, 0x80000000u, (uint32_t)step, (uint32_t)(step >> 32) << 1};
+        orc_philox4x32_10(ctr, key, out + 4 * i);
+    }
+}
+
 /* Uniform integer in [0, n), n >= 1: Lemire's multiply-shift with rejection
  * ("Fast random integer generation in an interval", 2019). */
 static uint32_t orc_uniform_below(orc_stream* st, uint32_t n)

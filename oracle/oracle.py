@@ -72,6 +72,7 @@ def lib():
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int, _i64p, ctypes.c_int64,
                                       _i64p, _i32p, _i64p, _i32p]
         L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.orc_noise_words.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, _u32p]
         L.orc_shell_ranks.restype = ctypes.c_int32
         L.orc_shell_ranks.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.c_int32, _i32p]
