@@ -71,7 +71,8 @@ typedef enum {
     IRBE_ECAPACITY = -4,    /* a list would exceed the hard capacity limit      */
     IRBE_ESTATE = -5,       /* call out of order (e.g. forces before lists)      */
     IRBE_EUNSUPPORTED = -6, /* valid but outside what this build supports       */
-    IRBE_ENONFINITE = -7    /* non-finite position seen on the device            */
+    IRBE_ENONFINITE = -7,   /* non-finite position seen on the device            */
+    IRBE_ECONVERGENCE = -8  /* a constraint iteration did not converge           */
 } irbe_status;
 
 enum { IRBE_MIXED_FP32 = 0, IRBE_FP64 = 1 };
@@ -255,6 +256,102 @@ const char* irbe_last_error(irbe_handle h);
 
 /* Wait for the handle's work and free everything it owns. */
 irbe_status irbe_destroy(irbe_handle h);
+
+/* ------------------------------------------------------------------------
+ * Langevin dynamics (Algorithm 1's last step, "integrate the equations of
+ * motion with a thermostat"): the underdamped Langevin equations of Sec. 3,
+ * m dv = (F - gamma m v) dt + sqrt(2 gamma m kT) dW, gamma a rate (1/ps),
+ * by the splitting kick - drift - noise - drift in leapfrog form with one force
+ * evaluation per step, and rigid bond lengths within groups of at most three
+ * atoms (rigid water). One step from constrained positions x, velocities v and
+ * forces F(x), with w = 1/m:
+ *   v += h w F; constrain v (relative velocity along every constraint vector
+ *   r_k = x_q - x_p made zero by multiples of r_k weighted by w);
+ *   y = x + h/2 v; v = a v + sqrt((1 - a^2) kT w) xi, a = exp(-gamma h);
+ *   y += h/2 v; x' = y moved along the r_k (weighted by w) until every
+ *   |x'_q - x'_p| equals its length (Newton's method, relative tolerance 1e-14
+ *   on the squared lengths); v += (x' - y) / h.
+ * xi: per atom, the Philox4x32-10 block of counter (atom, 2^31, step low,
+ * 2 * step high) under the key seed, Box-Muller on the word pairs (w0, w1) and
+ * (w2, w3) with u = (w + 1) 2^-32 and angle 2 pi w 2^-32. Positions are not
+ * wrapped. All state is FP64 (device), in caller atom order.
+ * ------------------------------------------------------------------------ */
+typedef struct irbe_dyn_ctx* irbe_dyn_handle;
+
+/* irbe_dyn_config.thermostat */
+enum { IRBE_LANGEVIN = 0, IRBE_NOSE_HOOVER = 1 };
+
+typedef struct {
+    int32_t abi_version;     /* IRBE_ABI_VERSION                                        */
+    int32_t force_precision; /* type of the force read and the position copy written:
+                                IRBE_MIXED_FP32 float, IRBE_FP64 double                */
+    int64_t n_atoms;         /* N >= 1                                                  */
+    int64_t n_groups;        /* constraint groups, 1 <= G <= N                          */
+    double dt;               /* h > 0 (ps)                                              */
+    double gamma;            /* friction rate >= 0 (1/ps)                               */
+    double kT;               /* >= 0 (kJ/mol)                                           */
+    uint64_t seed;           /* Philox key of the thermostat noise                      */
+    int32_t thermostat;      /* IRBE_LANGEVIN, or IRBE_NOSE_HOOVER (the paper's water runs,
+                                Sec. 4): the noise step becomes v = exp(-xi h) v (gamma
+                                and seed unused) and after the step
+                                xi += h (2 K / (n_dof kT) - 1) / tau^2, K the kinetic
+                                energy of the new velocities, n_dof = 3 N - (constraints)
+                                - 3, xi = 0 at create                                   */
+    int32_t reserved;        /* 0                                                       */
+    double tau;              /* Nose-Hoover period (ps), > 0 with IRBE_NOSE_HOOVER      */
+} irbe_dyn_config;
+
+/* New integrator on hip_stream (a hipStream_t; NULL = the default stream).
+ * IRBE_EINVAL for a bad configuration (message in irbe_dyn_last_error(NULL)). */
+irbe_status irbe_dyn_create(const irbe_dyn_config* cfg, void* hip_stream, irbe_dyn_handle* out);
+
+/* Topology (device arrays, copied; waits on the stream):
+ *   inv_mass[N] (> 0), groups[G][3] (atom indices, -1 = empty slot; slot 0 used;
+ *   every atom in exactly one slot), lengths[G][3] (>= 0: the lengths of the
+ *   slot pairs (0,1), (0,2), (1,2); a constraint where both slots are used and
+ *   the length is > 0). IRBE_EINVAL if any of this does not hold. */
+irbe_status irbe_dyn_set_system(irbe_dyn_handle d, const double* inv_mass, const int32_t* groups,
+                                const double* lengths);
+
+/* One step in place: pos[N][3], vel[N][3] (device, FP64), force[N][3] (device,
+ * float or double per force_precision) = F(pos); `step` keys the noise.
+ * pos_copy[N][3] (device, force precision, or NULL) receives the new positions
+ * for the next force evaluation. Does not wait; a non-finite result or a
+ * constraint iteration that did not converge is reported by irbe_dyn_check. */
+irbe_status irbe_dyn_step(irbe_dyn_handle d, double* pos, double* vel, const void* force, uint64_t step,
+                          void* pos_copy);
+
+/* out[0] (device FP64) = sum_i m_i |v_i|^2 / 2 (fixed-order sum). Does not wait. */
+irbe_status irbe_dyn_kinetic(irbe_dyn_handle d, const double* vel, double* out);
+
+/* out[0] (device FP64) = (1/m) sum_t |pos[sel[t]] - ref[sel[t]]|^2 over the m
+ * selected atoms (unwrapped positions; the mean-squared displacement). Does not wait. */
+irbe_status irbe_dyn_msd(irbe_dyn_handle d, const double* pos, const double* ref, const int32_t* sel, int64_t m,
+                         double* out);
+
+/* Adds to hist[n_bins] (device uint64) the pairs a < b of the m selected atoms
+ * by minimum-image distance r in a cubic box of edge `box` (FP64 without fused
+ * operations: d = x_b - x_a - box rint((x_b - x_a) / box) per axis,
+ * r = sqrt(d.d)), bin floor(r / (r_max / n_bins)) clamped to the last, r < r_max
+ * only; 1 <= n_bins <= 8192. O(m^2) work: an analysis of small systems (the
+ * radial distribution function g(r) follows on the host). Does not wait. */
+irbe_status irbe_dyn_rdf(irbe_dyn_handle d, const double* pos, const int32_t* sel, int64_t m, double box,
+                         double r_max, int32_t n_bins, uint64_t* hist);
+
+/* out[0..1] (device FP64) = the Nose-Hoover state {xi, sum over steps of h xi}
+ * (both 0 with IRBE_LANGEVIN); the quantity U + K + n_dof kT (tau^2 xi^2 / 2 +
+ * sum h xi) is conserved by the Nose-Hoover equations. Does not wait. */
+irbe_status irbe_dyn_thermostat_state(irbe_dyn_handle d, double* out);
+
+/* n_dof = 3 N - (constraints) - 3 of the topology set (-1 before set_system or for NULL). */
+int64_t irbe_dyn_degrees_of_freedom(irbe_dyn_handle d);
+
+/* Waits on the stream and reports device conditions since the last check:
+ * IRBE_ENONFINITE (non-finite position or velocity), IRBE_ECONVERGENCE. */
+irbe_status irbe_dyn_check(irbe_dyn_handle d);
+
+const char* irbe_dyn_last_error(irbe_dyn_handle d);  /* NULL: the last create failure */
+irbe_status irbe_dyn_destroy(irbe_dyn_handle d);
 
 #ifdef __cplusplus
 }

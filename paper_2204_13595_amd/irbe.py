@@ -32,14 +32,25 @@ _DBG_DTYPE = {1: np.int64, 2: np.int64, 3: np.int64, 4: np.int32, 5: np.int64, 6
               8: np.int32, 9: np.int32, 10: np.float64, 11: np.float64, 12: np.float64, 13: np.int64, 14: np.int32}
 
 STATUS = {0: "IRBE_OK", -1: "IRBE_EINVAL", -2: "IRBE_ENOMEM", -3: "IRBE_EHIP", -4: "IRBE_ECAPACITY",
-          -5: "IRBE_ESTATE", -6: "IRBE_EUNSUPPORTED", -7: "IRBE_ENONFINITE"}
+          -5: "IRBE_ESTATE", -6: "IRBE_EUNSUPPORTED", -7: "IRBE_ENONFINITE", -8: "IRBE_ECONVERGENCE"}
 
 EXPORTED = ("irbe_create", "irbe_set_system", "irbe_update_parameters", "irbe_build_lists", "irbe_compute_forces",
             "irbe_compute_forces_backward", "irbe_sync", "irbe_enable_timing", "irbe_get_timing", "irbe_get_debug",
-            "irbe_get_debug_rows", "irbe_last_error", "irbe_destroy")
+            "irbe_get_debug_rows", "irbe_last_error", "irbe_destroy", "irbe_dyn_create", "irbe_dyn_set_system",
+            "irbe_dyn_step", "irbe_dyn_kinetic", "irbe_dyn_msd", "irbe_dyn_rdf", "irbe_dyn_thermostat_state",
+            "irbe_dyn_degrees_of_freedom", "irbe_dyn_check", "irbe_dyn_last_error", "irbe_dyn_destroy")
 
 STAGES = ("bin", "lists", "quantize", "ksample", "rho", "pair", "pair_reduce", "kspace", "energy", "grad_gather",
           "rho_adj", "pair_adj", "kspace_adj")
+
+
+class DynConfig(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32), ("force_precision", ctypes.c_int32), ("n_atoms", ctypes.c_int64),
+        ("n_groups", ctypes.c_int64), ("dt", ctypes.c_double), ("gamma", ctypes.c_double), ("kT", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("thermostat", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+    ]
 
 
 class IRBEError(RuntimeError):
@@ -85,8 +96,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.irbe_last_error.argtypes = [vp]
     L.irbe_last_error.restype = ctypes.c_char_p
     L.irbe_destroy.argtypes = [vp]
+    L.irbe_dyn_create.argtypes = [ctypes.POINTER(DynConfig), vp, ctypes.POINTER(vp)]
+    L.irbe_dyn_set_system.argtypes = [vp, vp, vp, vp]
+    L.irbe_dyn_step.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp]
+    L.irbe_dyn_kinetic.argtypes = [vp, vp, vp]
+    L.irbe_dyn_msd.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp]
+    L.irbe_dyn_rdf.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp]
+    L.irbe_dyn_thermostat_state.argtypes = [vp, vp]
+    L.irbe_dyn_degrees_of_freedom.argtypes = [vp]
+    L.irbe_dyn_check.argtypes = [vp]
+    L.irbe_dyn_last_error.argtypes = [vp]
+    L.irbe_dyn_last_error.restype = ctypes.c_char_p
+    L.irbe_dyn_destroy.argtypes = [vp]
+    L.irbe_dyn_degrees_of_freedom.restype = ctypes.c_int64
     for name in EXPORTED:
-        if name != "irbe_last_error":
+        if name not in ("irbe_last_error", "irbe_dyn_last_error", "irbe_dyn_degrees_of_freedom"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

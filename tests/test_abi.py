@@ -41,6 +41,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(irbe_config), offsetof(irbe_config, n_atoms),
          offsetof(irbe_config, p_shell), offsetof(irbe_config, seed), offsetof(irbe_config, capacity_hint),
          offsetof(irbe_config, skin));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(irbe_dyn_config), offsetof(irbe_dyn_config, n_atoms),
+         offsetof(irbe_dyn_config, dt), offsetof(irbe_dyn_config, kT), offsetof(irbe_dyn_config, seed),
+         offsetof(irbe_dyn_config, tau));
   return 0;
 }
 '''
@@ -51,8 +54,11 @@ int main(void) {
         subprocess.run(["gcc", "-std=c99", f"-I{os.path.dirname(HEADER)}", c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     C = irbe.Config
-    assert [int(x) for x in out] == [ctypes.sizeof(C), C.n_atoms.offset, C.p_shell.offset, C.seed.offset,
-                                     C.capacity_hint.offset, C.skin.offset]
+    assert [int(x) for x in out[:6]] == [ctypes.sizeof(C), C.n_atoms.offset, C.p_shell.offset, C.seed.offset,
+                                         C.capacity_hint.offset, C.skin.offset]
+    D = irbe.DynConfig
+    assert [int(x) for x in out[6:]] == [ctypes.sizeof(D), D.n_atoms.offset, D.dt.offset, D.kT.offset,
+                                         D.seed.offset, D.tau.offset]
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
