@@ -449,7 +449,16 @@ typedef struct {
     double beta;     /* Ewald splitting: the paper's alpha is beta^2 */
     double ke;       /* Coulomb constant */
     int32_t n_types; /* LJ tables are n_types x n_types, entry [t_i * n_types + t_j] */
+    double lj_cut;   /* > 0: LJ only at r < lj_cut sigma_ij, shifted by -u_LJ(lj_cut sigma_ij) (the
+                        shifted-truncated LJ of the primitive-model electrolytes, Sec. 4, with
+                        lj_cut = 2^(1/6)); 0: LJ over every listed pair, unshifted */
 } orc_system;
+
+/* Whether the LJ term acts at distance r (pair parameters sig). */
+static inline int orc_lj_on(const orc_system* sy, double sig, double r)
+{
+    return sy->lj_cut <= 0.0 || r < sy->lj_cut * sig;
+}
 
 /* Pair force f_ij = phi(r) r_ij of Eq. (2.10) (erfc + Gaussian Coulomb, LJ),
  * and the pair energy u_ij = ke q_i q_j erfc(beta r)/r + 4 eps((s/r)^12-(s/r)^6)
@@ -462,10 +471,14 @@ static void orc_pair(const orc_system* sy, double qi, double qj, double sig, dou
     double gauss = 2.0 * b / sqrt(ORC_PI) * exp(-b * b * r * r);
     double coul = -sy->ke * qi * qj * (erfc_br / (r * r) + gauss / r) / r;
     double lj = 0.0, ulj = 0.0;
-    if (eps != 0.0) {
+    if (eps != 0.0 && orc_lj_on(sy, sig, r)) {
         double s6 = pow(sig, 6), s12 = s6 * s6;
         lj = -eps * (48.0 * s12 / pow(r, 14) - 24.0 * s6 / pow(r, 8));
         ulj = 4.0 * eps * (s12 / pow(r, 12) - s6 / pow(r, 6));
+        if (sy->lj_cut > 0.0) {
+            double k6 = pow(sy->lj_cut, -6);
+            ulj -= 4.0 * eps * (k6 * k6 - k6);
+        }
     }
     *phi = coul + lj;
     *u_coul = sy->ke * qi * qj * erfc_br / r;
@@ -729,7 +742,7 @@ int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, 
                 double phi = -ke * q[i] * q[j] * (A + B);
                 double dphi = -ke * q[i] * q[j] * (dA + dB);
                 double C = 0.0, dC = 0.0, dC_dsig = 0.0;
-                if (eps != 0.0 || sig != 0.0) {
+                if ((eps != 0.0 || sig != 0.0) && orc_lj_on(sy, sig, r)) {
                     C = 48.0 * pow(sig, 12) / pow(r, 14) - 24.0 * pow(sig, 6) / pow(r, 8);
                     dC = -672.0 * pow(sig, 12) / pow(r, 15) + 192.0 * pow(sig, 6) / pow(r, 9);
                     dC_dsig = 576.0 * pow(sig, 11) / pow(r, 14) - 144.0 * pow(sig, 5) / pow(r, 8);

@@ -41,7 +41,7 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 class _System(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double), ("beta", ctypes.c_double), ("ke", ctypes.c_double),
-                ("n_types", ctypes.c_int32)]
+                ("n_types", ctypes.c_int32), ("lj_cut", ctypes.c_double)]
 
 
 def build_library() -> str:
@@ -130,13 +130,14 @@ class Params:
     ke: float = COULOMB_K
     n_types: int = 2
     skin: float = 0.0      # lists kept over steps: cells and list radii enlarged by the skin
+    lj_cut: float = 0.0    # > 0: LJ truncated at lj_cut * sigma_ij and shifted to zero there
 
     @property
     def alpha(self) -> float:
         return self.beta * self.beta
 
     def system(self) -> _System:
-        return _System(self.box, self.beta, self.ke, self.n_types)
+        return _System(self.box, self.beta, self.ke, self.n_types, self.lj_cut)
 
 
 # --------------------------------------------------------------------------- geometry

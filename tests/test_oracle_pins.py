@@ -683,3 +683,87 @@ def test_ewald_virial_tensor_is_shear_derivative(orc):
             us.append(_ewald_energy_sheared(w, frac, e @ h0, pairs, p.beta, p.ke, p.r_shell, m))
         dudeps = (us[0] - us[1]) / (2.0 * delta)
         assert abs(res.energy[c] + dudeps) < 1e-6 * np.abs(res.energy[5:8]).max(), ((a, b), res.energy[c], dudeps)
+
+
+# --------------------------------------------------------------------------- shifted-truncated LJ
+
+WCA = 2.0 ** (1.0 / 6.0)
+
+
+def test_shifted_truncated_lj_closed_form(orc):
+    """Two neutral atoms (sigma = eps = 1): with the cutoff at 2^(1/6) sigma the
+    LJ energy is 4((1/r)^12 - (1/r)^6) + 1 inside and 0 outside, the force
+    24(2 r^-13 - r^-7) along the separation inside and 0 outside."""
+    p = orc.Params(box=10.0, beta=1.0, r_core=1.5, r_shell=3.0, p_kspace=10, ke=1.0, lj_cut=WCA)
+    for r in (0.9, 1.0, 1.1, WCA * (1 - 1e-6), WCA * (1 + 1e-6), 1.5, 2.5):
+        pos = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+        res = orc.forward(pos, np.zeros(2), np.zeros(2, np.int32), np.array([-1, -1], np.int32), np.ones(4),
+                          np.ones(4), p, mode="full")
+        rq = (orc.quantize(pos, 10.0)[1, 0] - orc.quantize(pos, 10.0)[0, 0]) * 10.0 / 2 ** 32
+        u = 4.0 * (rq ** -12 - rq ** -6) + 1.0 if rq < WCA else 0.0
+        f = 24.0 * (2.0 * rq ** -13 - rq ** -7) if rq < WCA else 0.0
+        assert abs(res.energy[1] - u) < 1e-9 * max(1.0, abs(u)), r
+        assert abs(res.force[1, 0] - f) < 1e-9 * max(1.0, abs(f)), r
+        assert abs(res.force[0, 0] + f) < 1e-9 * max(1.0, abs(f)), r
+    # without the cutoff the plain LJ tail acts
+    res = orc.forward(np.array([[5.0, 5.0, 5.0], [6.5, 5.0, 5.0]]), np.zeros(2), np.zeros(2, np.int32),
+                      np.array([-1, -1], np.int32), np.ones(4), np.ones(4),
+                      orc.Params(box=10.0, beta=1.0, r_core=1.5, r_shell=3.0, p_kspace=10, ke=1.0), mode="full")
+    assert res.energy[1] < 0.0
+
+
+def _dense_ions(n=240, box=12.0, seed=5):
+    """Random +1/-1 ions at least 0.85 sigma apart (some pairs inside 2^(1/6) sigma)."""
+    import types
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        c = rng.uniform(0.0, box, 3)
+        ok = True
+        for p_ in pts:
+            d = c - p_
+            d -= box * np.rint(d / box)
+            if d @ d < 0.85 ** 2:
+                ok = False
+                break
+        if ok:
+            pts.append(c)
+    charge = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return types.SimpleNamespace(pos=np.array(pts), charge=charge, atom_type=(np.arange(n) % 2).astype(np.int32),
+                                 molecule=np.full(n, -1, np.int32), lj_sigma=np.ones(4), lj_eps=np.ones(4), box=box,
+                                 n_atoms=n)
+
+
+def test_shifted_truncated_lj_adjoint_matches_central_differences(orc):
+    w = _dense_ions()
+    p = orc.Params(box=w.box, beta=0.6, r_core=2.5, r_shell=5.5, p_shell=10, p_kspace=50, ke=1.0, lj_cut=WCA)
+    res = orc.forward(*_args(w), p, mode="rbl")
+    s = res.s
+    d = (s[None, :, :].astype(np.int64) - s[:, None, :].astype(np.int64))
+    d = ((d + 2 ** 31) % 2 ** 32 - 2 ** 31) * (w.box / 2 ** 32)
+    r = np.sqrt((d * d).sum(axis=2)) + np.eye(w.n_atoms) * 99
+    assert (r < WCA).sum() >= 4  # some pairs feel the LJ core
+    G = np.random.default_rng(3).standard_normal(res.force.shape)
+    g_pos, g_q, g_sig, g_eps = orc.backward(G, *_args(w)[1:], p, res, mode="rbl")
+    quantum = w.box / 2 ** 32
+    hq = int(round(1e-6 / quantum))
+    h = hq * quantum
+    near = np.unique(np.nonzero(r < WCA)[0])[:3]
+    for i in list(near) + [7]:
+        for a in range(3):
+            sp = res.s.copy()
+            sm = res.s.copy()
+            sp[i, a] += np.uint32(hq)
+            sm[i, a] -= np.uint32(hq)
+            fd = (_loss(orc, w, p, res, G, s=sp) - _loss(orc, w, p, res, G, s=sm)) / (2 * h)
+            assert abs(fd - g_pos[i, a]) < 1e-5 * max(abs(g_pos[i, a]), 1.0)
+    for tbl, grad in (("sig", g_sig), ("eps", g_eps)):
+        base = w.lj_sigma if tbl == "sig" else w.lj_eps
+        for k in (0, 1):
+            hh = 1e-6
+            tp = base.copy()
+            tm = base.copy()
+            tp[k] += hh
+            tm[k] -= hh
+            fd = (_loss(orc, w, p, res, G, **{tbl: tp}) - _loss(orc, w, p, res, G, **{tbl: tm})) / (2 * hh)
+            assert abs(fd - grad[k]) < 1e-5 * max(abs(grad[k]), 1.0), (tbl, k, fd, grad[k])
