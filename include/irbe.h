@@ -124,6 +124,11 @@ typedef struct {
                               list length. floor(L / (r_core + skin)) >= 3 and
                               r_shell + skin < L/2. 0: the lists of Sec. 2.3 as they
                               are, no membership test at force time.            */
+    double lj_cut;         /* >= 0: 0 = the LJ term of every listed pair (r <= r_shell),
+                              unshifted; > 0 = the shifted-truncated LJ: only at
+                              r < lj_cut sigma_ij, its energy shifted to zero there
+                              (2^(1/6) for the soft spheres of the paper's
+                              primitive-model electrolytes, Sec. 4)              */
 } irbe_config;
 
 /* Create a handle for one system size and parameter set; work is queued on
@@ -329,14 +334,15 @@ irbe_status irbe_dyn_kinetic(irbe_dyn_handle d, const double* vel, double* out);
 irbe_status irbe_dyn_msd(irbe_dyn_handle d, const double* pos, const double* ref, const int32_t* sel, int64_t m,
                          double* out);
 
-/* Adds to hist[n_bins] (device uint64) the pairs a < b of the m selected atoms
- * by minimum-image distance r in a cubic box of edge `box` (FP64 without fused
+/* Adds to hist[n_bins] (device uint64) the pairs a < b of the m atoms of sel
+ * (sel_b NULL), or every pair of an atom of sel and a different atom of the
+ * m_b atoms of sel_b, by minimum-image distance r in a cubic box of edge `box` (FP64 without fused
  * operations: d = x_b - x_a - box rint((x_b - x_a) / box) per axis,
  * r = sqrt(d.d)), bin floor(r / (r_max / n_bins)) clamped to the last, r < r_max
  * only; 1 <= n_bins <= 8192. O(m^2) work: an analysis of small systems (the
  * radial distribution function g(r) follows on the host). Does not wait. */
-irbe_status irbe_dyn_rdf(irbe_dyn_handle d, const double* pos, const int32_t* sel, int64_t m, double box,
-                         double r_max, int32_t n_bins, uint64_t* hist);
+irbe_status irbe_dyn_rdf(irbe_dyn_handle d, const double* pos, const int32_t* sel, int64_t m, const int32_t* sel_b,
+                         int64_t m_b, double box, double r_max, int32_t n_bins, uint64_t* hist);
 
 /* out[0..1] (device FP64) = the Nose-Hoover state {xi, sum over steps of h xi}
  * (both 0 with IRBE_LANGEVIN); the quantity U + K + n_dof kT (tau^2 xi^2 / 2 +

@@ -181,16 +181,23 @@ def kinetic_energy(v, inv_mass) -> float:
     return float(0.5 * np.sum(m[:, None] * np.asarray(v) ** 2))
 
 
-def rdf_counts(pos, sel, box, r_max, n_bins) -> np.ndarray:
-    """Pairs i < j of the selected atoms by minimum-image distance r (FP64,
+def rdf_counts(pos, sel, box, r_max, n_bins, sel_b=None) -> np.ndarray:
+    """Pairs i < j of the selected atoms (or every pair of an atom of sel and a
+    different atom of sel_b) by minimum-image distance r (FP64,
     d = r_j - r_i - L rint((r_j - r_i) / L) per axis, r = sqrt(d.d) without
     fused operations), in n_bins equal bins of [0, r_max): bin floor(r / (r_max /
     n_bins)), clamped to the last; distances >= r_max are not counted."""
-    p = np.asarray(pos, dtype=np.float64)[np.asarray(sel)]
+    sel = np.asarray(sel)
+    p = np.asarray(pos, dtype=np.float64)[sel]
     out = np.zeros(n_bins, dtype=np.int64)
     width = r_max / n_bins
-    for i in range(p.shape[0] - 1):
-        d = p[i + 1:] - p[i]
+    for i in range(p.shape[0]):
+        if sel_b is None:
+            d = p[i + 1:] - p[i]
+        else:
+            other = np.asarray(sel_b)
+            other = other[other != sel[i]]
+            d = np.asarray(pos, dtype=np.float64)[other] - p[i]
         d -= box * np.rint(d / box)
         r = np.sqrt((d * d).sum(axis=1))
         b = np.minimum(np.floor(r / width).astype(np.int64), n_bins - 1)

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -261,6 +262,9 @@ void lj_tables(const irbe_ctx* h, std::vector<LJ<real>>& tab, std::vector<real>&
         tab[t].b6 = (real)(24.0 * e * s6);
         tab[t].c12 = (real)(4.0 * e * s12);
         tab[t].c6 = (real)(4.0 * e * s6);
+        const double k = h->cfg.lj_cut;
+        tab[t].rc2 = k > 0.0 ? (real)(k * s * k * s) : std::numeric_limits<real>::max();
+        tab[t].esh = k > 0.0 ? (real)(4.0 * e * (std::pow(k, -12.0) - std::pow(k, -6.0))) : (real)0;
         raw[t] = (real)s;
         raw[nt2 + t] = (real)e;
     }
@@ -328,6 +332,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
         return fail(nullptr, IRBE_EINVAL, "bad capacity_hint");
     if (!(c.skin >= 0.0) || !std::isfinite(c.skin) || !(c.r_shell + c.skin < 0.5 * c.box_length))
         return fail(nullptr, IRBE_EINVAL, "need skin >= 0 and r_shell + skin < L/2");
+    if (!(c.lj_cut >= 0.0) || !std::isfinite(c.lj_cut)) return fail(nullptr, IRBE_EINVAL, "need lj_cut >= 0");
     if (c.shell_source != IRBE_SHELL_LIST && c.shell_source != IRBE_SHELL_STENCIL)
         return fail(nullptr, IRBE_EINVAL, "bad shell_source");
     if (c.shell_source == IRBE_SHELL_STENCIL && c.p_shell <= 0)
@@ -380,7 +385,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc_bytes(h, &h->q_orig, n * rs));
     ALLOC(dalloc(h, &h->type_orig, n));
     ALLOC(dalloc(h, &h->mol_orig, n));
-    ALLOC(dalloc_bytes(h, &h->lj, (size_t)nt2 * 4 * rs));
+    ALLOC(dalloc_bytes(h, &h->lj, (size_t)nt2 * (h->fp64 ? sizeof(LJ<double>) : sizeof(LJ<float>))));
     ALLOC(dalloc_bytes(h, &h->lj_raw, (size_t)nt2 * 2 * rs));
     ALLOC(dalloc(h, &h->sumq2, 1));
     ALLOC(dalloc(h, &h->q2part, (size_t)nb));

@@ -153,6 +153,7 @@ struct Math;
 
 template <>
 struct Math<float> {
+    static __device__ __forceinline__ float max_() { return 3.402823466e38f; }
     static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
     // erfc(x) for x >= 0 given ex = exp(-x^2): the Chebyshev-fitted form of
     // Numerical Recipes (Press et al., Sec. 6.2, "erfcc"), fractional error
@@ -186,6 +187,7 @@ struct Math<float> {
 
 template <>
 struct Math<double> {
+    static __device__ __forceinline__ double max_() { return 1.7976931348623157e308; }
     static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
     static __device__ __forceinline__ double erfc_ex(double x, double) { return erfc(x); }
     static __device__ __forceinline__ double erf_(double x) { return erf(x); }

@@ -47,10 +47,12 @@ struct KAdj {
     real pad;
 };
 
-// LJ pair table entry: force 48 eps s^12, 24 eps s^6; energy 4 eps s^12, 4 eps s^6.
+// LJ pair table entry: force 48 eps s^12, 24 eps s^6; energy 4 eps s^12, 4 eps s^6;
+// the term acts at r^2 < rc2 (the largest finite value without a cutoff) and its
+// energy is lowered by esh there (the shifted-truncated form).
 template <typename real>
 struct LJ {
-    real a12, b6, c12, c6;
+    real a12, b6, c12, c6, rc2, esh;
 };
 
 struct Geometry {

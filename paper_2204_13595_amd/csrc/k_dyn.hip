@@ -311,31 +311,41 @@ __global__ void k_copy2(const double* __restrict__ a, double* __restrict__ b)
     if (threadIdx.x < 2) b[threadIdx.x] = a[threadIdx.x];
 }
 
-// Pair-distance histogram of the selected atoms (pairs a < b), minimum image per
-// axis, FP64 without contraction so that every distance and bin is the plain
+// Pair-distance histogram: pairs a < b of selection A (sel_b == nullptr), or
+// every pair of an atom of A and a different atom of B; minimum image per axis,
+// FP64 without contraction so that every distance and bin is the plain
 // definition's. Block: 256 atoms a, tiles of 256 atoms b staged in LDS; bins
 // counted in LDS, then added to the caller's 64-bit histogram.
 constexpr int kRdfMaxBins = 8192;
 
 __global__ __launch_bounds__(kDynBlock) void k_rdf(int64_t m, const double* __restrict__ pos,
-                                                   const int32_t* __restrict__ sel, double box, double r_max,
+                                                   const int32_t* __restrict__ sel, int64_t mb,
+                                                   const int32_t* __restrict__ sel_b, double box, double r_max,
                                                    double width, int n_bins, unsigned long long* __restrict__ hist)
 {
 #pragma clang fp contract(off)
     __shared__ uint32_t bins[kRdfMaxBins];
     __shared__ V3 tile[kDynBlock];
     for (int t = threadIdx.x; t < n_bins; t += kDynBlock) bins[t] = 0u;
+    __shared__ int32_t tile_id[kDynBlock];
+    const bool cross = sel_b != nullptr;
+    const int32_t* sb = cross ? sel_b : sel;
+    const int64_t nb = cross ? mb : m;
     const int64_t a0 = (int64_t)blockIdx.x * kDynBlock;
     const int64_t a = a0 + threadIdx.x;
-    const V3 pa = a < m ? load3(pos, sel[a]) : V3{0, 0, 0};
-    for (int64_t b0 = a0; b0 < m; b0 += kDynBlock) {
+    const int32_t ia = a < m ? sel[a] : -1;
+    const V3 pa = a < m ? load3(pos, ia) : V3{0, 0, 0};
+    for (int64_t b0 = cross ? 0 : a0; b0 < nb; b0 += kDynBlock) {
         __syncthreads();
-        if (b0 + threadIdx.x < m) tile[threadIdx.x] = load3(pos, sel[b0 + threadIdx.x]);
+        if (b0 + threadIdx.x < nb) {
+            tile_id[threadIdx.x] = sb[b0 + threadIdx.x];
+            tile[threadIdx.x] = load3(pos, tile_id[threadIdx.x]);
+        }
         __syncthreads();
-        const int cnt = (int)min<int64_t>(kDynBlock, m - b0);
+        const int cnt = (int)min<int64_t>(kDynBlock, nb - b0);
         if (a < m)
             for (int t = 0; t < cnt; ++t) {
-                if (b0 + t <= a) continue;
+                if (cross ? tile_id[t] == ia : b0 + t <= a) continue;
                 V3 d = tile[t] - pa;
                 d.x = d.x - box * rint(d.x / box);
                 d.y = d.y - box * rint(d.y / box);
@@ -548,17 +558,18 @@ irbe_status irbe_dyn_msd(irbe_dyn_handle d, const double* pos, const double* ref
     return IRBE_OK;
 }
 
-irbe_status irbe_dyn_rdf(irbe_dyn_handle d, const double* pos, const int32_t* sel, int64_t m, double box,
-                         double r_max, int32_t n_bins, uint64_t* hist)
+irbe_status irbe_dyn_rdf(irbe_dyn_handle d, const double* pos, const int32_t* sel, int64_t m, const int32_t* sel_b,
+                         int64_t m_b, double box, double r_max, int32_t n_bins, uint64_t* hist)
 {
     if (!d || !pos || !sel || !hist) return dyn_fail(d, IRBE_EINVAL, "null argument");
     if (m < 0 || m > d->cfg.n_atoms) return dyn_fail(d, IRBE_EINVAL, "need 0 <= m <= n_atoms");
+    if (sel_b && (m_b < 0 || m_b > d->cfg.n_atoms)) return dyn_fail(d, IRBE_EINVAL, "need 0 <= m_b <= n_atoms");
     if (n_bins < 1 || n_bins > kRdfMaxBins) return dyn_fail(d, IRBE_EINVAL, "need 1 <= n_bins <= 8192");
     if (!(box > 0.0) || !(r_max > 0.0) || !std::isfinite(box) || !std::isfinite(r_max))
         return dyn_fail(d, IRBE_EINVAL, "need box > 0 and r_max > 0");
-    if (m < 2) return IRBE_OK;
-    k_rdf<<<(unsigned)nblocks(m), kDynBlock, 0, d->stream>>>(m, pos, sel, box, r_max, r_max / n_bins, n_bins,
-                                                             (unsigned long long*)hist);
+    if (m < 1 || (!sel_b && m < 2) || (sel_b && m_b < 1)) return IRBE_OK;
+    k_rdf<<<(unsigned)nblocks(m), kDynBlock, 0, d->stream>>>(m, pos, sel, sel_b ? m_b : 0, sel_b, box, r_max,
+                                                             r_max / n_bins, n_bins, (unsigned long long*)hist);
     DYN_TRY(d, hipGetLastError(), "rdf");
     return IRBE_OK;
 }

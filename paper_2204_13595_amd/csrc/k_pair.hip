@@ -68,11 +68,12 @@ __device__ __forceinline__ real pair_phi(real r2, real qq, const LJ<real>& lj, c
     const real ec = M::erfc_ex(br, ex);
     const real rinv2 = rinv * rinv;
     const real r6 = rinv2 * rinv2 * rinv2;
+    const bool lj_on = r2 < lj.rc2;
     real phi = -qq * rinv2 * (ec * rinv + pp.cgauss * ex);
-    phi -= r6 * rinv2 * (lj.a12 * r6 - lj.b6);
+    phi -= lj_on ? r6 * rinv2 * (lj.a12 * r6 - lj.b6) : (real)0;
     if (EV) {
         uc = qq * ec * rinv;
-        ul = r6 * (lj.c12 * r6 - lj.c6);
+        ul = lj_on ? r6 * (lj.c12 * r6 - lj.c6) - lj.esh : (real)0;
     }
     return phi;
 }
@@ -355,7 +356,8 @@ __device__ __forceinline__ void add_pair_or_excl(PairSum<real>& pc, PairSum<real
     const real rinv2 = rinv * rinv;
     const real r6 = rinv2 * rinv2 * rinv2;
     const real coul = -qq * rinv2 * (ec * rinv + pp.cgauss * e);
-    const real phi = ex ? coul + qq * rinv2 * rinv : coul - r6 * rinv2 * (lj.a12 * r6 - lj.b6);
+    const real ljf = r2 < lj.rc2 ? r6 * rinv2 * (lj.a12 * r6 - lj.b6) : (real)0;
+    const real phi = ex ? coul + qq * rinv2 * rinv : coul - ljf;
     const real fx = phi * dx, fy = phi * dy, fz = phi * dz;
     pc.fx += ex ? (real)0 : fx;
     pc.fy += ex ? (real)0 : fy;
@@ -772,11 +774,11 @@ struct LJGrad {
     real a48, b24;    // 48 s^12, 24 s^6:   c_lj = (a48 r^-6 - b24) r^-8
     real a672, b192;  // 672 s^12, 192 s^6: d c_lj / dr = (b192 - a672 r^-6) r^-9
     real as, bs;      // 576 s^11, 144 s^5: d c_lj / d sigma = (as r^-6 - bs) r^-8
-    real eps, pad;
+    real eps, rc2;    // the LJ term acts at r^2 < rc2
 };
 
 template <typename real>
-__device__ __forceinline__ LJGrad<real> lj_grad_entry(real sig, real eps)
+__device__ __forceinline__ LJGrad<real> lj_grad_entry(real sig, real eps, real lj_cut)
 {
     const real s2 = sig * sig;
     const real s6 = s2 * s2 * s2;
@@ -789,7 +791,7 @@ __device__ __forceinline__ LJGrad<real> lj_grad_entry(real sig, real eps)
     L.as = sig != (real)0 ? (real)576 * s12 / sig : (real)0;
     L.bs = sig != (real)0 ? (real)144 * s6 / sig : (real)0;
     L.eps = eps;
-    L.pad = 0;
+    L.rc2 = lj_cut > (real)0 ? lj_cut * sig * lj_cut * sig : Math<real>::max_();
     return L;
 }
 
@@ -814,7 +816,7 @@ __device__ __forceinline__ PairGrad<real> pair_grad(real r2, real qq, const LJGr
     const real dB = -B * ((real)2 * pp.beta * pp.beta * r + (real)2 * rinv);
     const real r6 = rinv2 * rinv2 * rinv2;
     const real r8 = r6 * rinv2;
-    const real on = xp ? (real)0 : (real)1;
+    const real on = (xp || !(r2 < L.rc2)) ? (real)0 : (real)1;
     const real C = on * r8 * (L.a48 * r6 - L.b24);
     const real dC = on * rinv * r8 * (L.b192 - L.a672 * r6);
     const real eps = on * L.eps;
@@ -890,7 +892,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const real* __restrict__ ljraw_g, int n_types, int p_shell,
     int p_stride, const uint16_t* __restrict__ ranks, const int32_t* __restrict__ batch_j, uint64_t t_core,
-    uint64_t t_shell, bool skin, const real* __restrict__ gs, const double* __restrict__ gmean_d,
+    uint64_t t_shell, bool skin, real lj_cut, const real* __restrict__ gs, const double* __restrict__ gmean_d,
     real* __restrict__ gself, real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat,
     double* __restrict__ ljpart, BucketArgs bk, int rec_cap)
 {
@@ -914,7 +916,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int32_t* kcap = kfirst + nkeys;                         // [nkeys] bucket capacity
     int32_t* kcount = kcap + nkeys;                         // [nkeys] atoms of the row in the LDS window
     const int nt2 = n_types * n_types;
-    for (int t = threadIdx.x; t < nt2; t += kCoopBlock) ljg[t] = lj_grad_entry(ljraw_g[t], ljraw_g[nt2 + t]);
+    for (int t = threadIdx.x; t < nt2; t += kCoopBlock) ljg[t] = lj_grad_entry(ljraw_g[t], ljraw_g[nt2 + t], lj_cut);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (WANT_LJ)
         for (int t = lane; t < NLJ; t += 64) ljacc[wave][t] = 0.0;
@@ -1310,7 +1312,8 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
     k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL><<<nb, kCoopBlock, lds, h->stream>>>(
         n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
-        h->p_stride, h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, h->geo.skin, (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
+        h->p_stride, h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, h->geo.skin, (real)h->cfg.lj_cut,
+        (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
         (real*)h->gqscat, h->ljpart, bk, rec_cap);
     e = hipGetLastError();
     if (e != hipSuccess || !BK) return e;

@@ -100,12 +100,17 @@ class Langevin:
         self._check(self.lib.irbe_dyn_msd(self.h, _p(pos), _p(ref), _p(sel), int(sel.shape[0]), _p(out)))
         return out
 
-    def rdf(self, pos: torch.Tensor, sel: torch.Tensor, box: float, r_max: float, hist: torch.Tensor):
-        """Adds the pair-distance counts of the selected atoms to hist (int64, [n_bins])."""
+    def rdf(self, pos: torch.Tensor, sel: torch.Tensor, box: float, r_max: float, hist: torch.Tensor,
+            sel_b: torch.Tensor | None = None):
+        """Adds to hist (int64, [n_bins]) the pair-distance counts of the selected
+        atoms (pairs within sel, or between sel and sel_b)."""
         self._arr(pos, (self.n_atoms, 3), torch.float64)
         self._arr(sel, (sel.shape[0],), torch.int32)
+        if sel_b is not None:
+            self._arr(sel_b, (sel_b.shape[0],), torch.int32)
         self._arr(hist, (hist.shape[0],), torch.int64)
-        self._check(self.lib.irbe_dyn_rdf(self.h, _p(pos), _p(sel), int(sel.shape[0]), float(box), float(r_max),
+        self._check(self.lib.irbe_dyn_rdf(self.h, _p(pos), _p(sel), int(sel.shape[0]), _p(sel_b),
+                                          0 if sel_b is None else int(sel_b.shape[0]), float(box), float(r_max),
                                           int(hist.shape[0]), _p(hist)))
 
     def thermostat_state(self) -> torch.Tensor:
@@ -134,9 +139,12 @@ def _p(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def rdf_normalise(counts: np.ndarray, m: int, box: float, r_max: float, frames: int) -> tuple[np.ndarray, np.ndarray]:
-    """g(r) at the bin centres from pair counts summed over `frames` frames of m atoms."""
+def rdf_normalise(counts: np.ndarray, m: int, box: float, r_max: float, frames: int,
+                  m_b: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """g(r) at the bin centres from pair counts summed over `frames` frames: pairs
+    within m atoms, or between m and m_b atoms of distinct species."""
     n_bins = counts.shape[0]
     edges = np.linspace(0.0, r_max, n_bins + 1)
-    ideal = 0.5 * m * (m - 1) / box ** 3 * 4.0 / 3.0 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3) * frames
+    pairs = 0.5 * m * (m - 1) if m_b is None else float(m) * m_b
+    ideal = pairs / box ** 3 * 4.0 / 3.0 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3) * frames
     return 0.5 * (edges[1:] + edges[:-1]), counts / ideal

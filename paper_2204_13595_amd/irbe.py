@@ -66,6 +66,7 @@ class Config(ctypes.Structure):
         ("r_core", ctypes.c_double), ("r_shell", ctypes.c_double), ("p_shell", ctypes.c_int32),
         ("p_kspace", ctypes.c_int32), ("n_types", ctypes.c_int32), ("shell_source", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("capacity_hint", ctypes.c_double), ("skin", ctypes.c_double),
+        ("lj_cut", ctypes.c_double),
     ]
 
 
@@ -101,7 +102,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.irbe_dyn_step.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp]
     L.irbe_dyn_kinetic.argtypes = [vp, vp, vp]
     L.irbe_dyn_msd.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp]
-    L.irbe_dyn_rdf.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp]
+    L.irbe_dyn_rdf.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int32, vp]
     L.irbe_dyn_thermostat_state.argtypes = [vp, vp]
     L.irbe_dyn_degrees_of_freedom.argtypes = [vp]
     L.irbe_dyn_check.argtypes = [vp]
@@ -131,7 +133,8 @@ class Handle:
     def __init__(self, n_atoms: int, box: float, *, beta: float = 3.0, r_core: float = 0.5, r_shell: float = 1.2,
                  p_shell: int = 100, p_kspace: int = 100, seed: int = 13595, n_types: int = 2,
                  precision: str = "mixed", coulomb_k: float = 138.935458, capacity_hint: float = 0.0,
-                 shell_source: str = "list", skin: float = 0.0, device: torch.device | str | None = None):
+                 shell_source: str = "list", skin: float = 0.0, lj_cut: float = 0.0,
+                 device: torch.device | str | None = None):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the IRBE HIP library needs a GPU")
@@ -142,7 +145,7 @@ class Handle:
         self.cfg = Config(IRBE_ABI_VERSION, IRBE_FP64 if precision == "fp64" else IRBE_MIXED_FP32, self.n_atoms,
                           float(box), float(beta), float(coulomb_k), float(r_core), float(r_shell), int(p_shell),
                           int(p_kspace), self.n_types, SHELL_SOURCE[shell_source], int(seed), float(capacity_hint),
-                          float(skin))
+                          float(skin), float(lj_cut))
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             h = ctypes.c_void_p()

@@ -13,7 +13,13 @@ sampled observables on the host.
 runs the water comparison of the paper's Sec. 4 on synthetic water (901
 molecules, L = 3 nm, r_c = 1.2 nm, beta = 3 nm^-1 i.e. alpha = 0.09 A^-2,
 p = 200, T = 298 K) for the (r_core, p~) sets of the paper's parameter table at
-that alpha, and prints one JSON line.
+that alpha, and prints one JSON line;
+
+    python -m paper_2204_13595_amd.md --electrolytes
+
+runs the 1:1 and 2:1 primitive-model electrolytes of the same section (reduced
+units, shifted-truncated LJ, Langevin thermostat) with RBL+RBE against the full
+list.
 """
 from __future__ import annotations
 
@@ -164,14 +170,128 @@ def compare(prod_steps: int = 150000, equil_steps: int = 40000, log=None) -> dic
     return out
 
 
+def run_electrolyte(valence: int = 1, *, p_shell: int = 10, p_kspace: int = 100, r_core: float = 5.0,
+                    r_shell: float = 15.0, alpha: float = 0.03, ke: float = 1.0, dt: float = 0.002,
+                    gamma: float = 1.0, equil_steps: int = 20000, prod_steps: int = 80000, sample_every: int = 100,
+                    rdf_bins: int = 150, rdf_rmax: float = 15.0, msd_window: int = 20000,
+                    msd_origin_every: int = 5000, seed: int = 2204, log=None) -> dict:
+    """The primitive-model electrolytes of the paper's Sec. 4 in reduced units
+    (sigma = m = kT = 1): 1:1 or 2:1 ions in L = 80, shifted-truncated LJ at
+    2^(1/6) (soft spheres), Coulomb coupling `ke` (the Bjerrum length; not given
+    in the paper), Langevin thermostat with relaxation time 1 (friction 1), time
+    step 0.002. p_shell <= 0 is the full list. Returns g_{+-}, g_{++}, g_{--},
+    the MSD of each species against the lag, and the potential energy per atom."""
+    import torch
+
+    from . import dynamics, inputs, irbe
+    dev = torch.device("cuda", torch.cuda.current_device())
+    w = inputs.electrolyte(valence, seed=seed)
+    n = w.n_atoms
+    h = irbe.Handle(n, w.box, beta=math.sqrt(alpha), r_core=r_core, r_shell=r_shell, p_shell=p_shell,
+                    p_kspace=p_kspace, seed=seed, precision="mixed", coulomb_k=ke, lj_cut=2.0 ** (1.0 / 6.0),
+                    device=dev)
+    h.set_system(torch.tensor(w.atom_type, device=dev), torch.tensor(w.charge, dtype=torch.float32, device=dev),
+                 torch.tensor(w.molecule, device=dev), w.lj_sigma, w.lj_eps)
+    groups = np.stack([np.arange(n), -np.ones(n, np.int64), -np.ones(n, np.int64)], axis=1).astype(np.int32)
+    dyn = dynamics.Langevin(np.ones(n), groups, np.zeros((n, 3)), dt=dt, gamma=gamma, kT=1.0, seed=seed + 2,
+                            precision="mixed", device=dev)
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    vel = torch.zeros_like(pos)
+    pos_f = pos.float().contiguous()
+    force = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    species = {"+": torch.tensor(np.nonzero(w.atom_type == 0)[0], dtype=torch.int32, device=dev),
+               "-": torch.tensor(np.nonzero(w.atom_type == 1)[0], dtype=torch.int32, device=dev)}
+    pairs = {"+-": ("+", "-"), "++": ("+", None), "--": ("-", None)}
+    hist = {k: torch.zeros(rdf_bins, dtype=torch.int64, device=dev) for k in pairs}
+    u_s, origins, msd_acc = [], [], {"+": {}, "-": {}}
+    step = 0
+    t0 = time.perf_counter()
+
+    def sample(k, ev):
+        u_s.append(ev[:5].sum().reshape(1))
+        if k % msd_origin_every == 0 and k + msd_window <= prod_steps:
+            origins.append((k, pos.clone()))
+        for k0, ref in origins:
+            if k - k0 <= msd_window:
+                for sp, sel in species.items():
+                    msd_acc[sp].setdefault(k - k0, []).append(dyn.msd(pos, ref, sel))
+        for key, (a, b) in pairs.items():
+            dyn.rdf(pos, species[a], w.box, rdf_rmax, hist[key], sel_b=None if b is None else species[b])
+
+    for phase, count in (("equil", equil_steps), ("prod", prod_steps)):
+        for k in range(count):
+            h.build_lists(pos_f, step)
+            if phase == "prod" and k % sample_every == 0:
+                _, ev = h.compute_forces(pos_f, step, out=force, energy=True)
+                sample(k, ev)
+            else:
+                h.compute_forces(pos_f, step, out=force)
+            dyn.step(pos, vel, force, step, pos_copy=pos_f)
+            step += 1
+            if (k + 1) % 5000 == 0:
+                dyn.check()
+                if log:
+                    log(f"step {step}")
+    dyn.check()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    frames = len(u_s)
+    out = {"frames": frames, "steps": step, "ms_per_step": 1e3 * wall / step}
+    m = {sp: int(sel.shape[0]) for sp, sel in species.items()}
+    for key, (a, b) in pairs.items():
+        r, g = dynamics.rdf_normalise(hist[key].cpu().numpy(), m[a], w.box, rdf_rmax, frames,
+                                      m_b=None if b is None else m[b])
+        out["r"], out["g" + key] = r, g
+    for sp in species:
+        lags = np.array(sorted(msd_acc[sp]), dtype=np.int64)
+        out["msd_t"] = lags * dt
+        out["msd" + sp] = np.array([torch.cat(msd_acc[sp][lag]).mean().item() for lag in lags])
+    u = torch.cat(u_s).cpu().numpy() / n
+    out["u_per_atom"] = float(u.mean())
+    out["u_std"] = float(u.std(ddof=1))
+    h.close()
+    dyn.close()
+    return out
+
+
+def compare_electrolytes(prod_steps: int = 80000, equil_steps: int = 20000, log=None) -> dict:
+    """RBL+RBE (r_core = 5, p~ = 10) against the full list (the same RBE, p = 100)
+    for the 1:1 and 2:1 electrolytes: the potential energy per atom (mean and
+    standard deviation over the run), the g(r) differences and the end-of-window
+    MSD of each species."""
+    out = {}
+    for valence in (1, 2):
+        res = {m: run_electrolyte(valence, p_shell=ps, prod_steps=prod_steps, equil_steps=equil_steps, log=log)
+               for m, ps in (("full", 0), ("rbl", 10))}
+        f, r = res["full"], res["rbl"]
+        mask = f["r"] > 1.0
+        row = {}
+        for m in ("full", "rbl"):
+            row[m] = {"u_per_atom": res[m]["u_per_atom"], "u_std": res[m]["u_std"],
+                      "ms_per_step": res[m]["ms_per_step"],
+                      "msd_end": {sp: float(res[m]["msd" + sp][-1]) for sp in "+-"},
+                      "g_peak_+-": float(res[m]["g+-"].max())}
+        row["rel_u_diff"] = r["u_per_atom"] / f["u_per_atom"] - 1.0
+        row["max_abs_g_diff"] = {k: float(np.abs(r["g" + k] - f["g" + k])[mask].max()) for k in ("+-", "++", "--")}
+        row["rel_msd_end_diff"] = {sp: float(r["msd" + sp][-1] / f["msd" + sp][-1] - 1.0) for sp in "+-"}
+        out[f"{valence}:1"] = row
+    out["setup"] = (f"2560+2560 (1:1) or 1280+2560 (2:1) ions, L = 80, shifted-truncated LJ at 2^(1/6), ke = 1, "
+                    f"alpha = 0.03, p = 100, r_c = 15, RBL r_core = 5 and p~ = 10, Langevin friction 1, dt = 0.002, "
+                    f"{equil_steps} + {prod_steps} steps, lists rebuilt every step, mixed precision")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description="NVT water with the IRBE force")
     ap.add_argument("--compare", action="store_true")
+    ap.add_argument("--electrolytes", action="store_true", help="the 1:1 and 2:1 primitive-model comparison")
     ap.add_argument("--prod-steps", type=int, default=150000)
     ap.add_argument("--equil-steps", type=int, default=40000)
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    if args.compare:
+    if args.electrolytes:
+        print(json.dumps(compare_electrolytes(log=log)), flush=True)
+    elif args.compare:
         print(json.dumps(compare(args.prod_steps, args.equil_steps, log=log)), flush=True)
     else:
         res = run_water(prod_steps=args.prod_steps, equil_steps=args.equil_steps, log=log)

@@ -38,9 +38,9 @@ def test_config_layout_matches_header():
 #include <stdio.h>
 #include "irbe.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(irbe_config), offsetof(irbe_config, n_atoms),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(irbe_config), offsetof(irbe_config, n_atoms),
          offsetof(irbe_config, p_shell), offsetof(irbe_config, seed), offsetof(irbe_config, capacity_hint),
-         offsetof(irbe_config, skin));
+         offsetof(irbe_config, skin), offsetof(irbe_config, lj_cut));
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(irbe_dyn_config), offsetof(irbe_dyn_config, n_atoms),
          offsetof(irbe_dyn_config, dt), offsetof(irbe_dyn_config, kT), offsetof(irbe_dyn_config, seed),
          offsetof(irbe_dyn_config, tau));
@@ -54,10 +54,10 @@ int main(void) {
         subprocess.run(["gcc", "-std=c99", f"-I{os.path.dirname(HEADER)}", c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     C = irbe.Config
-    assert [int(x) for x in out[:6]] == [ctypes.sizeof(C), C.n_atoms.offset, C.p_shell.offset, C.seed.offset,
-                                         C.capacity_hint.offset, C.skin.offset]
+    assert [int(x) for x in out[:7]] == [ctypes.sizeof(C), C.n_atoms.offset, C.p_shell.offset, C.seed.offset,
+                                         C.capacity_hint.offset, C.skin.offset, C.lj_cut.offset]
     D = irbe.DynConfig
-    assert [int(x) for x in out[6:]] == [ctypes.sizeof(D), D.n_atoms.offset, D.dt.offset, D.kT.offset,
+    assert [int(x) for x in out[7:]] == [ctypes.sizeof(D), D.n_atoms.offset, D.dt.offset, D.kT.offset,
                                          D.seed.offset, D.tau.offset]
 
 

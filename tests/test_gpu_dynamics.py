@@ -112,6 +112,12 @@ def test_kinetic_msd_rdf_match_oracle(dyn_orc):
         got = hist.cpu().numpy()
         want = dyn_orc.rdf_counts(w.pos, sel.cpu().numpy(), w.box, r_max, bins)
         assert np.array_equal(got, 2 * want)
+    # between oxygens and the first hydrogens, plus three oxygens in both selections
+    sel_b = torch.cat([torch.arange(1, w.n_atoms, 3, dtype=torch.int32, device=dev), sel[:3]])
+    hist = torch.zeros(300, dtype=torch.int64, device=dev)
+    d.rdf(pos, sel, w.box, 1.5, hist, sel_b=sel_b)
+    want = dyn_orc.rdf_counts(w.pos, sel.cpu().numpy(), w.box, 1.5, 300, sel_b=sel_b.cpu().numpy())
+    assert np.array_equal(hist.cpu().numpy(), want)
     d.close()
 
 
@@ -168,3 +174,15 @@ def test_short_water_run_with_irbe_forces():
     assert abs(res["temperature"] / 298.0 - 1.0) < 0.25, res["temperature"]
     assert np.isfinite(res["u_per_molecule"])
     assert np.all(np.isfinite(res["g"]))
+
+
+def test_short_electrolyte_run():
+    """2:1 primitive-model electrolyte, 1,500 steps of RBL+RBE forces with the
+    shifted-truncated LJ and Langevin steps: no error, finite observables."""
+    from paper_2204_13595_amd import md
+    res = md.run_electrolyte(2, equil_steps=500, prod_steps=1000, sample_every=50, msd_window=500,
+                             msd_origin_every=250)
+    assert res["frames"] == 20
+    assert np.isfinite(res["u_per_atom"]) and res["u_per_atom"] < 0.0
+    for k in ("g+-", "g++", "g--", "msd+", "msd-"):
+        assert np.all(np.isfinite(res[k])), k

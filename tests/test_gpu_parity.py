@@ -357,3 +357,56 @@ def test_long_shell_lists_draw_bit_exact(orc):
     assert ns.min() > 16384
     ref = np.concatenate([orc.shell_ranks(13595, step, int(i), int(n), 100) for i, n in zip(rows, ns)])
     assert np.array_equal(got_rank, ref)
+
+
+def _dense_ions(n=3000, box=24.0, seed=5):
+    """+1/-1 ions on randomly chosen sites of a cubic lattice of spacing 1 sigma,
+    jittered by U(-0.075, 0.075) per axis: neighbours 0.85 to 1.15 sigma apart,
+    so that many pairs lie inside 2^(1/6) sigma."""
+    rng = np.random.default_rng(seed)
+    m = int(round(box))
+    sites = rng.choice(m ** 3, size=n, replace=False)
+    iz, rem = np.divmod(sites, m * m)
+    iy, ix = np.divmod(rem, m)
+    pos = np.stack([ix, iy, iz], axis=1) + 0.5 + rng.uniform(-0.075, 0.075, size=(n, 3))
+    charge = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return pos, charge, (np.arange(n) % 2).astype(np.int32)
+
+
+@pytest.mark.parametrize("precision,tol_f,tol_g", [("fp64", 1e-11, 1e-10), ("mixed", 1e-5, 2e-5)])
+def test_shifted_truncated_lj_parity(orc, precision, tol_f, tol_g):
+    """Shifted-truncated LJ at 2^(1/6) sigma (the soft spheres of the primitive
+    model) on a dense ionic box where many pairs lie inside the cutoff: forces,
+    the LJ energy and the gradients against the oracle."""
+    from paper_2204_13595_amd import irbe
+    wca = 2.0 ** (1.0 / 6.0)
+    pos_np, charge, types = _dense_ions()
+    n, box = pos_np.shape[0], 24.0
+    dev = torch.device("cuda", 0)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    h = irbe.Handle(n, box, beta=0.6, r_core=2.5, r_shell=5.5, p_shell=10, p_kspace=50, coulomb_k=1.0,
+                    precision=precision, lj_cut=wca, device=dev)
+    pos = torch.tensor(pos_np, dtype=dt, device=dev)
+    q = torch.tensor(charge, dtype=dt, device=dev)
+    mol = np.full(n, -1, np.int32)
+    h.set_system(torch.tensor(types, device=dev), q, torch.tensor(mol, device=dev), np.ones(4), np.ones(4))
+    h.build_lists(pos, 3)
+    f, ev = h.compute_forces(pos, 3, energy=True)
+    G = np.random.default_rng(2).standard_normal((n, 3))
+    Gt = torch.tensor(G, dtype=dt, device=dev)
+    gp, gq, gl = h.compute_forces_backward(pos, 3, Gt)
+    h.close()
+    x = pos.double().cpu().numpy()
+    p = orc.Params(box=box, beta=0.6, r_core=2.5, r_shell=5.5, p_shell=10, p_kspace=50, ke=1.0, lj_cut=wca)
+    ref = orc.forward(x, q.double().cpu().numpy(), types, mol, np.ones(4), np.ones(4), p, step=3, mode="rbl")
+    assert ref.energy[1] > 1.0  # the LJ cores act
+    assert _rms_rel(f.double().cpu().numpy(), ref.force) < tol_f
+    assert abs(ev[1].item() - ref.energy[1]) < 10 * tol_f * abs(ref.energy[1])
+    r_pos, r_q, r_sig, r_eps = orc.backward(Gt.double().cpu().numpy(), q.double().cpu().numpy(), types, mol,
+                                            np.ones(4), np.ones(4), p, ref, mode="rbl")
+    assert _rms_rel(gp.double().cpu().numpy(), r_pos) < tol_g
+    assert _rms_rel(gq.double().cpu().numpy(), r_q) < tol_g
+    gl = gl.cpu().numpy()
+    for k in range(4):
+        assert abs(gl[k] - r_sig[k]) < 10 * tol_g * max(abs(r_sig).max(), 1.0)
+        assert abs(gl[4 + k] - r_eps[k]) < 10 * tol_g * max(abs(r_eps).max(), 1.0)

@@ -170,6 +170,19 @@ def test_rdf_counts_brute_force(dyn):
             if best < r_max:
                 ref[min(int(best / (r_max / n_bins)), n_bins - 1)] += 1
     assert np.array_equal(got, ref)
+    # between two selections (sharing atoms 0 and 2): every pair of distinct atoms
+    sel_b = np.r_[np.arange(1, 60, 2), [0, 2]]
+    got = dyn.rdf_counts(pos, sel, box, r_max, n_bins, sel_b=sel_b)
+    ref = np.zeros(n_bins, dtype=np.int64)
+    for a in sel:
+        for b in sel_b:
+            if a == b:
+                continue
+            best = min(np.linalg.norm(pos[b] - pos[a] + box * np.array([i, j, k]))
+                       for i in range(-3, 4) for j in range(-3, 4) for k in range(-3, 4))
+            if best < r_max:
+                ref[min(int(best / (r_max / n_bins)), n_bins - 1)] += 1
+    assert np.array_equal(got, ref)
 
 
 def test_rdf_of_uniform_points_is_one(dyn):
