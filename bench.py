@@ -453,6 +453,13 @@ def main():
         torch.cuda.empty_cache()
         log("precision sweep on the 6.3M-atom box")
         sweep = precision_sweep(timed_steps) if args.workload == "water1M" and args.precision == "mixed" else None
+        log("constant-energy water32k")
+        from paper_2204_13595_amd import md
+        nve = {"rbl": md.run_nve(p_shell=args.p_shell), "full_list": md.run_nve(p_shell=0),
+               "note": ("32,768 rigid waters (98,304 atoms, L = 9.93 nm), P = 200, 1000 velocity-Verlet steps at "
+                        "dt = 1 fs from Maxwell velocities at 300 K (zero friction) after 2000 relaxation steps, lists "
+                        "rebuilt every step; "
+                        "drift = slope of the total energy; ms_per_step = lists + forces + integrator")}
         extras = {
             "fwd_bwd_atom_steps_per_s": n / (ms_fb * 1e-3), "ms_per_step_fwd_bwd": ms_fb,
             "forces_only_reused_lists_atom_steps_per_s": n / (ms_f * 1e-3), "ms_per_forces_only": ms_f,
@@ -467,6 +474,7 @@ def main():
             "stencil_sampling": stencil,
             "skin_lists": skin,
             "precision_sweep": sweep,
+            "nve_water32k": nve,
         }
     else:
         if args.with_backward:

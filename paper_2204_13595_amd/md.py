@@ -170,6 +170,76 @@ def compare(prod_steps: int = 150000, equil_steps: int = 40000, log=None) -> dic
     return out
 
 
+def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_kspace: int = 200,
+            r_core: float = 0.5, r_shell: float = 1.2, beta: float = 3.0, T0: float = 300.0, dt: float = 0.001,
+            steps: int = 1000, warm_steps: int = 2000, sample_every: int = 10, seed: int = 2204,
+            precision: str = "mixed") -> dict:
+    """Constant-energy run of rigid water (no thermostat: the integrator with zero
+    friction is velocity Verlet with the rigid constraints) from Maxwell
+    velocities at T0 (K), lists rebuilt every step. The synthetic lattice start
+    first relaxes for `warm_steps` Langevin steps of h/4 with strong friction
+    (untimed); the velocities are then drawn afresh. The total energy
+    E_n = U(x_n) + (K_{n-1/2} + K_{n+1/2}) / 2 is sampled every `sample_every`
+    steps; its drift (least-squares slope) measures the heating by the
+    stochastic force (Sec. 2.2 notes these methods are not meant for long
+    constant-energy runs). Returns the drift in kJ/mol per ps per molecule, the
+    energies, and ms per step (wall clock of the whole loop: lists, forces,
+    integrator)."""
+    import torch
+
+    from . import dynamics, inputs, irbe
+    dev = torch.device("cuda", torch.cuda.current_device())
+    w = inputs.make_water(n_waters, box, seed=seed)
+    n = w.n_atoms
+    fdt = torch.float64 if precision == "fp64" else torch.float32
+    h = irbe.Handle(n, box, beta=beta, r_core=r_core, r_shell=r_shell, p_shell=p_shell, p_kspace=p_kspace,
+                    seed=seed, precision=precision, device=dev)
+    h.set_system(torch.tensor(w.atom_type, device=dev), torch.tensor(w.charge, dtype=fdt, device=dev),
+                 torch.tensor(w.molecule, device=dev), w.lj_sigma, w.lj_eps)
+    groups, lengths, inv_mass = dynamics.water_topology(n_waters)
+    dyn = dynamics.Langevin(inv_mass, groups, lengths, dt=dt, gamma=0.0, kT=0.0, precision=precision, device=dev)
+    warm = dynamics.Langevin(inv_mass, groups, lengths, dt=dt / 4.0, gamma=50.0, kT=dynamics.KB * T0,
+                             seed=seed + 1, precision=precision, device=dev)
+    pos = torch.tensor(w.pos, dtype=torch.float64, device=dev)
+    vel = torch.zeros_like(pos)
+    pos_f = pos.to(fdt).contiguous()
+    force = torch.empty((n, 3), dtype=fdt, device=dev)
+    for step in range(warm_steps):
+        h.build_lists(pos_f, step)
+        h.compute_forces(pos_f, step, out=force)
+        warm.step(pos, vel, force, step, pos_copy=pos_f)
+    warm.check()
+    warm.close()
+    rng = np.random.default_rng(seed)
+    v0 = rng.standard_normal((n, 3)) * np.sqrt(dynamics.KB * T0 * inv_mass)[:, None]
+    v0 -= (v0 / inv_mass[:, None]).sum(axis=0) / (1.0 / inv_mass).sum()  # zero total momentum
+    vel.copy_(torch.tensor(v0, device=dev))
+    e_s, t_s = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(warm_steps, warm_steps + steps):
+        h.build_lists(pos_f, step)
+        if (step - warm_steps) % sample_every == 0 and step > warm_steps:
+            _, ev = h.compute_forces(pos_f, step, out=force, energy=True)
+            k_prev = dyn.kinetic(vel)
+            dyn.step(pos, vel, force, step, pos_copy=pos_f)
+            e_s.append(ev[:5].sum().reshape(1) + 0.5 * (k_prev + dyn.kinetic(vel)))
+            t_s.append((step - warm_steps) * dt)
+        else:
+            h.compute_forces(pos_f, step, out=force)
+            dyn.step(pos, vel, force, step, pos_copy=pos_f)
+    dyn.check()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    e = torch.cat(e_s).cpu().numpy() / n_waters
+    t = np.array(t_s)
+    slope = float(np.polyfit(t, e, 1)[0])
+    h.close()
+    dyn.close()
+    return {"drift_kj_mol_per_ps_per_molecule": slope, "energy_per_molecule_first": float(e[0]),
+            "energy_per_molecule_last": float(e[-1]), "ms_per_step": 1e3 * wall / steps, "steps": steps}
+
+
 def run_electrolyte(valence: int = 1, *, p_shell: int = 10, p_kspace: int = 100, r_core: float = 5.0,
                     r_shell: float = 15.0, alpha: float = 0.03, ke: float = 1.0, dt: float = 0.002,
                     gamma: float = 1.0, equil_steps: int = 20000, prod_steps: int = 80000, sample_every: int = 100,
