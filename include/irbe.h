@@ -353,7 +353,9 @@ irbe_status irbe_dyn_thermostat_state(irbe_dyn_handle d, double* out);
 int64_t irbe_dyn_degrees_of_freedom(irbe_dyn_handle d);
 
 /* Waits on the stream and reports device conditions since the last check:
- * IRBE_ENONFINITE (non-finite position or velocity), IRBE_ECONVERGENCE. */
+ * IRBE_EINVAL (an msd or rdf selection held an index outside [0, N): those
+ * entries were skipped), IRBE_ENONFINITE (non-finite position or velocity),
+ * IRBE_ECONVERGENCE. */
 irbe_status irbe_dyn_check(irbe_dyn_handle d);
 
 const char* irbe_dyn_last_error(irbe_dyn_handle d);  /* NULL: the last create failure */

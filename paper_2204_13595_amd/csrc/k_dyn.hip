@@ -39,7 +39,7 @@ constexpr int kDynBlock = 256;
 constexpr int kPartBlocks = 1024;  // grid of the reductions (grid-stride), one FP64 partial per block
 constexpr int kMaxNewton = 50;
 constexpr double kConstraintTol = 1e-14;  // |s^2 - d^2| / d^2 at convergence
-enum : uint32_t { DYN_NONFINITE = 1u, DYN_NOCONVERGE = 2u };
+enum : uint32_t { DYN_NONFINITE = 1u, DYN_NOCONVERGE = 2u, DYN_BADINDEX = 4u };
 
 struct V3 {
     double x, y, z;
@@ -245,7 +245,8 @@ __global__ __launch_bounds__(kDynBlock) void k_langevin_step(int64_t n_groups, c
 template <int KIND>
 __global__ __launch_bounds__(kDynBlock) void k_sum_partial(int64_t n, const double* __restrict__ a,
                                                            const double* __restrict__ b,
-                                                           const int32_t* __restrict__ sel, double* __restrict__ part)
+                                                           const int32_t* __restrict__ sel, int64_t n_atoms,
+                                                           double* __restrict__ part, uint32_t* err)
 {
     __shared__ double red[kDynBlock / 64];
     double acc = 0.0;
@@ -255,6 +256,10 @@ __global__ __launch_bounds__(kDynBlock) void k_sum_partial(int64_t n, const doub
             acc += 0.5 * dot(v, v) / b[i];
         } else {
             const int64_t j = sel[i];
+            if (j < 0 || j >= n_atoms) {  // a selection outside the system: flagged, not read
+                atomicOr(err, DYN_BADINDEX);
+                continue;
+            }
             const V3 d = load3(a, j) - load3(b, j);
             acc += dot(d, d);
         }
@@ -318,10 +323,11 @@ __global__ void k_copy2(const double* __restrict__ a, double* __restrict__ b)
 // counted in LDS, then added to the caller's 64-bit histogram.
 constexpr int kRdfMaxBins = 8192;
 
-__global__ __launch_bounds__(kDynBlock) void k_rdf(int64_t m, const double* __restrict__ pos,
+__global__ __launch_bounds__(kDynBlock) void k_rdf(int64_t m, const double* __restrict__ pos, int64_t n_atoms,
                                                    const int32_t* __restrict__ sel, int64_t mb,
                                                    const int32_t* __restrict__ sel_b, double box, double r_max,
-                                                   double width, int n_bins, unsigned long long* __restrict__ hist)
+                                                   double width, int n_bins, unsigned long long* __restrict__ hist,
+                                                   uint32_t* err)
 {
 #pragma clang fp contract(off)
     __shared__ uint32_t bins[kRdfMaxBins];
@@ -333,19 +339,30 @@ __global__ __launch_bounds__(kDynBlock) void k_rdf(int64_t m, const double* __re
     const int64_t nb = cross ? mb : m;
     const int64_t a0 = (int64_t)blockIdx.x * kDynBlock;
     const int64_t a = a0 + threadIdx.x;
-    const int32_t ia = a < m ? sel[a] : -1;
-    const V3 pa = a < m ? load3(pos, ia) : V3{0, 0, 0};
+    // selections outside the system are flagged and their atoms skipped (never read)
+    int32_t ia = a < m ? sel[a] : -1;
+    if (a < m && (ia < 0 || ia >= n_atoms)) {
+        atomicOr(err, DYN_BADINDEX);
+        ia = -1;
+    }
+    const bool a_ok = ia >= 0;
+    const V3 pa = a_ok ? load3(pos, ia) : V3{0, 0, 0};
     for (int64_t b0 = cross ? 0 : a0; b0 < nb; b0 += kDynBlock) {
         __syncthreads();
         if (b0 + threadIdx.x < nb) {
-            tile_id[threadIdx.x] = sb[b0 + threadIdx.x];
-            tile[threadIdx.x] = load3(pos, tile_id[threadIdx.x]);
+            int32_t ib = sb[b0 + threadIdx.x];
+            if (ib < 0 || ib >= n_atoms) {
+                atomicOr(err, DYN_BADINDEX);
+                ib = -1;
+            }
+            tile_id[threadIdx.x] = ib;
+            tile[threadIdx.x] = ib >= 0 ? load3(pos, ib) : V3{0, 0, 0};
         }
         __syncthreads();
         const int cnt = (int)min<int64_t>(kDynBlock, nb - b0);
-        if (a < m)
+        if (a_ok)
             for (int t = 0; t < cnt; ++t) {
-                if (cross ? tile_id[t] == ia : b0 + t <= a) continue;
+                if (tile_id[t] < 0 || (cross ? tile_id[t] == ia : b0 + t <= a)) continue;
                 V3 d = tile[t] - pa;
                 d.x = d.x - box * rint(d.x / box);
                 d.y = d.y - box * rint(d.y / box);
@@ -526,7 +543,8 @@ irbe_status irbe_dyn_step(irbe_dyn_handle d, double* pos, double* vel, const voi
                                                                 nh, (float*)pos_copy, d->err);
     DYN_TRY(d, hipGetLastError(), "step");
     if (nose) {
-        k_sum_partial<0><<<kPartBlocks, kDynBlock, 0, d->stream>>>(c.n_atoms, vel, d->inv_mass, nullptr, d->part);
+        k_sum_partial<0><<<kPartBlocks, kDynBlock, 0, d->stream>>>(c.n_atoms, vel, d->inv_mass, nullptr, c.n_atoms,
+                                                                   d->part, d->err);
         DYN_TRY(d, hipGetLastError(), "step");
         k_nh_update<<<1, kDynBlock, 0, d->stream>>>(d->part, (double)d->n_dof * c.kT, c.dt, 1.0 / (c.tau * c.tau),
                                                     d->nh);
@@ -539,7 +557,8 @@ irbe_status irbe_dyn_kinetic(irbe_dyn_handle d, const double* vel, double* out)
 {
     if (!d || !vel || !out) return dyn_fail(d, IRBE_EINVAL, "null argument");
     if (!d->have_system) return dyn_fail(d, IRBE_ESTATE, "set_system first");
-    k_sum_partial<0><<<kPartBlocks, kDynBlock, 0, d->stream>>>(d->cfg.n_atoms, vel, d->inv_mass, nullptr, d->part);
+    k_sum_partial<0><<<kPartBlocks, kDynBlock, 0, d->stream>>>(d->cfg.n_atoms, vel, d->inv_mass, nullptr,
+                                                               d->cfg.n_atoms, d->part, d->err);
     DYN_TRY(d, hipGetLastError(), "kinetic");
     k_sum_final<<<1, kDynBlock, 0, d->stream>>>(d->part, 1.0, out);
     DYN_TRY(d, hipGetLastError(), "kinetic");
@@ -551,7 +570,7 @@ irbe_status irbe_dyn_msd(irbe_dyn_handle d, const double* pos, const double* ref
 {
     if (!d || !pos || !ref || !sel || !out) return dyn_fail(d, IRBE_EINVAL, "null argument");
     if (m < 1 || m > d->cfg.n_atoms) return dyn_fail(d, IRBE_EINVAL, "need 1 <= m <= n_atoms");
-    k_sum_partial<1><<<kPartBlocks, kDynBlock, 0, d->stream>>>(m, pos, ref, sel, d->part);
+    k_sum_partial<1><<<kPartBlocks, kDynBlock, 0, d->stream>>>(m, pos, ref, sel, d->cfg.n_atoms, d->part, d->err);
     DYN_TRY(d, hipGetLastError(), "msd");
     k_sum_final<<<1, kDynBlock, 0, d->stream>>>(d->part, 1.0 / (double)m, out);
     DYN_TRY(d, hipGetLastError(), "msd");
@@ -568,8 +587,9 @@ irbe_status irbe_dyn_rdf(irbe_dyn_handle d, const double* pos, const int32_t* se
     if (!(box > 0.0) || !(r_max > 0.0) || !std::isfinite(box) || !std::isfinite(r_max))
         return dyn_fail(d, IRBE_EINVAL, "need box > 0 and r_max > 0");
     if (m < 1 || (!sel_b && m < 2) || (sel_b && m_b < 1)) return IRBE_OK;
-    k_rdf<<<(unsigned)nblocks(m), kDynBlock, 0, d->stream>>>(m, pos, sel, sel_b ? m_b : 0, sel_b, box, r_max,
-                                                             r_max / n_bins, n_bins, (unsigned long long*)hist);
+    k_rdf<<<(unsigned)nblocks(m), kDynBlock, 0, d->stream>>>(m, pos, d->cfg.n_atoms, sel, sel_b ? m_b : 0, sel_b, box,
+                                                             r_max, r_max / n_bins, n_bins,
+                                                             (unsigned long long*)hist, d->err);
     DYN_TRY(d, hipGetLastError(), "rdf");
     return IRBE_OK;
 }
@@ -593,6 +613,7 @@ irbe_status irbe_dyn_check(irbe_dyn_handle d)
     if (err) {
         k_clear_word<<<1, 1, 0, d->stream>>>(d->err);
         DYN_TRY(d, hipGetLastError(), "check");
+        if (err & DYN_BADINDEX) return dyn_fail(d, IRBE_EINVAL, "an atom selection outside [0, n_atoms)");
         if (err & DYN_NONFINITE) return dyn_fail(d, IRBE_ENONFINITE, "non-finite position or velocity");
         return dyn_fail(d, IRBE_ECONVERGENCE, "constraint iteration did not converge");
     }

@@ -186,3 +186,24 @@ def test_short_electrolyte_run():
     assert np.isfinite(res["u_per_atom"]) and res["u_per_atom"] < 0.0
     for k in ("g+-", "g++", "g--", "msd+", "msd-"):
         assert np.all(np.isfinite(res[k])), k
+
+
+def test_selection_outside_the_system_is_flagged():
+    """msd and rdf skip selection entries outside [0, N) and report them at the next check."""
+    from paper_2204_13595_amd import dynamics, irbe
+    groups, lengths, inv_mass = dynamics.water_topology(4)
+    dev = torch.device("cuda", 0)
+    d = dynamics.Langevin(inv_mass, groups, lengths, dt=0.002, gamma=1.0, kT=1.0, device=dev)
+    pos = torch.tensor(inputs.make_water(4, 2.0).pos, device=dev)
+    bad = torch.tensor([0, 3, 99], dtype=torch.int32, device=dev)
+    m = d.msd(pos, pos, bad)
+    with pytest.raises(irbe.IRBEError):
+        d.check()
+    assert m.item() == 0.0
+    hist = torch.zeros(10, dtype=torch.int64, device=dev)
+    d.rdf(pos, bad, 2.0, 1.0, hist)
+    with pytest.raises(irbe.IRBEError):
+        d.check()
+    assert int(hist.sum().item()) == 1  # the one pair of valid atoms, (0, 3), 0.99 nm apart
+    d.check()  # cleared
+    d.close()
