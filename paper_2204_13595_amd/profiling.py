@@ -3,6 +3,7 @@
     python -m paper_2204_13595_amd.profiling stats <kernel_stats.csv>
     python -m paper_2204_13595_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv> \
         <kernel substring> <out.json>
+    python -m paper_2204_13595_amd.profiling issue <counter_collection.csv> <kernel_stats.csv>
 
 `stats` prints the per-kernel table (calls, average and total duration) of a
 `rocprofv3 --kernel-trace --stats --output-format csv` run. `traffic` turns two
@@ -10,7 +11,12 @@
 of one kernel: the counters (KiB per dispatch) are scaled by what they read for
 the 1 GiB device-to-device copy that `bench.py --copy-probe` performs (1 GiB read,
 1 GiB written), and the result records the hash of the kernel's source file so
-that a later change of the kernel invalidates it.
+that a later change of the kernel invalidates it. `issue` turns a run with
+SQ_INSTS_VALU, SQ_INSTS_SALU and SQ_INSTS_LDS into per-dispatch instruction
+counts and the VALU issue fraction of each kernel: SQ_INSTS_VALU x 4 cycles (one
+wave64 instruction on a 16-lane SIMD) over the SIMD cycles of its average
+duration (1,024 SIMDs at 2.4 GHz), a lower bound on VALU busy time since
+quarter-rate instructions occupy the SIMD longer.
 """
 from __future__ import annotations
 
@@ -82,9 +88,33 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str) -> dict:
     }
 
 
+N_SIMD = 1024
+CLOCK_HZ = 2.4e9
+
+
+def issue_table(counters_csv: str, stats_csv: str) -> str:
+    dur = {short_name(r["Name"]): float(r["AverageNs"]) * 1e-9 for r in csv.DictReader(open(stats_csv))}
+    cols = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS")
+    per = {c: _per_dispatch(counters_csv, c) for c in cols}
+    out = [f"{'kernel':58s} {'avg_us':>9s} {'VALU/disp':>11s} {'SALU/disp':>11s} {'LDS/disp':>11s} {'VALU_issue':>10s}"]
+    rows = []
+    for k, v in per["SQ_INSTS_VALU"].items():
+        if k not in dur:
+            continue
+        valu = sum(v) / len(v)
+        salu = sum(per["SQ_INSTS_SALU"].get(k, [0.0])) / max(len(per["SQ_INSTS_SALU"].get(k, [0.0])), 1)
+        lds = sum(per["SQ_INSTS_LDS"].get(k, [0.0])) / max(len(per["SQ_INSTS_LDS"].get(k, [0.0])), 1)
+        frac = valu * 4.0 / (N_SIMD * CLOCK_HZ * dur[k])
+        rows.append((dur[k], f"{k[:58]:58s} {dur[k] * 1e6:9.1f} {valu:11.4g} {salu:11.4g} {lds:11.4g} {frac:10.3f}"))
+    out += [r for _, r in sorted(rows, reverse=True)]
+    return "\n".join(out)
+
+
 def main(argv):
     if argv[:1] == ["stats"]:
         print(stats_table(argv[1]))
+    elif argv[:1] == ["issue"]:
+        print(issue_table(argv[1], argv[2]))
     elif argv[:1] == ["traffic"]:
         t = traffic(argv[1], argv[2], argv[3])
         json.dump(t, open(argv[4], "w"), indent=1)
