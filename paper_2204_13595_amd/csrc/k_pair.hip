@@ -899,6 +899,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     constexpr int NLJ = 2 * kMaxTypesGrad * kMaxTypesGrad;
     constexpr int NW = kCoopBlock / 64;
     __shared__ LJGrad<real> ljg[256];
+    __shared__ int lj_row[16];  // 1 when some sigma of type t's row is nonzero (else no LJ term or gradient)
     __shared__ double ljacc[NW][NLJ];
     __shared__ int nrec;
     __shared__ double bmaxw[NW];
@@ -917,6 +918,11 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int32_t* kcount = kcap + nkeys;                         // [nkeys] atoms of the row in the LDS window
     const int nt2 = n_types * n_types;
     for (int t = threadIdx.x; t < nt2; t += kCoopBlock) ljg[t] = lj_grad_entry(ljraw_g[t], ljraw_g[nt2 + t], lj_cut);
+    if (threadIdx.x < n_types) {
+        int any = 0;
+        for (int u = 0; u < n_types; ++u) any |= ljraw_g[threadIdx.x * n_types + u] != (real)0;
+        lj_row[threadIdx.x] = any;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (WANT_LJ)
         for (int t = lane; t < NLJ; t += 64) ljacc[wave][t] = 0.0;
@@ -977,6 +983,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const uint4 si = make_uint4(bcast(h_s.x, t_a), bcast(h_s.y, t_a), bcast(h_s.z, t_a),
                                     bcast(h_s.w, t_a));
         const int ti = (int)si.w;
+        // with every sigma of its row zero, the atom has no LJ term and no LJ gradient
+        const bool lj_i = WANT_LJ && lj_row[ti];
         const real qi = bcast(h_q, t_a);
         const real gx = bcast(h_gx, t_a), gy = bcast(h_gy, t_a), gz = bcast(h_gz, t_a);
         const real pgx = gx - mx, pgy = gy - my, pgz = gz - mz;  // G'_i
@@ -1009,7 +1017,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             ry += g.phi * ey_ + g.dphi_r * dy * gd;
             rz += g.phi * ez_ + g.dphi_r * dz * gd;
             rq += ke * qj * g.a_coul * gd;
-            if (WANT_LJ) {
+            if (lj_i) {
                 const real gdi = dx * pgx + dy * pgy + dz * pgz;
                 const int tj = (int)sj.w;
 #pragma unroll
@@ -1070,7 +1078,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                 }
             }
             if (!staged) scatter_atomic(gscat, gqscat, (int64_t)j, jx_, jy_, jz_, jq_);
-            if (WANT_LJ) {
+            if (lj_i) {
                 const int tj = (int)sj.w;
 #pragma unroll
                 for (int t = 0; t < kMaxTypesGrad; ++t)
@@ -1132,7 +1140,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             gself[3 * a + 2] = rz;
             gqself[a] = rq;
         }
-        if (WANT_LJ && ti < kMaxTypesGrad) {
+        if (lj_i && ti < kMaxTypesGrad) {
 #pragma unroll
             for (int t = 0; t < kMaxTypesGrad; ++t) {
                 const real s_sig = wave_sum_r(acc_sig[t]);
