@@ -316,6 +316,51 @@ def skin_lists(make, pos, G, w, args, ms_full, timed_steps, every=10):
     return out
 
 
+def electrolyte_scaling(timed_steps):
+    """The 1:1 primitive-model electrolyte of the paper's scaling runs (density
+    0.01 sigma^-3, reduced units, shifted-truncated LJ, alpha = 0.03, p = 100,
+    r_c = 15) at 10^6 and 10^7 ions: forward step time of RBL+RBE (r_core = 5,
+    p~ = 10) against the full list with the same RBE, with lists rebuilt every
+    step and with a skin of 0.5 sigma and lists rebuilt every 20 steps."""
+    import torch
+
+    from paper_2204_13595_amd import inputs, irbe
+    dev = torch.device("cuda", 0)
+    out = {}
+    for n in (1_000_000, 10_000_000):
+        box = (n / 0.01) ** (1.0 / 3.0)
+        w = inputs.electrolyte(1, n_anions=n // 2, box=box)
+        pos = torch.tensor(w.pos, dtype=torch.float32, device=dev)
+        row = {}
+        for kind, ps, skin, every in (("rbl", 10, 0.0, 1), ("full_list", 0, 0.0, 1), ("rbl_skin", 10, 0.5, 20),
+                                      ("full_list_skin", 0, 0.5, 20)):
+            h = irbe.Handle(w.n_atoms, box, beta=math.sqrt(0.03), r_core=5.0, r_shell=15.0, p_shell=ps,
+                            p_kspace=100, coulomb_k=1.0, lj_cut=2.0 ** (1.0 / 6.0), skin=skin, device=dev)
+            h.set_system(torch.tensor(w.atom_type, device=dev), torch.tensor(w.charge, dtype=torch.float32, device=dev),
+                         torch.tensor(w.molecule, device=dev), w.lj_sigma, w.lj_eps)
+
+            def fwd(step):
+                if step % every == 0:
+                    h.build_lists(pos, step)
+                h.compute_forces(pos, step)
+
+            ms = timed_steps(fwd, every, max(5, 2 * every), 11000) * 1e3
+            st = stage_times(h, fwd, every, 11200)
+            counts = h.debug("counts")
+            h.close()
+            row[kind] = {"ms_per_step": ms, "atom_steps_per_s": w.n_atoms / (ms * 1e-3),
+                         "stage_ms": {k: round(v[0], 3) for k, v in st.items() if v[1]},
+                         "list_entries_per_atom": [int(counts[0]) / w.n_atoms, int(counts[1]) / w.n_atoms]}
+        row["speedup_rbl"] = row["full_list"]["ms_per_step"] / row["rbl"]["ms_per_step"]
+        row["speedup_rbl_skin"] = row["full_list_skin"]["ms_per_step"] / row["rbl_skin"]["ms_per_step"]
+        out[str(w.n_atoms)] = row
+        del pos
+        torch.cuda.empty_cache()
+    out["note"] = ("1:1 electrolyte, density 0.01, L = (N / 0.01)^(1/3); *_skin: skin 0.5 sigma, lists rebuilt every "
+                   "20 steps (static positions); list_entries_per_atom = [core, shell or full]")
+    return out
+
+
 def precision_sweep(timed_steps):
     """FP64 against mixed precision, forward + backward, on the 6,291,456-atom box
     (2,097,152 waters, L = 39.7 nm, p_shell = 100, p = 500): atom-steps/s of
@@ -453,6 +498,8 @@ def main():
         torch.cuda.empty_cache()
         log("precision sweep on the 6.3M-atom box")
         sweep = precision_sweep(timed_steps) if args.workload == "water1M" and args.precision == "mixed" else None
+        log("electrolyte scaling")
+        elec = electrolyte_scaling(timed_steps)
         log("constant-energy water32k")
         from paper_2204_13595_amd import md
         nve = {"rbl": md.run_nve(p_shell=args.p_shell), "full_list": md.run_nve(p_shell=0),
@@ -475,6 +522,7 @@ def main():
             "skin_lists": skin,
             "precision_sweep": sweep,
             "nve_water32k": nve,
+            "electrolyte_scaling": elec,
         }
     else:
         if args.with_backward:

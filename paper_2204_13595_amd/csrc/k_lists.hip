@@ -492,7 +492,12 @@ hipError_t launch_build_lists(irbe_ctx* h)
     }
     const int n_c = g.n_c;
     const bool narrow = 2 * g.reach + 1 <= n_c;
-    const int G = narrow ? std::min(4, n_c - 2 * g.reach) : 1;
+    // cells per wavefront: about 48 atoms (4 cells of water; more in sparse systems,
+    // such as the electrolytes with about one atom per cell), and the union x
+    // range of the group's stencils within one period of the box
+    const double per_cell = (double)h->cfg.n_atoms / (double)g.n_cells;
+    const int g_want = (int)std::lround(std::min(64.0, std::max(4.0, 48.0 / std::max(per_cell, 0.75))));
+    const int G = narrow ? std::max(1, std::min(g_want, n_c - 2 * g.reach)) : 1;
     const int prune = narrow ? 1 : 0;
     const int64_t groups = (int64_t)n_c * n_c * ((n_c + G - 1) / G);
     const PackedGeometry pg = packed_geometry(g, G, narrow);

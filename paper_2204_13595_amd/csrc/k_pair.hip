@@ -582,6 +582,77 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     if (threadIdx.x < 12) part[blk * (int64_t)kPairPartials + threadIdx.x] = out;
 }
 
+// Sparse lists (every atom's core list and batch within a few dozen entries, as
+// in the dilute electrolytes): one thread per atom walks its own core list,
+// excluded partners and batch, so that no wavefront lane idles on an atom with
+// a handful of pairs. Same sums and partials as k_pair_coop (split lists).
+template <typename real, bool EV>
+__global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
+    int64_t n, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
+    const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
+    const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
+    const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
+    int p_stride, const uint16_t* __restrict__ ranks, uint64_t t_core, uint64_t t_shell, bool skin,
+    real* __restrict__ fsr, double* __restrict__ part)
+{
+    __shared__ LJ<real> lj[256];
+    __shared__ double red[kPairPartials * (kCoopBlock / 64)];
+    const int nt2 = n_types * n_types;
+    for (int t = threadIdx.x; t < nt2; t += kCoopBlock) lj[t] = lj_g[t];
+    __syncthreads();
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t a = blk * kCoopBlock + threadIdx.x;
+    double vals[kPairPartials];
+    for (int c = 0; c < kPairPartials; ++c) vals[c] = 0.0;
+    if (a < n) {
+        const uint4 si = spos[a];
+        const real qi = sqr[a] * pp.ke;
+        const LJ<real>* lrow = lj + (int)si.w * n_types;
+        PairSum<real> pc, ps, px;
+        const int nc = ncore[a];
+        const int32_t* crow = core + a * (int64_t)cap_core;
+        for (int c = 0; c < nc; ++c) {
+            const int j = crow[c];
+            const uint4 sj = spos[j];
+            if (!skin || dist2_q(si, sj) <= t_core) add_pair<real, EV>(pc, si, qi, sj, sqr[j], lrow, pp);
+        }
+        const int2 xr = sxr[a];
+        for (int c = 0; c < xr.y; ++c) {
+            const int j = sxidx[xr.x + c];
+            add_excl<real, EV>(px, si, qi, spos[j], sqr[j], pp);
+        }
+        const int ns = nshell[a];
+        const bool sample = ns > p_shell;
+        const int cnt = sample ? p_shell : ns;
+        const int32_t* srow = shell + a * (int64_t)cap_shell;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        for (int c = 0; c < cnt; ++c) {
+            const int j = srow[sample ? (int)rrow[c] : c];
+            const uint4 sj = spos[j];
+            if (!skin || in_annulus(si, sj, t_core, t_shell)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
+        }
+        const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
+        const real fx = pc.fx + w * ps.fx + px.fx;
+        const real fy = pc.fy + w * ps.fy + px.fy;
+        const real fz = pc.fz + w * ps.fz + px.fz;
+        fsr[3 * a + 0] = fx;
+        fsr[3 * a + 1] = fy;
+        fsr[3 * a + 2] = fz;
+        vals[0] = (double)fx;
+        vals[1] = (double)fy;
+        vals[2] = (double)fz;
+        if (EV) {
+            vals[3] = 0.5 * (double)(pc.uc + w * ps.uc);
+            vals[4] = 0.5 * (double)(pc.ul + w * ps.ul);
+            vals[5] = 0.5 * (double)px.uc;
+            for (int c = 0; c < 6; ++c) vals[6 + c] = -0.5 * (double)(pc.v[c] + w * ps.v[c] + px.v[c]);
+        }
+    }
+    double out;
+    block_sum_vec<12, kCoopBlock>(vals, red, threadIdx.x, out);
+    if (threadIdx.x < 12) part[blk * (int64_t)kPairPartials + threadIdx.x] = out;
+}
+
 static StencilArgs stencil_args(const irbe_ctx* h)
 {
     StencilArgs sa;
@@ -673,9 +744,36 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     return hipGetLastError();
 }
 
+template <typename real, bool EV>
+static hipError_t launch_thread_t(irbe_ctx* h, uint64_t step)
+{
+    const int64_t n = h->cfg.n_atoms;
+    PairParams<real> pp;
+    pp.quantum = (real)h->geo.quantum;
+    pp.beta = (real)h->cfg.ewald_beta;
+    pp.cgauss = (real)(2.0 * h->cfg.ewald_beta / 1.7724538509055160273);
+    pp.ke = (real)h->cfg.coulomb_k;
+    hipError_t e = launch_draw(h, step);
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)blocks_for(n, kCoopBlock);
+    if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
+    k_pair_thread<real, EV><<<nb, kCoopBlock, 0, h->stream>>>(
+        n, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core, h->shell, h->nshell,
+        h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride, h->ranks, h->geo.t_core,
+        h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part);
+    h->pair_nb = nb;
+    return hipGetLastError();
+}
+
+// Split lists whose longest core list plus batch stays within this many entries
+// take the thread-per-atom kernel.
+constexpr int kSparsePairs = 32;
+
 template <typename real>
 static hipError_t launch_coop_r(irbe_ctx* h, uint64_t step, bool ev)
 {
+    if (!h->full_list && !h->stencil && h->max_core + std::min(h->max_shell, h->cfg.p_shell) <= kSparsePairs)
+        return ev ? launch_thread_t<real, true>(h, step) : launch_thread_t<real, false>(h, step);
     if (h->full_list)
         return ev ? launch_coop_t<real, true, true, false>(h, step) : launch_coop_t<real, true, false, false>(h, step);
     if (h->stencil)

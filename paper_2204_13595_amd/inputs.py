@@ -146,16 +146,17 @@ class IonSystem:
         return int(self.pos.shape[0])
 
 
-def electrolyte(valence: int = 1, seed: int = 2204, box: float = 80.0) -> IonSystem:
+def electrolyte(valence: int = 1, seed: int = 2204, box: float = 80.0, n_anions: int = 2560) -> IonSystem:
     """Primitive-model electrolyte in reduced units (sigma = 1), the paper's
     electrolyte sizes: 2560 monovalent cations and 2560 anions (valence 1), or
-    1280 divalent cations and 2560 monovalent anions (valence 2), L = 80 sigma.
+    1280 divalent cations and 2560 monovalent anions (valence 2), L = 80 sigma
+    (other sizes: `n_anions` anions and the neutralising cations in `box`).
     Ions sit on the sites of the smallest cubic lattice that holds them (random
     vacancies), jittered by U(-0.1 a, 0.1 a), in random species order. LJ with
     sigma = eps = 1 for every pair (plain, truncated at the shell cutoff)."""
     rng = np.random.default_rng(seed)
-    n_cat = 2560 if valence == 1 else 1280
-    n_an = 2560
+    n_an = int(n_anions)
+    n_cat = n_an if valence == 1 else n_an // 2
     n = n_cat + n_an
     n_side = 1
     while n_side ** 3 < n:

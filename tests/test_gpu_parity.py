@@ -410,3 +410,44 @@ def test_shifted_truncated_lj_parity(orc, precision, tol_f, tol_g):
     for k in range(4):
         assert abs(gl[k] - r_sig[k]) < 10 * tol_g * max(abs(r_sig).max(), 1.0)
         assert abs(gl[4 + k] - r_eps[k]) < 10 * tol_g * max(abs(r_eps).max(), 1.0)
+
+
+@pytest.mark.parametrize("precision,tol_f,tol_e", [("fp64", 1e-11, 1e-10), ("mixed", 1e-5, 2e-5)])
+@pytest.mark.parametrize("skin", [0.0, 0.5])
+def test_sparse_lists_forces_energies(orc, precision, tol_f, tol_e, skin):
+    """The 2:1 electrolyte with the shifted-truncated LJ (a few core entries and a
+    batch of 10 per atom: the thread-per-atom pair kernel), lists with and without
+    a skin, positions moved by just under skin/2 after the build: forces and all
+    energies against the oracle."""
+    from paper_2204_13595_amd import irbe
+    w = inputs.electrolyte(2)
+    beta = math.sqrt(0.03)
+    wca = 2.0 ** (1.0 / 6.0)
+    dev = torch.device("cuda", 0)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    step = 8
+    h = irbe.Handle(w.n_atoms, w.box, beta=beta, r_core=5.0, r_shell=15.0, p_shell=10, p_kspace=100,
+                    coulomb_k=1.0, precision=precision, lj_cut=wca, skin=skin, device=dev)
+    pos = torch.tensor(w.pos, dtype=dt, device=dev)
+    q = torch.tensor(w.charge, dtype=dt, device=dev)
+    h.set_system(torch.tensor(w.atom_type, device=dev), q, torch.tensor(w.molecule, device=dev), w.lj_sigma,
+                 w.lj_eps)
+    h.build_lists(pos, step)
+    pos_np = pos.double().cpu().numpy()
+    p = orc.Params(box=w.box, beta=beta, r_core=5.0, r_shell=15.0, p_shell=10, p_kspace=100, ke=1.0, lj_cut=wca,
+                   skin=skin)
+    lists = orc.build_lists(orc.quantize(pos_np, w.box), w.molecule, w.box, 5.0, 15.0, skin=skin)
+    if skin > 0.0:
+        hh = skin / (2.0 * math.sqrt(3.0)) * 0.999
+        pos = pos + torch.tensor(np.random.default_rng(4).uniform(-hh, hh, size=pos_np.shape), dtype=dt, device=dev)
+        pos_np = pos.double().cpu().numpy()
+    f, ev = h.compute_forces(pos, step, energy=True)
+    h.close()
+    ref = orc.forward(None, q.double().cpu().numpy(), w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step,
+                      mode="rbl", s=orc.quantize(pos_np, w.box), lists=lists)
+    assert lists.core_off[-1] / w.n_atoms < 10  # a sparse system
+    assert _rms_rel(f.double().cpu().numpy(), ref.force) < tol_f
+    ev = ev.cpu().numpy()
+    scale = np.abs(ref.energy[:5]).max()
+    for c in range(11):
+        assert abs(ev[c] - ref.energy[c]) < tol_e * scale, (c, ev[c], ref.energy[c])
