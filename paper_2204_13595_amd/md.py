@@ -136,17 +136,26 @@ def run_water(n_waters: int = 901, box: float = 3.0, *, p_shell: int = 100, p_ks
 TABLE_SETS = [(0.6, 150), (0.7, 100)]
 
 
-def compare(prod_steps: int = 150000, equil_steps: int = 40000, log=None) -> dict:
+def water_sets():
+    """The runs of the water comparison: name -> run_water keyword arguments."""
+    sets = {"full": {"p_shell": 0}}
+    for rc, ps in TABLE_SETS:
+        sets[f"rbl_{rc}_{ps}"] = {"r_core": rc, "p_shell": ps}
+    return sets
+
+
+def compare(prod_steps: int = 150000, equil_steps: int = 40000, log=None, runs: dict | None = None) -> dict:
     """The full-list variant (every pair within r_c, RBE at p = 200) against
     RBL+RBE at the table's sets: max |g_RBL(r) - g_full(r)| over r > 0.2 nm, the
     first-peak height and position, the O mean-squared displacement at the end
-    of the run, and the mean potential energy."""
-    runs = {"full": run_water(p_shell=0, prod_steps=prod_steps, equil_steps=equil_steps, log=log)}
-    for rc, ps in TABLE_SETS:
-        runs[f"rbl_{rc}_{ps}"] = run_water(r_core=rc, p_shell=ps, prod_steps=prod_steps, equil_steps=equil_steps,
-                                           log=log)
-        if log:
-            log(f"done rbl {rc} {ps}")
+    of the run, and the mean potential energy. `runs` (name -> run_water result)
+    compares runs made separately instead."""
+    if runs is None:
+        runs = {}
+        for name, kw in water_sets().items():
+            runs[name] = run_water(prod_steps=prod_steps, equil_steps=equil_steps, log=log, **kw)
+            if log:
+                log(f"done {name}")
     ref = runs["full"]
     mask = ref["r"] > 0.2
     out = {}
@@ -165,8 +174,9 @@ def compare(prod_steps: int = 150000, equil_steps: int = 40000, log=None) -> dic
             "rel_u_diff_vs_full": float(res["u_per_molecule"] / ref["u_per_molecule"] - 1.0),
         }
     out["setup"] = (f"901 rigid waters, L = 3 nm, beta = 3/nm, r_c = 1.2 nm, p = 200, T = 298 K, Nose-Hoover "
-                    f"tau = 1 ps, dt = 1 fs, {equil_steps} equilibration + {prod_steps} production steps, lists "
-                    f"rebuilt every step, mixed precision; MSD over time origins every 5 ps, lags up to 25 ps")
+                    f"tau = 1 ps, dt = 1 fs, {ref['steps']} steps per run of which {ref['frames']} production frames "
+                    f"every 100 steps, lists rebuilt every step, mixed precision; MSD over time origins every 5 ps, "
+                    f"lags up to 25 ps")
     return out
 
 
@@ -355,11 +365,23 @@ def main():
     ap = argparse.ArgumentParser(description="NVT water with the IRBE force")
     ap.add_argument("--compare", action="store_true")
     ap.add_argument("--electrolytes", action="store_true", help="the 1:1 and 2:1 primitive-model comparison")
+    ap.add_argument("--set", help="one run of the water comparison (full, rbl_0.6_150, rbl_0.7_100), as JSON")
+    ap.add_argument("--combine", nargs="+", help="compare the JSON files of separate --set runs")
     ap.add_argument("--prod-steps", type=int, default=150000)
     ap.add_argument("--equil-steps", type=int, default=40000)
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    if args.electrolytes:
+    if args.combine:
+        runs = {}
+        for path in args.combine:
+            d = json.load(open(path))
+            runs[d.pop("name")] = {k: (np.array(v) if isinstance(v, list) else v) for k, v in d.items()}
+        print(json.dumps(compare(runs=runs)), flush=True)
+    elif args.set:
+        res = run_water(prod_steps=args.prod_steps, equil_steps=args.equil_steps, log=log, **water_sets()[args.set])
+        res = {k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in res.items()}
+        print(json.dumps(dict(name=args.set, **res)), flush=True)
+    elif args.electrolytes:
         print(json.dumps(compare_electrolytes(log=log)), flush=True)
     elif args.compare:
         print(json.dumps(compare(args.prod_steps, args.equil_steps, log=log)), flush=True)
