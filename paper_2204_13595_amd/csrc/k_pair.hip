@@ -611,10 +611,22 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
         PairSum<real> pc, ps, px;
         const int nc = ncore[a];
         const int32_t* crow = core + a * (int64_t)cap_core;
-        for (int c = 0; c < nc; ++c) {
-            const int j = crow[c];
-            const uint4 sj = spos[j];
-            if (!skin || dist2_q(si, sj) <= t_core) add_pair<real, EV>(pc, si, qi, sj, sqr[j], lrow, pp);
+        // four entries at a time: their index and position loads go out together
+        for (int c0 = 0; c0 < nc; c0 += 4) {
+            int j[4];
+            uint4 sj[4];
+            real qj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) j[u] = c0 + u < nc ? crow[c0 + u] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sj[u] = spos[max(j[u], 0)];
+                qj[u] = sqr[max(j[u], 0)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j[u] >= 0 && (!skin || dist2_q(si, sj[u]) <= t_core))
+                    add_pair<real, EV>(pc, si, qi, sj[u], qj[u], lrow, pp);
         }
         const int2 xr = sxr[a];
         for (int c = 0; c < xr.y; ++c) {
@@ -626,10 +638,23 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
         const int cnt = sample ? p_shell : ns;
         const int32_t* srow = shell + a * (int64_t)cap_shell;
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
-        for (int c = 0; c < cnt; ++c) {
-            const int j = srow[sample ? (int)rrow[c] : c];
-            const uint4 sj = spos[j];
-            if (!skin || in_annulus(si, sj, t_core, t_shell)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
+        for (int c0 = 0; c0 < cnt; c0 += 4) {
+            int r[4], j[4];
+            uint4 sj[4];
+            real qj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r[u] = c0 + u < cnt ? (sample ? (int)rrow[c0 + u] : c0 + u) : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) j[u] = r[u] >= 0 ? srow[r[u]] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sj[u] = spos[max(j[u], 0)];
+                qj[u] = sqr[max(j[u], 0)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j[u] >= 0 && (!skin || in_annulus(si, sj[u], t_core, t_shell)))
+                    add_pair<real, EV>(ps, si, qi, sj[u], qj[u], lrow, pp);
         }
         const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
         const real fx = pc.fx + w * ps.fx + px.fx;
