@@ -365,6 +365,8 @@ def main():
     ap = argparse.ArgumentParser(description="NVT water with the IRBE force")
     ap.add_argument("--compare", action="store_true")
     ap.add_argument("--electrolytes", action="store_true", help="the 1:1 and 2:1 primitive-model comparison")
+    ap.add_argument("--elec-prod-steps", type=int, default=80000)
+    ap.add_argument("--elec-equil-steps", type=int, default=20000)
     ap.add_argument("--set", help="one run of the water comparison (full, rbl_0.6_150, rbl_0.7_100), as JSON")
     ap.add_argument("--combine", nargs="+", help="compare the JSON files of separate --set runs")
     ap.add_argument("--prod-steps", type=int, default=150000)
@@ -382,7 +384,7 @@ def main():
         res = {k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in res.items()}
         print(json.dumps(dict(name=args.set, **res)), flush=True)
     elif args.electrolytes:
-        print(json.dumps(compare_electrolytes(log=log)), flush=True)
+        print(json.dumps(compare_electrolytes(args.elec_prod_steps, args.elec_equil_steps, log=log)), flush=True)
     elif args.compare:
         print(json.dumps(compare(args.prod_steps, args.equil_steps, log=log)), flush=True)
     else:
