@@ -492,12 +492,19 @@ hipError_t launch_build_lists(irbe_ctx* h)
     }
     const int n_c = g.n_c;
     const bool narrow = 2 * g.reach + 1 <= n_c;
-    // cells per wavefront: about 48 atoms (4 cells of water; more in sparse systems,
-    // such as the electrolytes with about one atom per cell), and the union x
-    // range of the group's stencils within one period of the box
+    // cells per wavefront (measured optima): about 40 atoms for the split and full
+    // lists (3 cells of water), about 76 for the core list alone (6 cells of water,
+    // two passes of 64 lanes: its 9 short stencil rows make the per-row set-up the
+    // larger cost), more cells in sparse systems such as the electrolytes with
+    // about one atom per cell; the union x range of the group's stencils within one
+    // period of the box, and the groups of a cell row balanced (a short last group
+    // leaves its wavefront mostly idle)
     const double per_cell = (double)h->cfg.n_atoms / (double)g.n_cells;
-    const int g_want = (int)std::lround(std::min(64.0, std::max(4.0, 48.0 / std::max(per_cell, 0.75))));
-    const int G = narrow ? std::max(1, std::min(g_want, n_c - 2 * g.reach)) : 1;
+    const double g_atoms = h->stencil ? 76.0 : 40.0, g_min = h->stencil ? 6.0 : 3.0;
+    const int g_want = (int)std::lround(std::min(64.0, std::max(g_min, g_atoms / std::max(per_cell, 0.75))));
+    const int g_cap = narrow ? std::max(1, std::min(g_want, n_c - 2 * g.reach)) : 1;
+    const int groups_per_row = (n_c + g_cap - 1) / g_cap;
+    const int G = (n_c + groups_per_row - 1) / groups_per_row;
     const int prune = narrow ? 1 : 0;
     const int64_t groups = (int64_t)n_c * n_c * ((n_c + G - 1) / G);
     const PackedGeometry pg = packed_geometry(g, G, narrow);
