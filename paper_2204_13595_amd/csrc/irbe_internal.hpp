@@ -21,7 +21,11 @@ constexpr int kPairPartials = 16;    // FP64 values per block of the pair kernel
 constexpr int kRhoChunk = 16;        // k-vectors per block row of the structure factor
 constexpr int kRhoAtomsPerThread = 8;
 constexpr int kMaxTypesGrad = 4;     // LJ parameter gradients: n_types <= 4
-constexpr int kAtomsPerWave = 8;     // atoms per wavefront in the cooperative pair kernels
+// atoms per wavefront in the cooperative pair kernels: the adjoint, the forward
+// kernel with list-drawn batches, and the forward kernel with stencil sampling
+constexpr int kAtomsPerWave = 8;
+constexpr int kAtomsPerWaveList = 4;
+constexpr int kAtomsPerWaveStencil = 16;
 // Shell-adjoint transpose: scatter records staged per block in LDS, then
 // bucketed by destination cell row (y, z) and reduced per row.
 constexpr int kBucketRowLds = 2048;  // atoms of a row accumulated in LDS (the rest: device atomics)

@@ -758,11 +758,14 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     pp.ke = (real)h->cfg.coulomb_k;
     hipError_t e = launch_draw(h, step);
     if (e != hipSuccess) return e;
-    const int64_t waves = blocks_for(n, kAtomsPerWave);
+    // stencil sampling keeps one cell's stencil rows for consecutive atoms: longer
+    // runs of atoms per wavefront pay there, shorter ones with list-drawn batches
+    const int apw = STENCIL ? kAtomsPerWaveStencil : kAtomsPerWaveList;
+    const int64_t waves = blocks_for(n, apw);
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     k_pair_coop<real, FULL, EV, STENCIL><<<nb, kCoopBlock, 0, h->stream>>>(
-        n, kAtomsPerWave, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
+        n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
         h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
