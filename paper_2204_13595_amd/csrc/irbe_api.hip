@@ -392,7 +392,6 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc(h, &h->sq, n));
     ALLOC(dalloc(h, &h->cell_count, (size_t)h->geo.n_cells));
     ALLOC(dalloc(h, &h->cell_start, (size_t)h->geo.n_cells + 1));
-    ALLOC(dalloc(h, &h->cursor, (size_t)h->geo.n_cells));
     ALLOC(dalloc(h, &h->cell_bound, (size_t)h->geo.n_c + 1));
     {
         int64_t m = h->geo.n_cells;

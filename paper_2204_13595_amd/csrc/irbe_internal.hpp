@@ -120,7 +120,6 @@ struct irbe_ctx {
     int32_t* cell_count = nullptr;    // [n_cells]
     int32_t* cell_start = nullptr;    // [n_cells + 1]
     uint32_t* cell_bound = nullptr;   // [n_c + 1] first fixed-point coordinate of each cell row/column
-    int32_t* cursor = nullptr;        // [n_cells]
     std::vector<int32_t*> scan_levels;
     std::vector<int64_t> scan_sizes;
     int32_t* perm = nullptr;          // [N] sorted -> caller id

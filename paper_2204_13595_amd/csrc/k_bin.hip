@@ -71,7 +71,8 @@ __device__ __forceinline__ uint32_t cell_coord(uint32_t s, int n_c) { return (ui
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_quantize_hist(int64_t n, const real* __restrict__ pos, double inv_l,
                                                           int n_c, uint4* __restrict__ sq,
-                                                          int32_t* __restrict__ cell_count, uint32_t* err)
+                                                          int32_t* __restrict__ cell_count,
+                                                          int32_t* __restrict__ slot, uint32_t* err)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_quantize_hist(int64_t n, const real*
     const uint32_t sz = quantize1((double)pos[3 * i + 2], inv_l, bad);
     const uint32_t cell = (cell_coord(sz, n_c) * (uint32_t)n_c + cell_coord(sy, n_c)) * (uint32_t)n_c + cell_coord(sx, n_c);
     sq[i] = make_uint4(sx, sy, sz, cell);
-    atomicAdd(&cell_count[cell], 1);
+    slot[i] = atomicAdd(&cell_count[cell], 1);  // the atom's place among its cell's atoms
     if (bad) atomicOr(err, ERR_NONFINITE);
 }
 
@@ -160,37 +161,35 @@ __global__ void k_scan_total(const int32_t* __restrict__ in, int32_t* __restrict
 
 __global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const uint4* __restrict__ sq,
                                                     const int32_t* __restrict__ cell_start,
-                                                    int32_t* __restrict__ cursor, int32_t* __restrict__ perm)
+                                                    const int32_t* __restrict__ slot, int32_t* __restrict__ perm)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t c = sq[i].w;
-    const int32_t slot = cell_start[c] + atomicAdd(&cursor[c], 1);
-    perm[slot] = (int32_t)i;
+    perm[cell_start[sq[i].w] + slot[i]] = (int32_t)i;
 }
 
-// Order each cell's atoms by (fixed-point x coordinate, atom id): insertion
-// sort (a cell holds a few tens of atoms). Sorting by x lets the list build
-// trim each atom's candidate range to its exact x extent.
-__global__ __launch_bounds__(kBlock) void k_cell_sort(int64_t n_cells, const int32_t* __restrict__ cell_start,
-                                                      const uint4* __restrict__ sq, int32_t* __restrict__ perm)
+// Order each cell's atoms by (fixed-point x coordinate, atom id); sorting by x
+// lets the list build trim each atom's candidate range to its exact x extent.
+// Slot k of the cell-grouped order `in` holds atom i; its place in the cell is
+// the number of the cell's atoms with a smaller key (keys are distinct, as the
+// ids are): one thread per atom over the cell's few tens of atoms, whose loads
+// the threads of one cell share.
+__global__ __launch_bounds__(kBlock) void k_cell_rank(int64_t n, const int32_t* __restrict__ cell_start,
+                                                      const uint4* __restrict__ sq, const int32_t* __restrict__ in,
+                                                      int32_t* __restrict__ perm)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    const int32_t b = cell_start[c], e = cell_start[c + 1];
-    for (int32_t k = b + 1; k < e; ++k) {
-        const int32_t v = perm[k];
-        const uint32_t xv = sq[v].x;
-        int32_t t = k - 1;
-        while (t >= b) {
-            const int32_t u = perm[t];
-            const uint32_t xu = sq[u].x;
-            if (xu < xv || (xu == xv && u < v)) break;
-            perm[t + 1] = u;
-            --t;
-        }
-        perm[t + 1] = v;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t i = in[k];
+    const uint4 si = sq[i];
+    const int32_t b = cell_start[si.w], e = cell_start[si.w + 1];
+    int32_t r = 0;
+    for (int32_t t = b; t < e; ++t) {
+        const int32_t u = in[t];
+        const uint32_t xu = sq[u].x;
+        r += (xu < si.x || (xu == si.x && u < i)) ? 1 : 0;
     }
+    perm[b + r] = i;
 }
 
 template <typename real>
@@ -228,20 +227,20 @@ hipError_t launch_bin(irbe_ctx* h, const void* pos)
     const unsigned nb = (unsigned)blocks_for(n, kBlock);
     hipError_t e = launch_fill_i32(h->stream, h->cell_count, 0, h->geo.n_cells);
     if (e != hipSuccess) return e;
-    e = launch_fill_i32(h->stream, h->cursor, 0, h->geo.n_cells);
-    if (e != hipSuccess) return e;
     if (h->fp64)
         k_quantize_hist<double><<<nb, kBlock, 0, h->stream>>>(n, (const double*)pos, h->geo.inv_l, h->geo.n_c, h->sq,
-                                                              h->cell_count, h->err);
+                                                              h->cell_count, h->smol, h->err);
     else
         k_quantize_hist<float><<<nb, kBlock, 0, h->stream>>>(n, (const float*)pos, h->geo.inv_l, h->geo.n_c, h->sq,
-                                                             h->cell_count, h->err);
+                                                             h->cell_count, h->smol, h->err);
     e = scan_exclusive(h, h->cell_count, h->cell_start, h->geo.n_cells);
     if (e != hipSuccess) return e;
     k_scan_total<<<1, 64, 0, h->stream>>>(h->cell_count, h->cell_start, h->geo.n_cells);
-    k_scatter<<<nb, kBlock, 0, h->stream>>>(n, h->sq, h->cell_start, h->cursor, h->perm);
-    k_cell_sort<<<(unsigned)blocks_for(h->geo.n_cells, kBlock), kBlock, 0, h->stream>>>(h->geo.n_cells,
-                                                                                         h->cell_start, h->sq, h->perm);
+    // the atoms grouped by cell into rank, each at the place its histogram atomic
+    // returned (held in smol), then each cell ordered into perm; rank and smol are
+    // free until k_gather_sorted rewrites them
+    k_scatter<<<nb, kBlock, 0, h->stream>>>(n, h->sq, h->cell_start, h->smol, h->rank);
+    k_cell_rank<<<nb, kBlock, 0, h->stream>>>(n, h->cell_start, h->sq, h->rank, h->perm);
     if (h->fp64)
         k_gather_sorted<double><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const double*)h->q_orig,
                                                               h->mol_orig, h->xoff, h->spos, (double*)h->sq_r,
