@@ -29,8 +29,10 @@ constexpr int kAtomsPerWaveStencil = 16;
 // Shell-adjoint transpose: scatter records staged per block in LDS, then
 // bucketed by destination cell row (y, z) and reduced per row.
 constexpr int kBucketRowLds = 2048;  // atoms of a row accumulated in LDS (the rest: device atomics)
-constexpr int kBucketRecF = 1024;    // staged records per block, FP32
-constexpr int kBucketRecD = 512;     // staged records per block, FP64
+constexpr int kBucketRecF = 1200;    // staged records per block (budget), FP32
+constexpr int kBucketRecD = 600;     // staged records per block (budget), FP64
+constexpr int kBucketRecMaxF = 2048; // staged records per block (LDS limit), FP32
+constexpr int kBucketRecMaxD = 1024; // staged records per block (LDS limit), FP64
 constexpr int kBucketMaxKeys = 256;  // (source row, destination row) keys per block
 constexpr int kBucketSlack = 64;     // records of spare capacity per destination row
 

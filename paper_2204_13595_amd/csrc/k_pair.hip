@@ -1494,8 +1494,17 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
         const double frac = std::min(1.0, 4.0 / 3.0 * 3.14159265358979323846 * (rs * rs * rs - rc * rc * rc) / (span * span * span));
         p_eff = std::max(1, std::min(p_eff, (int)std::ceil(1.3 * frac * h->cfg.p_shell)));
     }
-    const int rec_cap = h->fp64 ? kBucketRecD : kBucketRecF;
-    const int apw = std::min(kAtomsPerWave, rec_cap / (4 * p_eff));
+    // records staged per block: room for the shell terms of every atom of the block
+    // (kCoopBlock / 64 wavefronts of apw atoms, p_eff records each); apw fills a
+    // budget that keeps five blocks on a CU, but is at least 2 (the bucketed
+    // path's minimum) while the records fit the LDS limit (p~ <= 256 in FP32,
+    // 128 in FP64; beyond, the shell terms take device atomics)
+    const int waves_pb = kCoopBlock / 64;
+    const int rec_budget = h->fp64 ? kBucketRecD : kBucketRecF;
+    const int rec_max = h->fp64 ? kBucketRecMaxD : kBucketRecMaxF;
+    int apw = std::min(kAtomsPerWave, std::max(2, rec_budget / (waves_pb * p_eff)));
+    if (waves_pb * apw * p_eff > rec_max) apw = rec_max / (waves_pb * p_eff);
+    const int rec_cap = waves_pb * std::max(apw, 1) * p_eff;
     const int nkeys = 2 * bk.span * bk.span;
     const bool use_bk = !h->full_list && apw >= 2 && nkeys <= kBucketMaxKeys;
     size_t lds = 0;

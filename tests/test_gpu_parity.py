@@ -108,11 +108,13 @@ def test_forces_energies_parity(orc, name, precision, p_shell, tol_f, tol_e):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
 @pytest.mark.parametrize("name,p_shell,moved", [("water512", 100, False), ("water512", 0, False),
-                                                ("water4k", 100, False), ("water4k", 300, False),
-                                                ("water4k", 100, True)])
+                                                ("water4k", 100, False), ("water4k", 200, False),
+                                                ("water4k", 300, False), ("water4k", 100, True)])
 def test_backward_parity(orc, precision, tol, name, p_shell, moved):
-    """p_shell = 100 takes the bucketed shell scatter, 300 the direct-atomic one
-    (a block's records exceed the staging area); `moved` evaluates at positions
+    """p_shell = 100 takes the bucketed shell scatter (two or three atoms per
+    wavefront), 200 too in mixed precision (1,600 staged records per block) and
+    the direct-atomic one in FP64, 300 the direct-atomic one in both (a block's
+    records exceed the staging area); `moved` evaluates at positions
     displaced by up to 0.04 nm after the lists were built, so that some pairs
     leave their build-time cell rows and take the fallback atomics."""
     w = inputs.workload(name)
