@@ -18,8 +18,7 @@ enum : uint32_t { ERR_NONFINITE = 1u, ERR_CORE_CAP = 2u, ERR_SHELL_CAP = 4u };
 constexpr int kBlock = 256;          // threads per block of the per-atom kernels
 constexpr int kReduceBlock = 256;    // threads of the deterministic final reductions
 constexpr int kPairPartials = 16;    // FP64 values per block of the pair kernel
-constexpr int kRhoChunk = 16;        // k-vectors per block row of the structure factor
-constexpr int kRhoAtomsPerThread = 8;
+constexpr int kRhoAtomsPerThread = 8;  // fewest atoms per thread of the structure-factor kernels
 constexpr int kMaxTypesGrad = 4;     // LJ parameter gradients: n_types <= 4
 // atoms per wavefront in the cooperative pair kernels: the adjoint, the forward
 // kernel with list-drawn batches, and the forward kernel with stencil sampling
