@@ -171,6 +171,28 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step);
 irbe_status irbe_compute_forces(irbe_handle h, const void* pos, uint64_t step, void* force, uint32_t flags,
                                 double* energy_virial);
 
+/* irbe_compute_forces for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels, arguments, results and errors, but the
+ * per-call scratch of the evaluation (short-range forces in cell order, the
+ * per-block partial sums, the momentum correction, the sampled k-vectors, the
+ * structure factor and its partials, and the shell batch ranks) is carved from
+ * one static device array of 64 MiB per GPU (held until the process ends)
+ * instead of the handle's buffers. The call never allocates or frees memory and
+ * records no timing events. It needs roughly 3 N real + 2 N ceil4(p_shell)
+ * bytes plus the partials (about 230 bytes per atom at p_shell = 100 in mixed
+ * precision, i.e. up to ~290,000 atoms); larger systems return IRBE_ECAPACITY,
+ * stencil sampling and shell lists longer than 16,384 entries IRBE_EUNSUPPORTED,
+ * all before anything is queued. Every call on one GPU shares that GPU's array:
+ * calls whose queued work overlaps (on different streams, or from different
+ * threads) race and must be serialized by the caller. The array keeps the last
+ * call's contents; nothing in it is read before this call writes it. The
+ * handle's own state is left as irbe_compute_forces would leave it except that
+ * irbe_get_debug's KVEC, RHO, FCORR and BATCH_* selectors still describe the
+ * last irbe_compute_forces, and the next backward redraws the batch. */
+irbe_status irbe_compute_forces_noalloc(irbe_handle h, const void* pos, uint64_t step, void* force, uint32_t flags,
+                                        double* energy_virial);
+
 /* Vector-Jacobian product of irbe_compute_forces at fixed samples and lists:
  * given grad_force = dL/dF [N][3] (device), writes grad_pos = dL/dr [N][3]
  * (device), grad_charge = dL/dq [N] (device, or NULL) and grad_lj =

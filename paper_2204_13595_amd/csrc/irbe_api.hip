@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,7 +20,49 @@
 
 using namespace irbe;
 
+// Per-call scratch of irbe_compute_forces_noalloc: one array per GPU, held
+// until the process ends. Host code never passes this name to a kernel (on the
+// host it only stands in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+// Device address of `scratch` on each device, looked up once per device (with
+// that device current) by the first irbe_create there.
+struct ScratchAddr {
+    bool looked_up = false;
+    void* ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+std::mutex g_scratch_mutex;
+std::vector<ScratchAddr> g_scratch_addr;
+
+void lookup_scratch(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (device < 0) return;
+    if ((size_t)device >= g_scratch_addr.size()) g_scratch_addr.resize((size_t)device + 1);
+    ScratchAddr& a = g_scratch_addr[(size_t)device];
+    if (a.looked_up) return;
+    void* p = nullptr;
+    a.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    a.ptr = a.err == hipSuccess ? p : nullptr;
+    a.looked_up = true;
+}
+
+// The address found for `device`, or nullptr (err says why).
+void* scratch_addr(int device, hipError_t* err)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (device < 0 || (size_t)device >= g_scratch_addr.size() || !g_scratch_addr[(size_t)device].looked_up) {
+        *err = hipErrorNotInitialized;
+        return nullptr;
+    }
+    *err = g_scratch_addr[(size_t)device].err;
+    return g_scratch_addr[(size_t)device].ptr;
+}
 
 thread_local std::string g_create_error;
 
@@ -366,6 +409,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
         return fail(nullptr, IRBE_EUNSUPPORTED, "k table too large (beta L too big)");
     }
     hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) lookup_scratch(h->device);
     const size_t n = (size_t)c.n_atoms;
     const size_t rs = h->real_size;
     const int64_t nb = blocks_for(c.n_atoms, kBlock);
@@ -619,6 +663,98 @@ irbe_status irbe_compute_forces(irbe_handle h, const void* pos, uint64_t step, v
     if (ev) IRBE_STAGE(h, IRBE_STAGE_ENERGY, launch_energy_finalize(h, energy_virial), "energy");
     h->last_force_step = step;
     h->have_force_step = true;
+    return IRBE_OK;
+}
+
+irbe_status irbe_compute_forces_noalloc(irbe_handle h, const void* pos, uint64_t step, void* force, uint32_t flags,
+                                        double* energy_virial)
+{
+    if (!h) return IRBE_EINVAL;
+    if (!pos || !force) return fail(h, IRBE_EINVAL, "irbe_compute_forces_noalloc: null argument");
+    if (flags & ~(uint32_t)(IRBE_ENERGY | IRBE_VIRIAL)) return fail(h, IRBE_EINVAL, "unknown flags");
+    if (flags && !energy_virial) return fail(h, IRBE_EINVAL, "energy/virial requested without a buffer");
+    if (!h->have_lists) return fail(h, IRBE_ESTATE, "irbe_compute_forces_noalloc before irbe_build_lists");
+    if (h->stencil) return fail(h, IRBE_EUNSUPPORTED, "irbe_compute_forces_noalloc: stencil sampling not supported");
+    if (!h->full_list && !draw_bitmaps_in_lds(h))
+        return fail(h, IRBE_EUNSUPPORTED,
+                    "irbe_compute_forces_noalloc: shell lists longer than the batch draw keeps in LDS");
+    hipError_t se = hipSuccess;
+    unsigned char* base = (unsigned char*)scratch_addr(h->device, &se);
+    if (!base) return hip_fail(h, se, "irbe_compute_forces_noalloc: device address of the scratch array");
+
+    // the per-call buffers of one force evaluation, carved from the scratch array
+    const size_t n = (size_t)h->cfg.n_atoms, rs = h->real_size, P = (size_t)h->cfg.p_kspace;
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base + used;
+        used += (bytes + 255) / 256 * 256;
+        return (void*)p;
+    };
+    void* fsr = take(3 * n * rs);
+    double* pair_part = (double*)take((size_t)h->part_blocks * kPairPartials * sizeof(double));
+    double* pair_slices = (double*)take(256 * 12 * sizeof(double));
+    double* ev_pair = (double*)take(kPairPartials * sizeof(double));
+    double* fcorr = (double*)take(3 * sizeof(double));
+    int4* kvec = (int4*)take(P * sizeof(int4));
+    double* kcoef = (double*)take(4 * P * sizeof(double));
+    double* rho_part = (double*)take(2 * P * (size_t)rho_blocks(h->cfg.n_atoms) * sizeof(double));
+    double* rho = (double*)take(2 * P * sizeof(double));
+    void* kforce = take(P * (h->fp64 ? sizeof(KForce<double>) : sizeof(KForce<float>)));
+    uint16_t* ranks = h->p_stride > 0 ? (uint16_t*)take(n * (size_t)h->p_stride * sizeof(uint16_t)) : nullptr;
+    if (used > kNoAllocScratchBytes)
+        return fail(h, IRBE_ECAPACITY,
+                    "irbe_compute_forces_noalloc: this system needs " + std::to_string(used) +
+                        " bytes of scratch; the no-allocation scratch holds " + std::to_string(kNoAllocScratchBytes));
+
+    // the launchers take their buffers from the handle: point it at the carved
+    // buffers for this call and restore its own afterwards (the kernels already
+    // hold the addresses they were given)
+    struct Swap {
+        irbe_ctx* h;
+        void *fsr, *kforce;
+        double *pair_part, *pair_slices, *ev_pair, *fcorr, *kcoef, *rho_part, *rho;
+        int4* kvec;
+        uint16_t* ranks;
+        ~Swap()
+        {
+            h->fsr = fsr;
+            h->kforce = kforce;
+            h->pair_part = pair_part;
+            h->pair_slices = pair_slices;
+            h->ev_pair = ev_pair;
+            h->fcorr = fcorr;
+            h->kcoef = kcoef;
+            h->rho_part = rho_part;
+            h->rho = rho;
+            h->kvec = kvec;
+            h->ranks = ranks;
+            // the draw of this call lived in the scratch array
+            h->ranks_valid = false;
+        }
+    } saved{h, h->fsr, h->kforce, h->pair_part, h->pair_slices, h->ev_pair, h->fcorr, h->kcoef,
+            h->rho_part, h->rho, h->kvec, h->ranks};
+    h->fsr = fsr;
+    h->kforce = kforce;
+    h->pair_part = pair_part;
+    h->pair_slices = pair_slices;
+    h->ev_pair = ev_pair;
+    h->fcorr = fcorr;
+    h->kcoef = kcoef;
+    h->rho_part = rho_part;
+    h->rho = rho;
+    h->kvec = kvec;
+    h->ranks = ranks;
+    h->ranks_valid = false;
+
+    // the launch sequence of irbe_compute_forces, without timing events
+    const bool ev = flags != 0;
+    IRBE_TRY(h, launch_requantize(h, pos), "quantize");
+    IRBE_TRY(h, launch_ksample(h, step), "k sampling");
+    IRBE_TRY(h, launch_rho(h, nullptr, false), "structure factor");
+    IRBE_TRY(h, launch_pair_forces(h, step, ev), "pair forces");
+    IRBE_TRY(h, launch_pair_reduce(h), "pair reduction");
+    IRBE_TRY(h, launch_kspace_forces(h, force), "k-space forces");
+    if (ev) IRBE_TRY(h, launch_energy_finalize(h, energy_virial), "energy");
     return IRBE_OK;
 }
 

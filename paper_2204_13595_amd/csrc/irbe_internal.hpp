@@ -203,6 +203,9 @@ hipError_t launch_build_lists(irbe_ctx* h);
 hipError_t launch_ksample(irbe_ctx* h, uint64_t step);
 hipError_t launch_rho(irbe_ctx* h, const void* grad, bool with_adjoint);
 hipError_t launch_pair_forces(irbe_ctx* h, uint64_t step, bool ev);
+// True when the shell batch draw of the current lists keeps its Floyd bitmaps in
+// LDS (lists of at most 16,384 entries); false when it needs device memory.
+bool draw_bitmaps_in_lds(const irbe_ctx* h);
 hipError_t launch_pair_reduce(irbe_ctx* h);
 hipError_t launch_kspace_forces(irbe_ctx* h, void* force);
 hipError_t launch_energy_finalize(irbe_ctx* h, double* ev);

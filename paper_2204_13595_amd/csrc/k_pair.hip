@@ -707,16 +707,33 @@ hipError_t launch_stencil_decode(irbe_ctx* h)
     return hipGetLastError();
 }
 
+// Threads per block of the batch draw and the LDS its bitmaps take (one bitmap
+// of the longest list per thread); more than 64 KiB means device memory.
+static int draw_block(const irbe_ctx* h, size_t* lds)
+{
+    const int words = (h->max_shell + 31) / 32;
+    int block = 256;
+    while (block > 64 && (size_t)words * block * 4 > 32 * 1024) block /= 2;
+    if (block == 64 && (size_t)words * block * 4 > 64 * 1024) block = 32;
+    *lds = (size_t)words * block * 4;
+    return block;
+}
+
+bool draw_bitmaps_in_lds(const irbe_ctx* h)
+{
+    size_t lds = 0;
+    draw_block(h, &lds);
+    return lds <= 64 * 1024;
+}
+
 // Batch ranks of every atom for `step` (kept until the lists or the step change).
 static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
 {
     if (h->full_list || (h->ranks_valid && h->ranks_step == step)) return hipSuccess;
     const int64_t n = h->cfg.n_atoms;
     const int words = (h->max_shell + 31) / 32;
-    int block = 256;
-    while (block > 64 && (size_t)words * block * 4 > 32 * 1024) block /= 2;
-    if (block == 64 && (size_t)words * block * 4 > 64 * 1024) block = 32;
-    const size_t lds = (size_t)words * block * 4;
+    size_t lds = 0;
+    const int block = draw_block(h, &lds);
     const unsigned nb = (unsigned)blocks_for(n, block);
     if (lds > 64 * 1024) {
         // bitmaps in device memory: as many threads as fit 1 GiB of bitmaps

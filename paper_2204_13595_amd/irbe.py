@@ -35,7 +35,7 @@ STATUS = {0: "IRBE_OK", -1: "IRBE_EINVAL", -2: "IRBE_ENOMEM", -3: "IRBE_EHIP", -
           -5: "IRBE_ESTATE", -6: "IRBE_EUNSUPPORTED", -7: "IRBE_ENONFINITE", -8: "IRBE_ECONVERGENCE"}
 
 EXPORTED = ("irbe_create", "irbe_set_system", "irbe_update_parameters", "irbe_build_lists", "irbe_compute_forces",
-            "irbe_compute_forces_backward", "irbe_sync", "irbe_enable_timing", "irbe_get_timing", "irbe_get_debug",
+            "irbe_compute_forces_backward", "irbe_compute_forces_noalloc", "irbe_sync", "irbe_enable_timing", "irbe_get_timing", "irbe_get_debug",
             "irbe_get_debug_rows", "irbe_last_error", "irbe_destroy", "irbe_dyn_create", "irbe_dyn_set_system",
             "irbe_dyn_step", "irbe_dyn_kinetic", "irbe_dyn_msd", "irbe_dyn_rdf", "irbe_dyn_thermostat_state",
             "irbe_dyn_degrees_of_freedom", "irbe_dyn_check", "irbe_dyn_last_error", "irbe_dyn_destroy")
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.irbe_build_lists.argtypes = [vp, vp, ctypes.c_uint64]
     L.irbe_compute_forces.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_uint32, vp]
     L.irbe_compute_forces_backward.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, vp]
+    L.irbe_compute_forces_noalloc.argtypes = [vp, vp, ctypes.c_uint64, vp, ctypes.c_uint32, vp]
     L.irbe_sync.argtypes = [vp]
     L.irbe_enable_timing.argtypes = [vp, ctypes.c_int32]
     L.irbe_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
@@ -201,6 +202,17 @@ class Handle:
         flags = (IRBE_ENERGY | IRBE_VIRIAL) if energy else 0
         self._check(self.lib.irbe_compute_forces(self.h, _ptr(p), int(step), _ptr(f), flags, _ptr(ev)))
         return (f, ev) if energy else f
+
+    def compute_forces_noalloc(self, pos: torch.Tensor, step: int, out: torch.Tensor,
+                               energy_out: torch.Tensor | None = None):
+        """irbe_compute_forces_noalloc: the caller passes the output buffers (the
+        library allocates nothing during the call)."""
+        p = self._vec(pos, (self.n_atoms, 3), self.dtype)
+        f = self._vec(out, (self.n_atoms, 3), self.dtype)
+        ev = None if energy_out is None else self._vec(energy_out, (11,), torch.float64)
+        flags = 0 if ev is None else (IRBE_ENERGY | IRBE_VIRIAL)
+        self._check(self.lib.irbe_compute_forces_noalloc(self.h, _ptr(p), int(step), _ptr(f), flags, _ptr(ev)))
+        return f
 
     def compute_forces_backward(self, pos: torch.Tensor, step: int, grad_force: torch.Tensor, want_charge=True,
                                 want_lj=True):
