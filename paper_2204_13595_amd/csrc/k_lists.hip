@@ -386,6 +386,235 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lane-per-atom form, for dilute systems (a few atoms per cell, e.g. the
+// primitive-model electrolytes) with cells narrower than the box
+// (2R + 1 <= n_c). The same lists in the same order as k_build_lists_tiled.
+// There every atom's range in a stencil row holds only a handful of candidates,
+// so a half-wave per atom and row idles most of its lanes; here one wavefront
+// takes up to 64 atoms of consecutive cells of one cell row, one atom per lane.
+// For every stencil row (dz, dy) the union of the atoms' x ranges is staged in
+// LDS as above; each lane computes its own cell range in it (row pruning) and
+// the lanes then walk their ranges in lockstep, lane a testing its k-th
+// candidate at step k. A lane appends its shell members (or full-list
+// members) to a ring of 16 entries in LDS and every 8 steps the lanes whose
+// ring holds 8 unwritten entries store them as one aligned 32-byte segment of
+// their list row; core members are stored directly. Candidates between the
+// packed bounds take the exact test on full positions staged beside the
+// packed ones. (In dense cells, such as water's ~13 atoms per cell, the
+// lanes' ranges spread over the staged row and the half-wave form is faster.)
+// ---------------------------------------------------------------------------
+constexpr int kLaneTile = 256;           // staged candidates per pass of a row
+constexpr int kRing = 16;                // ring entries per lane
+constexpr int kSeg = 8;                  // entries per stored segment (32 bytes)
+constexpr int kRingStride = kRing + 1;   // words per lane's ring (odd: conflict-free lanes)
+constexpr double kLaneGroupAtoms = 60.0; // atoms per group the launch aims at (at most 64 per pass)
+constexpr double kLaneMaxPerCell = 4.0;  // mean atoms per cell below which the launch takes this form
+
+template <int MODE>
+__global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
+    int n_c, int lo, int hi, int G, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb,
+    uint64_t t_core, uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos,
+    const int32_t* __restrict__ smol, const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g,
+    int cap_core, int cap_shell, int32_t* __restrict__ core, int32_t* __restrict__ ncore,
+    int32_t* __restrict__ shell, int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt)
+{
+    __shared__ u32x4 trec[kLaneTile + 1];          // packed x | y, packed z, exclusion id, sorted index
+    __shared__ uint32_t tfx[kLaneTile], tfy[kLaneTile], tfz[kLaneTile];  // full fixed-point positions
+    __shared__ int32_t ring[kListWave * kRingStride];
+    __shared__ int32_t tcs[64];                    // union positions of the row's cells (segment A, then B)
+    const uint32_t* bound = bound_g;
+    const int lane = threadIdx.x;
+    const int span = hi - lo + 1;
+    const int groups_per_row = (n_c + G - 1) / G;
+    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int rowid = g / groups_per_row;
+    const int cz = rowid / n_c, cy = rowid % n_c;
+    const int x0 = (g % groups_per_row) * G;
+    const int gr = min(G, n_c - x0);
+    const int home = (cz * n_c + cy) * n_c;
+    const int a0 = cell_start[home + x0], a1 = cell_start[home + x0 + gr];
+    const int span_u = gr - 1 + span;           // cells of the union x range
+    const int xu0 = wrap(x0 + lo, n_c);         // first cell of the union
+    const int lenA = min(span_u, n_c - xu0);    // cells before the wrap
+    const uint32_t orx = bound[x0] + ox, ory = bound[cy] + oyz, orz = bound[cz] + oyz;
+    int32_t* const myring = ring + lane * kRingStride;
+    int maxc = 0, maxs = 0;
+    for (int chunk = a0; chunk < a1; chunk += kListWave) {
+        const int k = chunk + lane;
+        const bool act = k < a1;
+        const uint4 si = act ? spos[k] : make_uint4(0, 0, 0, 0);
+        const int32_t mi = act ? smol[k] : -1;
+        const int cx = (int)(((uint64_t)si.x * (uint32_t)n_c) >> 32);
+        const int ti = act ? wrap(cx - x0, n_c) : 0;  // lane's home cell in [0, gr)
+        const uint32_t axy = pack_rel(si.x, orx, sh) | (pack_rel(si.y, ory, sh) << 16);
+        const uint32_t az = pack_rel(si.z, orz, sh);
+        const uint32_t amol = (uint32_t)(mi >= 0 ? mi : -2 - k);
+        int32_t* const crow = core + (int64_t)k * cap_core;
+        int32_t* const srow = shell + (int64_t)k * cap_shell;
+        int cc = 0, cs = 0;  // list lengths so far
+        int fs = 0;          // shell entries already stored (a multiple of kSeg)
+        for (int dz = lo; dz <= hi; ++dz) {
+            const int z = wrap(cz + dz, n_c);
+            const float gz = (float)slab_gap(si.z, dz, z, bound);
+            for (int dy = lo; dy <= hi; ++dy) {
+                const int y = wrap(cy + dy, n_c);
+                const int row = (z * n_c + y) * n_c;
+                const bool core_row = MODE != kListsFull && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
+                if (MODE == kListsCoreOnly && !core_row) continue;
+                // the lane's range: cells [u_lo, u_hi] of the union, pruned by the row gap
+                int u_lo = ti, u_hi = ti + span - 1;
+                bool need = act;
+                if (act) {
+                    const float gy = (float)slab_gap(si.y, dy, y, bound);
+                    const float rem = tfs_hi - gy * gy - gz * gz;
+                    if (rem < 0.0f) {
+                        need = false;
+                    } else {
+                        const uint32_t ext = (uint32_t)(sqrtf(rem) * 1.000002f) + 2u;
+                        const int cl = (int)(((uint64_t)(uint32_t)(si.x - ext) * (uint32_t)n_c) >> 32);
+                        const int ch = (int)(((uint64_t)(uint32_t)(si.x + ext) * (uint32_t)n_c) >> 32);
+                        int ol = cl - cx, oh = ch - cx;
+                        if (ol > n_c / 2) ol -= n_c;
+                        if (ol < -n_c / 2) ol += n_c;
+                        if (oh > n_c / 2) oh -= n_c;
+                        if (oh < -n_c / 2) oh += n_c;
+                        u_lo = ti + (max(ol, lo) - lo);
+                        u_hi = ti + (min(oh, hi) - lo);
+                    }
+                }
+                if (ballot(need) == 0) continue;
+                const int jA = cell_start[row + xu0];
+                const int nA = cell_start[row + xu0 + lenA] - jA;
+                const int lenB = span_u - lenA;
+                const int jB = cell_start[row];
+                const int total = nA + (lenB > 0 ? cell_start[row + lenB] - jB : 0);
+                __syncthreads();  // the previous row's tables are no longer read
+                if (lane <= span_u)
+                    tcs[lane] = lane < lenA ? cell_start[row + xu0 + lane] - jA
+                                            : nA + cell_start[row + lane - lenA] - jB;
+                __syncthreads();
+                const int p_lo = need ? tcs[u_lo] : 0;
+                const int p_hi = need ? tcs[u_hi + 1] : 0;
+                for (int base = 0; base < total; base += kLaneTile) {
+                    const int cnt = min(kLaneTile, total - base);
+                    if (base > 0) __syncthreads();
+                    for (int t = lane; t < cnt; t += kListWave) {
+                        const int p = base + t;
+                        const int j = p < nA ? jA + p : jB + (p - nA);
+                        const uint4 sj = spos[j];
+                        const int32_t mj = smol[j];
+                        trec[t] = u32x4{pack_rel(sj.x, orx, sh) | (pack_rel(sj.y, ory, sh) << 16),
+                                        pack_rel(sj.z, orz, sh), (uint32_t)(mj >= 0 ? mj : -2 - j), (uint32_t)j};
+                        tfx[t] = sj.x;
+                        tfy[t] = sj.y;
+                        tfz[t] = sj.z;
+                    }
+                    __syncthreads();
+                    // this tile's part of the range, in tile positions
+                    const int s0 = need ? max(p_lo, base) - base : 0;
+                    const int len = need ? max(min(p_hi, base + cnt) - base - s0, 0) : 0;
+                    int steps = len;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
+                    for (int st = 0; st < steps; ++st) {
+                        const bool k_in = st < len;
+                        const int tp = k_in ? s0 + st : kLaneTile;
+                        const u32x4 r = trec[tp];
+                        const uint32_t d2 = d2_packed(r.x, r.y, axy, az);
+                        const bool keep = k_in && r.z != amol;
+                        bool in_core = false, in_shell = false, amb;
+                        if (MODE == kListsCoreOnly) {
+                            in_core = keep && d2 < tb.core_in;
+                            amb = keep && !in_core && d2 <= tb.core_out;
+                        } else if (MODE == kListsSplitSkin) {
+                            const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
+                            const bool l_in = d2 < tb.lo_in, l_out = d2 > tb.lo_out;
+                            const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
+                            in_core = keep && c_in;
+                            in_shell = keep && l_out && s_in;
+                            amb = keep && !((c_in || c_out) && (l_in || (l_out && s_in) || s_out));
+                        } else if (MODE == kListsSplit) {
+                            const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
+                            const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
+                            in_core = keep && c_in;
+                            in_shell = keep && c_out && s_in;
+                            amb = keep && !c_in && !in_shell && !s_out;
+                        } else {
+                            in_shell = keep && d2 < tb.shell_in;
+                            amb = keep && !in_shell && d2 <= tb.shell_out;
+                        }
+                        if (amb) {
+                            // between the bounds: the exact test on full positions decides
+                            const int32_t dx = (int32_t)(tfx[tp] - si.x);
+                            const int32_t dy2 = (int32_t)(tfy[tp] - si.y);
+                            const int32_t dz2 = (int32_t)(tfz[tp] - si.z);
+                            const uint64_t d2x = (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy2 * dy2) +
+                                                 (uint64_t)((int64_t)dz2 * dz2);
+                            in_core = MODE != kListsFull && d2x <= t_core;
+                            in_shell = MODE != kListsCoreOnly &&
+                                       (MODE == kListsSplitSkin ? d2x > t_lo : !in_core) && d2x <= t_shell;
+                        }
+                        if (MODE != kListsCoreOnly && in_shell) {
+                            myring[cs & (kRing - 1)] = (int32_t)r.w;
+                            ++cs;
+                        }
+                        if (MODE != kListsFull && core_row && in_core) {
+                            if (cc < cap_core) crow[cc] = (int32_t)r.w;
+                            ++cc;
+                        }
+                        if (MODE != kListsCoreOnly && (st & (kSeg - 1)) == kSeg - 1) {
+                            // lanes with a full segment store it (at most one per 8 steps)
+                            if (cs - fs >= kSeg) {
+                                const int o = fs & (kRing - 1);
+                                if (fs + kSeg <= cap_shell) {
+                                    int4* dst = (int4*)(srow + fs);
+                                    dst[0] = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
+                                    dst[1] = make_int4(myring[o + 4], myring[o + 5], myring[o + 6], myring[o + 7]);
+                                }
+                                fs += kSeg;
+                            }
+                        }
+                    }
+                    if (MODE != kListsCoreOnly) {
+                        // at most one full segment waits after the last step
+                        if (cs - fs >= kSeg) {
+                            const int o = fs & (kRing - 1);
+                            if (fs + kSeg <= cap_shell) {
+                                int4* dst = (int4*)(srow + fs);
+                                dst[0] = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
+                                dst[1] = make_int4(myring[o + 4], myring[o + 5], myring[o + 6], myring[o + 7]);
+                            }
+                            fs += kSeg;
+                        }
+                    }
+                }
+            }
+        }
+        if (MODE != kListsCoreOnly) {
+            // the last, partial segment
+            for (int e = fs; e < cs; ++e)
+                if (e < cap_shell) srow[e] = myring[e & (kRing - 1)];
+        }
+        if (act) {
+            ncore[k] = cc;
+            if (MODE != kListsCoreOnly) nshell[k] = cs;
+            maxc = max(maxc, cc);
+            maxs = max(maxs, cs);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        maxc = max(maxc, __shfl_xor(maxc, off, 64));
+        maxs = max(maxs, __shfl_xor(maxs, off, 64));
+    }
+    if (lane == 0) {
+        atomicMax(&maxcnt[0], maxc);
+        atomicMax(&maxcnt[1], maxs);
+    }
+}
+
 // Stencil sampling: |K(i)|, the number of atoms in the shell stencil's cells
 // around atom i's cell (span^2 rows of span cells, each row at most two index
 // ranges of the cell-sorted atoms), written as the shell count of every atom
@@ -500,9 +729,15 @@ hipError_t launch_build_lists(irbe_ctx* h)
     // period of the box, and the groups of a cell row balanced (a short last group
     // leaves its wavefront mostly idle)
     const double per_cell = (double)h->cfg.n_atoms / (double)g.n_cells;
-    const double g_atoms = h->stencil ? 76.0 : 40.0, g_min = h->stencil ? 6.0 : 3.0;
+    // dilute cells take the lane-per-atom kernel (up to 64 atoms per pass of its
+    // wavefront, its groups aiming at kLaneGroupAtoms)
+    const bool lanes = narrow && per_cell < kLaneMaxPerCell;
+    const double g_atoms = lanes ? kLaneGroupAtoms : (h->stencil ? 76.0 : 40.0);
+    const double g_min = lanes ? 1.0 : (h->stencil ? 6.0 : 3.0);
     const int g_want = (int)std::lround(std::min(64.0, std::max(g_min, g_atoms / std::max(per_cell, 0.75))));
-    const int g_cap = narrow ? std::max(1, std::min(g_want, n_c - 2 * g.reach)) : 1;
+    int g_cap = narrow ? std::max(1, std::min(g_want, n_c - 2 * g.reach)) : 1;
+    // the lane-per-atom kernel keeps the union's cell starts in 64 LDS words
+    if (lanes) g_cap = std::min(g_cap, 64 - (g.hi - g.lo + 1));
     const int groups_per_row = (n_c + g_cap - 1) / g_cap;
     const int G = (n_c + groups_per_row - 1) / groups_per_row;
     const int prune = narrow ? 1 : 0;
@@ -517,7 +752,20 @@ hipError_t launch_build_lists(irbe_ctx* h)
     n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos, \
         h->smol,                                                                                                  \
         h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt
-    if (h->full_list)
+#define IRBE_LANES_ARGS                                                                                            \
+    n_c, g.lo, g.hi, G, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi,                       \
+        h->spos, h->smol, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,     \
+        h->nshell, h->maxcnt
+    if (lanes) {
+        if (h->full_list)
+            k_build_lists_lanes<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
+        else if (h->stencil)
+            k_build_lists_lanes<kListsCoreOnly><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
+        else if (g.skin)
+            k_build_lists_lanes<kListsSplitSkin><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
+        else
+            k_build_lists_lanes<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
+    } else if (h->full_list)
         k_build_lists_tiled<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
     else if (h->stencil)
         k_build_lists_tiled<kListsCoreOnly><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
@@ -525,6 +773,7 @@ hipError_t launch_build_lists(irbe_ctx* h)
         k_build_lists_tiled<kListsSplitSkin><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
     else
         k_build_lists_tiled<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+#undef IRBE_LANES_ARGS
 #undef IRBE_LISTS_ARGS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !h->stencil) return e;
