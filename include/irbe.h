@@ -41,14 +41,21 @@
  * library owns its scratch (allocated in irbe_create / irbe_set_system, grown in
  * irbe_build_lists, freed in irbe_destroy) and keeps no caller pointer across
  * calls. Every call queues work on the stream given to irbe_create and returns
- * without waiting, except irbe_set_system, irbe_build_lists (one wait, to read
- * the list sizes) and the debug/sync calls. A handle is not thread-safe.
+ * without waiting, except irbe_set_system, the first irbe_build_lists of a
+ * handle (one wait, to size the list rows; with stencil sampling every build
+ * waits once) and the debug/sync calls. A handle is not thread-safe.
  *
  * Errors. Arguments are checked on the host before anything is queued; a bad
  * argument returns IRBE_EINVAL and leaves the handle as it was. Device-side
- * conditions (non-finite positions) set an error word that the next waiting
- * call (irbe_build_lists, irbe_sync, irbe_get_debug) reports. No call aborts or
- * throws; irbe_last_error() describes the most recent failure.
+ * conditions set an error word that the next waiting call (irbe_sync, a
+ * waiting irbe_build_lists) reports and clears: IRBE_ENONFINITE for a
+ * non-finite position, IRBE_ECAPACITY when a build's lists outgrew their rows
+ * (the rows then hold the first entries only, so forces computed from those
+ * lists are incomplete; the rows have been grown and the lists must be built
+ * again). A queued build also reads back, without waiting, the list lengths of
+ * an earlier build once that has completed, and grows the rows for the next
+ * builds when they were too short. No call aborts or throws;
+ * irbe_last_error() describes the most recent failure.
  */
 #ifndef IRBE_H
 #define IRBE_H
@@ -101,8 +108,9 @@ typedef struct {
                               IRBE_SHELL_LIST: S(i), materialized by build_lists,
                               weight N_S / p~ (Eq. (2.11)); IRBE_SHELL_STENCIL:
                               every atom of the shell stencil's cells, K(i)
-                              (Algorithm 1 draws "from its stencils"; Sec. 2.3:
-                              the filter step may be skipped), weight |K(i)| / p~,
+                              (Algorithm 1 draws the batch from the stencil's
+                              cells; Sec. 2.3 lets the distance filter be
+                              skipped), weight |K(i)| / p~,
                               a drawn atom counting only when it is in S(i) at
                               the positions given to compute_forces; build_lists
                               then builds no shell list                           */
@@ -153,10 +161,12 @@ irbe_status irbe_set_system(irbe_handle h, const int32_t* type, const void* char
 irbe_status irbe_update_parameters(irbe_handle h, const void* charge, const double* lj_sigma_host,
                                    const double* lj_eps_host);
 
-/* Bin atoms into cells and build the core and shell lists (Sec. 2.3,
- * Algorithm 1 step "create the core neighbor lists") from pos [N][3] (device).
- * Lists are kept until the next call. Waits once on the stream to read the
- * list sizes; grows the list storage and rebuilds when they exceed it. */
+/* Bin atoms into cells and build the core and shell lists (Sec. 2.3;
+ * Algorithm 1 builds the core lists of every step) from pos [N][3] (device).
+ * Lists are kept until the next call. The first call of a handle (and every
+ * call with stencil sampling) waits once to read the list lengths, grows the
+ * list rows and builds again when they are too short; later calls queue the
+ * build without waiting (see Errors above for rows that turn out too short). */
 irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step);
 
 /* Forces of the last built lists at positions pos (Algorithm 1, force steps):
@@ -197,8 +207,18 @@ irbe_status irbe_compute_forces_noalloc(irbe_handle h, const void* pos, uint64_t
  * given grad_force = dL/dF [N][3] (device), writes grad_pos = dL/dr [N][3]
  * (device), grad_charge = dL/dq [N] (device, or NULL) and grad_lj =
  * [dL/dsigma (n_types^2), dL/deps (n_types^2)] (device, 2 n_types^2 doubles,
- * or NULL; needs n_types <= 4). The shell scatter uses atomics, so results
- * may differ in the last bits from run to run. */
+ * or NULL; needs n_types <= 4).
+ * Run-to-run reproducibility: the one-sided shell terms dL/dr_j of the batch
+ * pairs are staged per block, bucketed by the cell row of j and summed per row
+ * in 64-bit fixed point, an order-independent sum, so the result is bitwise
+ * reproducible for given inputs. The exceptions, records added with FP atomics
+ * whose order varies: all of them with the full list, or when a block's
+ * records do not fit the LDS staging (p_shell above 256 in mixed precision,
+ * 128 in FP64); single records when a block's staging area or a row's bucket
+ * is full, when j's cell row lies outside the stencil window of the block's
+ * rows (positions moved far since the build), or when a cell row holds more
+ * than 2,048 atoms. irbe_get_debug(IRBE_DBG_ADJ_ATOMICS) returns the number of
+ * such records of the last call (-1: all of them). */
 irbe_status irbe_compute_forces_backward(irbe_handle h, const void* pos, uint64_t step, const void* grad_force,
                                          void* grad_pos, void* grad_charge, double* grad_lj);
 
@@ -250,7 +270,10 @@ irbe_status irbe_get_timing(irbe_handle h, double* ms_host, int64_t capacity, in
  *   IRBE_DBG_SCALARS     double [4]         S, H, n_c, R
  *   IRBE_DBG_COUNTS      int64 [4]          total core entries, total shell (or
  *                                           full-list) entries, row capacities
- *                                           (core, shell) of the last build */
+ *                                           (core, shell) of the last build
+ *   IRBE_DBG_ADJ_ATOMICS int64 [1]          shell-adjoint records of the last
+ *                                           compute_forces_backward added with FP
+ *                                           atomics (-1: all of them) */
 enum {
     IRBE_DBG_CELL_START = 1,
     IRBE_DBG_CELL_ATOMS = 2,
@@ -265,7 +288,8 @@ enum {
     IRBE_DBG_FCORR = 11,
     IRBE_DBG_SCALARS = 12,
     IRBE_DBG_COUNTS = 13,
-    IRBE_DBG_BATCH_ATOMS = 14
+    IRBE_DBG_BATCH_ATOMS = 14,
+    IRBE_DBG_ADJ_ATOMICS = 15
 };
 irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written);
 

@@ -247,15 +247,63 @@ hipError_t alloc_lists(irbe_ctx* h, int32_t cap_core, int32_t cap_shell)
     return hipSuccess;
 }
 
+// Rows for lists of the given longest lengths, grown by at least 30% so that a
+// few rounds converge (waits: the old rows may still be read by queued work).
+hipError_t grow_lists(irbe_ctx* h, int32_t max_core, int32_t max_shell)
+{
+    const int32_t nc = max_core > h->cap_core
+                           ? std::max(round_up32(1.15 * max_core + 32.0), round_up32(1.3 * h->cap_core))
+                           : h->cap_core;
+    const int32_t ns = !h->stencil && max_shell > h->cap_shell
+                           ? std::max(round_up32(1.15 * max_shell + 32.0), round_up32(1.3 * h->cap_shell))
+                           : h->cap_shell;
+    if (nc == h->cap_core && ns == h->cap_shell) return hipSuccess;
+    if (ns > 65535) return hipErrorInvalidValue;
+    const hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    h->have_lists = false;
+    return alloc_lists(h, nc, ns);
+}
+
 irbe_status check_device_error(irbe_ctx* h)
 {
     uint32_t err = 0;
+    int32_t mx[2] = {0, 0};
     IRBE_TRY(h, hipMemcpyAsync(&err, h->err, sizeof(err), hipMemcpyDeviceToHost, h->stream), "read error word");
+    IRBE_TRY(h, hipMemcpyAsync(mx, h->maxcnt, sizeof(mx), hipMemcpyDeviceToHost, h->stream), "read list sizes");
     IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
     if (err) {
         IRBE_TRY(h, launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1), "clear error word");
         if (err & ERR_NONFINITE) return fail(h, IRBE_ENONFINITE, "non-finite position");
-        return fail(h, IRBE_ECAPACITY, "list capacity exceeded");
+        // the rows of some build since the last check were too short: the forces
+        // computed from those lists miss entries; grow the rows for the next build
+        const hipError_t e = grow_lists(h, std::max(mx[0], h->max_core), std::max(mx[1], h->max_shell));
+        if (e == hipErrorInvalidValue) return fail(h, IRBE_ECAPACITY, "more than 65535 list entries per atom");
+        if (e != hipSuccess) return hip_fail(h, e, "grow lists");
+        return fail(h, IRBE_ECAPACITY,
+                    "list capacity exceeded by a build since the last check: forces computed from those lists are "
+                    "incomplete; the rows have been grown, build the lists again");
+    }
+    return IRBE_OK;
+}
+
+// Reads back, without waiting, the error word and list lengths of the last
+// asynchronous build once its copy has completed; grows the rows when they
+// were too short (the error stays set for the next waiting call to report).
+irbe_status poll_list_check(irbe_ctx* h)
+{
+    if (!h->chk_pending) return IRBE_OK;
+    const hipError_t q = hipEventQuery(h->chk_event);
+    if (q == hipErrorNotReady) return IRBE_OK;
+    if (q != hipSuccess) return hip_fail(h, q, "list check");
+    h->chk_pending = false;
+    const uint32_t err = (uint32_t)h->chk_host[0];
+    h->max_core = h->chk_host[1];
+    h->max_shell = h->chk_host[2];
+    if (err & (ERR_CORE_CAP | ERR_SHELL_CAP)) {
+        const hipError_t e = grow_lists(h, h->max_core, h->max_shell);
+        if (e == hipErrorInvalidValue) return fail(h, IRBE_ECAPACITY, "more than 65535 list entries per atom");
+        if (e != hipSuccess) return hip_fail(h, e, "grow lists");
     }
     return IRBE_OK;
 }
@@ -425,6 +473,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     if (e == hipSuccess) e = (expr);
     ALLOC(dalloc(h, &h->err, 1));
     ALLOC(dalloc(h, &h->maxcnt, 2));
+    ALLOC(dalloc(h, &h->adj_atomics, 1));
     ALLOC(dalloc(h, &h->ktab, U.size()));
     ALLOC(dalloc_bytes(h, &h->q_orig, n * rs));
     ALLOC(dalloc(h, &h->type_orig, n));
@@ -506,6 +555,8 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
         bound[c] = (uint32_t)((((uint64_t)c << 32) + (uint64_t)h->geo.n_c - 1) / (uint64_t)h->geo.n_c);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->cell_bound, bound.data(), bound.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&h->chk_host, 4 * sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->chk_event, hipEventDisableTiming);
     if (e == hipSuccess) e = launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -621,20 +672,44 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
     h->have_lists = false;
     h->ranks_valid = false;
     h->batch_j_valid = false;
+    if (h->lists_sized && !h->stencil) {
+        // steady state: queue the build and a copy of its error word and list
+        // lengths, and take in an earlier copy if it has completed; no wait
+        const irbe_status st = poll_list_check(h);
+        if (st != IRBE_OK) return st;
+        IRBE_STAGE(h, IRBE_STAGE_BIN, launch_bin(h, pos), "binning");
+        IRBE_TRY(h, launch_fill_i32(h->stream, h->maxcnt, 0, 2), "list build");
+        IRBE_STAGE(h, IRBE_STAGE_LISTS, launch_build_lists(h), "list build");
+        IRBE_TRY(h, hipMemcpyAsync(h->chk_host, h->err, 4, hipMemcpyDeviceToHost, h->stream), "list check");
+        IRBE_TRY(h, hipMemcpyAsync(h->chk_host + 1, h->maxcnt, 8, hipMemcpyDeviceToHost, h->stream), "list check");
+        IRBE_TRY(h, hipEventRecord(h->chk_event, h->stream), "list check");
+        h->chk_pending = true;
+        h->have_lists = true;
+        return IRBE_OK;
+    }
+    // the first build (and every build with stencil sampling, whose stencil
+    // counts size the batch draw): wait for the list lengths and grow the rows
     IRBE_STAGE(h, IRBE_STAGE_BIN, launch_bin(h, pos), "binning");
     for (int attempt = 0; attempt < 3; ++attempt) {
         IRBE_TRY(h, launch_fill_i32(h->stream, h->maxcnt, 0, 2), "list build");
         IRBE_STAGE(h, IRBE_STAGE_LISTS, launch_build_lists(h), "list build");
         int32_t mx[2] = {0, 0};
+        uint32_t err = 0;
         IRBE_TRY(h, hipMemcpyAsync(mx, h->maxcnt, sizeof(mx), hipMemcpyDeviceToHost, h->stream), "read list sizes");
-        const irbe_status st = check_device_error(h);
-        if (st != IRBE_OK) return st;
+        IRBE_TRY(h, hipMemcpyAsync(&err, h->err, sizeof(err), hipMemcpyDeviceToHost, h->stream), "read error word");
+        IRBE_TRY(h, hipStreamSynchronize(h->stream), "synchronize");
+        if (err) {
+            IRBE_TRY(h, launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1), "clear error word");
+            if (err & ERR_NONFINITE) return fail(h, IRBE_ENONFINITE, "non-finite position");
+            // capacity bits of this build: the rows grow below and the lists are built again
+        }
         if (h->stencil && mx[1] > 65535)
             return fail(h, IRBE_EUNSUPPORTED, "more than 65535 atoms in a shell stencil");
         if (mx[0] <= h->cap_core && (h->stencil || mx[1] <= h->cap_shell)) {
             h->max_core = mx[0];
             h->max_shell = mx[1];
             h->have_lists = true;
+            h->lists_sized = true;
             return IRBE_OK;
         }
         const int32_t nc = std::max(h->cap_core, round_up32(1.15 * mx[0] + 32.0));
@@ -910,6 +985,13 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
         copy_out(v, 8, 4);
         return IRBE_OK;
     }
+    case IRBE_DBG_ADJ_ATOMICS: {
+        unsigned long long c = 0;
+        IRBE_TRY(h, d2h(&c, h->adj_atomics, sizeof(c)), "debug");
+        const int64_t v = h->adj_all_atomic ? -1 : (int64_t)c;
+        copy_out(&v, 8, 1);
+        return IRBE_OK;
+    }
     case IRBE_DBG_SCALARS: {
         const double v[4] = {h->kS, h->kH, (double)h->geo.n_c, (double)h->geo.reach};
         copy_out(v, 8, 4);
@@ -1041,6 +1123,8 @@ irbe_status irbe_destroy(irbe_handle h)
     drain_timing(h);
     for (void* p : h->owned) hipFree(p);
     h->owned.clear();
+    if (h->chk_host) hipHostFree(h->chk_host);
+    if (h->chk_event) hipEventDestroy(h->chk_event);
     delete h;
     return IRBE_OK;
 }

@@ -95,7 +95,18 @@ struct irbe_ctx {
     bool have_system = false;
     bool have_lists = false;
     int32_t cap_core = 0, cap_shell = 0;
+    // longest core / shell (or stencil) list of the last build whose lengths the
+    // host has seen: exact after a waiting build, possibly stale after the
+    // asynchronous ones (which only read them back when they have completed), so
+    // only choices of speed use them; sizes that must hold every list use
+    // shell_bound()
     int32_t max_core = 0, max_shell = 0;
+    bool lists_sized = false;         // a waiting build has sized the list rows
+    int32_t* chk_host = nullptr;      // pinned [3]: error word, max core, max shell of the last build
+    hipEvent_t chk_event = nullptr;   // recorded after the copy into chk_host
+    bool chk_pending = false;         // chk_host awaits a completed copy
+    // Upper bound on every atom's shell (or full, or stencil) list length.
+    int32_t shell_bound() const { return stencil ? max_shell : cap_shell; }
     uint64_t last_force_step = 0;
     bool have_force_step = false;
     std::vector<double> lj_sigma_host, lj_eps_host;
@@ -164,6 +175,8 @@ struct irbe_ctx {
     void* bk_c = nullptr;             // real[4 * bk_total] shell-adjoint records: dL/dr_j (3), dL/dq_j
     uint16_t* bk_j = nullptr;         // [bk_total] record's atom, relative to its row's first atom
     int64_t bk_total = 0;             // allocated records
+    unsigned long long* adj_atomics = nullptr;  // [1] shell-adjoint records of the last backward added by atomics
+    bool adj_all_atomic = false;      // the last backward added every shell-adjoint record by atomics
     uint16_t* ranks = nullptr;        // [N * p_stride] shell batch ranks of the current step
     int32_t* batch_j = nullptr;       // [N * p_stride] stencil sampling: the drawn atoms (sorted index, -1: i or
                                       // i's molecule), for the adjoint and read-back, allocated on first use

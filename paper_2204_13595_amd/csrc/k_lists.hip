@@ -110,13 +110,34 @@ __device__ __forceinline__ int member_pos(uint32_t mlo, uint32_t mhi, uint32_t l
 // end (the two lists overlap).
 enum { kListsSplit = 0, kListsFull = 1, kListsCoreOnly = 2, kListsSplitSkin = 3 };
 
+// The list lengths of atom k: the stored lengths never exceed the row
+// capacities, so that every reader stays inside its rows; a longer list sets
+// its bit in the error word (the rows then hold its first entries only) and its
+// true length still reaches maxcnt, from which the host grows the rows.
+template <int MODE>
+__device__ __forceinline__ void store_counts(int k, int cc, int cs, int cap_core, int cap_shell,
+                                             int32_t* __restrict__ ncore, int32_t* __restrict__ nshell,
+                                             uint32_t* __restrict__ err)
+{
+    if (MODE != kListsFull) {
+        ncore[k] = min(cc, cap_core);
+        if (cc > cap_core) atomicOr(err, ERR_CORE_CAP);
+    } else {
+        ncore[k] = cc;
+    }
+    if (MODE != kListsCoreOnly) {
+        nshell[k] = min(cs, cap_shell);
+        if (cs > cap_shell) atomicOr(err, ERR_SHELL_CAP);
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     int n_c, int lo, int hi, int G, int prune, int trim, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb, uint64_t t_core,
     uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const int32_t* __restrict__ smol,
     const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g, int cap_core, int cap_shell,
     int32_t* __restrict__ core, int32_t* __restrict__ ncore, int32_t* __restrict__ shell,
-    int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt)
+    int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt, uint32_t* __restrict__ err)
 {
     __shared__ u32x4 trec[kTileCap + kTilePad];  // candidate: packed x | y, packed z, exclusion id, sorted index
     __shared__ u32x4 apk[kListWave];             // atom: packed x | y, packed z, exclusion id, range start | length << 16
@@ -367,8 +388,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
         __syncthreads();
         if (act) {
             const int2 c = acnt[lane];
-            ncore[k] = c.x;
-            if (MODE != kListsCoreOnly) nshell[k] = c.y;
+            store_counts<MODE>(k, c.x, c.y, cap_core, cap_shell, ncore, nshell, err);
             maxc = max(maxc, c.x);
             maxs = max(maxs, c.y);
         }
@@ -417,7 +437,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
     uint64_t t_core, uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos,
     const int32_t* __restrict__ smol, const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g,
     int cap_core, int cap_shell, int32_t* __restrict__ core, int32_t* __restrict__ ncore,
-    int32_t* __restrict__ shell, int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt)
+    int32_t* __restrict__ shell, int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt,
+    uint32_t* __restrict__ err)
 {
     __shared__ u32x4 trec[kLaneTile + 1];          // packed x | y, packed z, exclusion id, sorted index
     __shared__ uint32_t tfx[kLaneTile], tfy[kLaneTile], tfz[kLaneTile];  // full fixed-point positions
@@ -597,8 +618,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                 if (e < cap_shell) srow[e] = myring[e & (kRing - 1)];
         }
         if (act) {
-            ncore[k] = cc;
-            if (MODE != kListsCoreOnly) nshell[k] = cs;
+            store_counts<MODE>(k, cc, cs, cap_core, cap_shell, ncore, nshell, err);
             maxc = max(maxc, cc);
             maxs = max(maxs, cs);
         }
@@ -624,7 +644,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
 __global__ __launch_bounds__(kBlock) void k_stencil_counts(int n_c, int lo, int span,
                                                            const int32_t* __restrict__ cell_start,
                                                            int32_t* __restrict__ nshell, int32_t* __restrict__ scell,
-                                                           int32_t* __restrict__ maxcnt)
+                                                           int32_t* __restrict__ maxcnt, uint32_t* __restrict__ err)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cells = (int64_t)n_c * n_c * n_c;
@@ -641,8 +661,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil_counts(int n_c, int lo, int 
                 if (span > la) m += cell_start[row + span - la] - cell_start[row];
             }
         }
+        // the batch ranks are 16-bit: a larger stencil is an error (and its count is clamped)
+        if (m > 65535) atomicOr(err, ERR_SHELL_CAP);
         for (int k = cell_start[c]; k < cell_start[c + 1]; ++k) {
-            nshell[k] = m;
+            nshell[k] = min(m, 65535);
             scell[k] = (int32_t)c;
         }
     }
@@ -751,11 +773,12 @@ hipError_t launch_build_lists(irbe_ctx* h)
 #define IRBE_LISTS_ARGS                                                                                           \
     n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos, \
         h->smol,                                                                                                  \
-        h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt
+        h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt,   \
+        h->err
 #define IRBE_LANES_ARGS                                                                                            \
     n_c, g.lo, g.hi, G, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi,                       \
         h->spos, h->smol, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,     \
-        h->nshell, h->maxcnt
+        h->nshell, h->maxcnt, h->err
     if (lanes) {
         if (h->full_list)
             k_build_lists_lanes<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
@@ -781,7 +804,7 @@ hipError_t launch_build_lists(irbe_ctx* h)
     const Geometry& gs = h->geo;
     const int64_t cells = gs.n_cells;
     k_stencil_counts<<<(unsigned)blocks_for(cells, kBlock), kBlock, 0, h->stream>>>(
-        gs.n_c, gs.lo, gs.hi - gs.lo + 1, h->cell_start, h->nshell, h->scell, h->maxcnt);
+        gs.n_c, gs.lo, gs.hi - gs.lo + 1, h->cell_start, h->nshell, h->scell, h->maxcnt, h->err);
     return hipGetLastError();
 }
 

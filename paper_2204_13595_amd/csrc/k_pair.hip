@@ -711,7 +711,7 @@ hipError_t launch_stencil_decode(irbe_ctx* h)
 // of the longest list per thread); more than 64 KiB means device memory.
 static int draw_block(const irbe_ctx* h, size_t* lds)
 {
-    const int words = (h->max_shell + 31) / 32;
+    const int words = (h->shell_bound() + 31) / 32;
     int block = 256;
     while (block > 64 && (size_t)words * block * 4 > 32 * 1024) block /= 2;
     if (block == 64 && (size_t)words * block * 4 > 64 * 1024) block = 32;
@@ -731,7 +731,7 @@ static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
 {
     if (h->full_list || (h->ranks_valid && h->ranks_step == step)) return hipSuccess;
     const int64_t n = h->cfg.n_atoms;
-    const int words = (h->max_shell + 31) / 32;
+    const int words = (h->shell_bound() + 31) / 32;
     size_t lds = 0;
     const int block = draw_block(h, &lds);
     const unsigned nb = (unsigned)blocks_for(n, block);
@@ -992,6 +992,7 @@ struct BucketArgs {
     unsigned long long* rowmax;   // [n_c^2] bits of the largest |record component| (as a non-negative double)
     void* rec_c;                  // real[4 * total]
     uint16_t* rec_j;              // [total]
+    unsigned long long* n_atomic; // records that took device atomics instead of a bucket
 };
 
 __device__ __forceinline__ int64_t bucket_start(const BucketArgs& bk, int row)
@@ -1220,7 +1221,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                     }
                 }
             }
-            if (!staged) scatter_atomic(gscat, gqscat, (int64_t)j, jx_, jy_, jz_, jq_);
+            if (!staged) {
+                scatter_atomic(gscat, gqscat, (int64_t)j, jx_, jy_, jz_, jq_);
+                if (BK) atomicAdd(bk.n_atomic, 1ull);
+            }
             if (lj_i) {
                 const int tj = (int)sj.w;
 #pragma unroll
@@ -1358,6 +1362,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                 bk.rec_j[at] = (uint16_t)0xffffu;  // reserved slot left empty
             }
             scatter_atomic(gscat, gqscat, (int64_t)j, rc[4 * s + 0], rc[4 * s + 1], rc[4 * s + 2], rc[4 * s + 3]);
+            atomicAdd(bk.n_atomic, 1ull);
         }
     }
 }
@@ -1501,7 +1506,7 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
     bk.n_c = h->geo.n_c;
     bk.lo = h->geo.lo;
     bk.span = h->geo.hi - h->geo.lo + 1;
-    int p_eff = std::max(1, std::min(h->cfg.p_shell, std::max(h->max_shell, 1)));
+    int p_eff = std::max(1, std::min(h->cfg.p_shell, std::max(h->shell_bound(), 1)));
     if (h->stencil) {
         // records only for the drawn atoms inside the shell: p~ times the shell's
         // share of the stencil volume, with a margin (the rest take the atomics)
@@ -1533,6 +1538,9 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
         if (e != hipSuccess) return e;
         e = launch_fill_i32(h->stream, (int32_t*)h->bk_cursor, 0, 4 * rows);
         if (e != hipSuccess) return e;
+        e = launch_fill_i32(h->stream, (int32_t*)h->adj_atomics, 0, 2);
+        if (e != hipSuccess) return e;
+        bk.n_atomic = h->adj_atomics;
         bk.cell_start = h->cell_start;
         bk.cursor = h->bk_cursor;
         bk.rowmax = h->bk_cursor + rows;
@@ -1540,6 +1548,7 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
         bk.rec_j = h->bk_j;
         lds = (size_t)rec_cap * (4 * h->real_size + 4) + (size_t)((rec_cap + 1) & ~1) * 2 + (size_t)nkeys * 7 * 4;
     }
+    h->adj_all_atomic = !use_bk;
     if (h->fp64)
         return use_bk ? launch_adj_r<double, true>(h, step, want_lj, apw, bk, rec_cap, lds)
                       : launch_adj_r<double, false>(h, step, want_lj, kAtomsPerWave, bk, 0, 0);

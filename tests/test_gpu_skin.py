@@ -28,6 +28,17 @@ def _rms_rel(a, b):
     return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
 
 
+def _max_atom(a, b):
+    """Largest per-atom error |a_i - b_i| in units of the RMS per-atom magnitude
+    of b. With ~10^4 atoms whose errors scatter normally, the largest is about
+    4.5 times their RMS, so a bound of 20 times the RMS tolerance holds with a
+    margin while a single atom with a wrong or missing term (orders of magnitude
+    above the rounding) fails it."""
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return float(np.sqrt(((a - b) ** 2).sum(1)).max() / np.sqrt((b ** 2).sum(1).mean()))
+
+
 def _moved(pos_np, skin, seed=8):
     """Positions displaced by less than skin / 2 per atom."""
     h = skin / (2.0 * math.sqrt(3.0)) * 0.999
@@ -98,6 +109,7 @@ def test_skin_forces_energies_after_moves(orc, name, skin, mode, precision, tol_
     ref = orc.forward(None, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=step, mode=mode,
                       s=orc.quantize(pos_np, w.box), lists=lists)
     assert _rms_rel(f, ref.force) < tol_f
+    assert _max_atom(f, ref.force) < 20 * tol_f
     scale = np.abs(ref.energy[:5]).max()
     for c in range(11):
         assert abs(ev[c] - ref.energy[c]) < tol_e * scale, (c, ev[c], ref.energy[c])
@@ -128,6 +140,7 @@ def test_skin_backward_after_moves(orc, mode, precision, tol):
     r_pos, r_q, r_sig, r_eps = orc.backward(G_used, q_np, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, ref,
                                             mode=mode)
     assert _rms_rel(gp, r_pos) < tol
+    assert _max_atom(gp, r_pos) < 20 * tol
     assert _rms_rel(gq, r_q) < tol
     assert abs(gl[0] - r_sig[0]) < tol * max(abs(r_sig[0]), 1.0) * 10
     assert abs(gl[4] - r_eps[0]) < tol * max(abs(r_eps[0]), 1.0) * 10
