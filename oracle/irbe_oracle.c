@@ -701,12 +701,16 @@ int orc_kspace_energy(const orc_system* sy, int32_t n_k, const int32_t* kvec, co
  *   dL/dsigma[t_i t_j], dL/deps[t_i t_j] likewise.
  * Runs over every atom (rows are all atoms). Outputs are accumulated.
  */
+/* The terms are those of G'_i . F_i for each listed atom i (rows, or all atoms
+ * when rows is NULL; the lists are per row): for a dL/dF that vanishes outside
+ * the rows and sums to zero, the rows' terms are all the short-range terms. */
 int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, const double* q,
-                            const int32_t* type, const double* lj_sigma, const double* lj_eps,
-                            const int64_t* core_off, const int32_t* core_idx, const int64_t* shell_off,
-                            const int32_t* shell_idx, const int64_t* batch_off, const int32_t* batch_rank,
-                            const double* w, const uint8_t* core_accept, const uint8_t* accept, int rbl,
-                            const double* G, double* g_pos, double* g_q, double* g_sigma, double* g_eps)
+                            const int32_t* type, const double* lj_sigma, const double* lj_eps, const int64_t* rows,
+                            int64_t n_rows, const int64_t* core_off, const int32_t* core_idx,
+                            const int64_t* shell_off, const int32_t* shell_idx, const int64_t* batch_off,
+                            const int32_t* batch_rank, const double* w, const uint8_t* core_accept,
+                            const uint8_t* accept, int rbl, const double* G, double* g_pos, double* g_q,
+                            double* g_sigma, double* g_eps)
 {
     const int nt = sy->n_types;
     const double b = sy->beta, ke = sy->ke, spi = sqrt(ORC_PI);
@@ -716,19 +720,20 @@ int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, 
             for (int a = 0; a < 3; ++a) mean[a] += G[3 * i + a];
         for (int a = 0; a < 3; ++a) mean[a] /= (double)n;
     }
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t i = orc_row_atom(rows, r);
         double gi[3] = {G[3 * i] - mean[0], G[3 * i + 1] - mean[1], G[3 * i + 2] - mean[2]};
         for (int pass = 0; pass < 2; ++pass) {
             int64_t cnt;
-            if (pass == 0) cnt = core_off ? core_off[i + 1] - core_off[i] : 0;
-            else cnt = batch_off ? batch_off[i + 1] - batch_off[i] : shell_off[i + 1] - shell_off[i];
-            double c = pass == 0 ? 1.0 : (w ? w[i] : 1.0);
+            if (pass == 0) cnt = core_off ? core_off[r + 1] - core_off[r] : 0;
+            else cnt = batch_off ? batch_off[r + 1] - batch_off[r] : shell_off[r + 1] - shell_off[r];
+            double c = pass == 0 ? 1.0 : (w ? w[r] : 1.0);
             for (int64_t k = 0; k < cnt; ++k) {
                 int64_t j;
-                if (pass == 0) j = core_idx[core_off[i] + k];
-                else j = shell_idx[shell_off[i] + (batch_off ? batch_rank[batch_off[i] + k] : k)];
-                if (pass == 0 && core_accept && !core_accept[core_off[i] + k]) continue;
-                if (pass == 1 && accept && !accept[(batch_off ? batch_off[i] : shell_off[i]) + k]) continue;
+                if (pass == 0) j = core_idx[core_off[r] + k];
+                else j = shell_idx[shell_off[r] + (batch_off ? batch_rank[batch_off[r] + k] : k)];
+                if (pass == 0 && core_accept && !core_accept[core_off[r] + k]) continue;
+                if (pass == 1 && accept && !accept[(batch_off ? batch_off[r] : shell_off[r]) + k]) continue;
                 double dv[3], r;
                 orc_sep(s, i, j, sy->L, dv, &r);
                 int tp = type[i] * nt + type[j];
@@ -769,13 +774,14 @@ int orc_short_range_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, 
 
 /* Adjoint of the excluded-pair correction (uses G itself: the momentum
  * correction does not cover it). excl lists are per atom over all atoms. */
-int orc_exclusions_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, const double* q,
-                           const int64_t* excl_off, const int64_t* excl_idx, const double* G, double* g_pos,
-                           double* g_q)
+int orc_exclusions_adjoint(const orc_system* sy, const uint32_t* s, const double* q, const int64_t* rows,
+                           int64_t n_rows, const int64_t* excl_off, const int64_t* excl_idx, const double* G,
+                           double* g_pos, double* g_q)
 {
     const double b = sy->beta, ke = sy->ke, spi = sqrt(ORC_PI);
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t k = excl_off[i]; k < excl_off[i + 1]; ++k) {
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t i = orc_row_atom(rows, r);
+        for (int64_t k = excl_off[r]; k < excl_off[r + 1]; ++k) {
             int64_t j = excl_idx[k];
             double dv[3], r;
             orc_sep(s, i, j, sy->L, dv, &r);
@@ -798,6 +804,7 @@ int orc_exclusions_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, c
                 g_q[j] += -ke * q[i] * (Bx - E) * gd;
             }
         }
+    }
     return ORC_OK;
 }
 
@@ -807,11 +814,13 @@ int orc_exclusions_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, c
  * A_l = sum_m q_m g_ml e^{i theta_ml}:
  *   dL/dr_n = -ke q_n sum_l c_l k_l [Re(e^{i theta_nl} conj(A_l)) - g_nl Re(e^{-i theta_nl} rho_l)]
  *   dL/dq_n = -ke sum_l c_l [Im(e^{i theta_nl} conj(A_l)) + g_nl Im(e^{-i theta_nl} rho_l)]
- * rho is over all atoms. Outputs are accumulated.
+ * rho is over all atoms. A_l and the outputs are over the rows (all atoms when
+ * rows is NULL): A_l is exact when G vanishes outside the rows. Outputs are
+ * accumulated at the rows' atoms.
  */
-int orc_kspace_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, const double* q, int32_t n_k,
-                       const int32_t* kvec, const double* wk, const double* rho, const double* G, double* g_pos,
-                       double* g_q)
+int orc_kspace_adjoint(const orc_system* sy, const uint32_t* s, const double* q, const int64_t* rows,
+                       int64_t n_rows, int32_t n_k, const int32_t* kvec, const double* wk, const double* rho,
+                       const double* G, double* g_pos, double* g_q)
 {
     const double L = sy->L, V = L * L * L, tpl = 2.0 * ORC_PI / L;
     double* A = (double*)calloc((size_t)(2 * n_k > 0 ? 2 * n_k : 1), sizeof(double));
@@ -820,7 +829,8 @@ int orc_kspace_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, const
     for (int32_t l = 0; l < n_k; ++l) {
         double k[3] = {tpl * kvec[3 * l], tpl * kvec[3 * l + 1], tpl * kvec[3 * l + 2]};
         double re = 0.0, im = 0.0;
-        for (int64_t m = 0; m < n; ++m) {
+        for (int64_t r = 0; r < n_rows; ++r) {
+            const int64_t m = orc_row_atom(rows, r);
             double th = orc_phase(kvec + 3 * l, s + 3 * m);
             double g = G[3 * m] * k[0] + G[3 * m + 1] * k[1] + G[3 * m + 2] * k[2];
             re += q[m] * g * cos(th);
@@ -830,7 +840,8 @@ int orc_kspace_adjoint(const orc_system* sy, int64_t n, const uint32_t* s, const
         A[2 * l + 1] = im;
     }
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t i = orc_row_atom(rows, r);
         double gp[3] = {0, 0, 0}, gq = 0.0;
         for (int32_t l = 0; l < n_k; ++l) {
             double k[3] = {tpl * kvec[3 * l], tpl * kvec[3 * l + 1], tpl * kvec[3 * l + 2]};

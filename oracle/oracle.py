@@ -95,12 +95,13 @@ def lib():
                                        ctypes.c_int32, _i32p, _f64p, _f64p, _f64p]
         L.orc_kspace_energy.argtypes = [ctypes.POINTER(_System), ctypes.c_int32, _i32p, _f64p, _f64p, _f64p]
         L.orc_short_range_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i32p,
-                                              _f64p, _f64p, _i64p, _i32p, _i64p, _i32p, _i64p, _i32p, _f64p,
-                                              _u8p, _u8p, ctypes.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
-        L.orc_exclusions_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, _i64p, _i64p,
-                                             _f64p, _f64p, _f64p]
-        L.orc_kspace_adjoint.argtypes = [ctypes.POINTER(_System), ctypes.c_int64, _u32p, _f64p, ctypes.c_int32,
-                                         _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]
+                                              _f64p, _f64p, _i64p, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p,
+                                              _i64p, _i32p, _f64p, _u8p, _u8p, ctypes.c_int, _f64p, _f64p, _f64p,
+                                              _f64p, _f64p]
+        L.orc_exclusions_adjoint.argtypes = [ctypes.POINTER(_System), _u32p, _f64p, _i64p, ctypes.c_int64, _i64p,
+                                             _i64p, _f64p, _f64p, _f64p]
+        L.orc_kspace_adjoint.argtypes = [ctypes.POINTER(_System), _u32p, _f64p, _i64p, ctypes.c_int64,
+                                         ctypes.c_int32, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]
         _lib = L
     return _lib
 
@@ -460,6 +461,32 @@ def forward(pos, q, atom_type, mol, lj_sigma, lj_eps, params: Params, step: int 
 def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result, mode: str = "rbl"):
     """Gradients of L = sum_i G_i . F_i with respect to positions, charges and the
     LJ tables, with the lists, batches and k of ``res`` frozen (all atoms)."""
+    assert res.lists.rows is None
+    return _adjoint(G, q, atom_type, mol, lj_sigma, lj_eps, params, res, mode, None)
+
+
+def backward_rows(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result, mode: str = "rbl"):
+    """The same gradients for a dL/dF = G that vanishes outside the rows of
+    ``res`` (a :func:`forward` with ``rows``, its ``rho`` over all atoms) and
+    sums to zero. Then G' = G - mean(G) = G (the adjoint of the momentum
+    correction of Eq. (2.12) is the identity), so every short-range and
+    excluded-pair term of L is a term G_i . f_ij of a row atom i with its own
+    lists and batch, and A_l = sum_m q_m (G_m . k_l) e^{i k_l . r_m} runs over
+    the rows: the rows' lists suffice. Returns dL/dr and dL/dq of the row atoms
+    (in row order) and dL/dsigma, dL/deps (every pair's term)."""
+    rows = res.lists.rows
+    assert rows is not None
+    G = _c(G, np.float64)
+    n = res.s.shape[0]
+    mask = np.zeros(n, dtype=bool)
+    mask[rows] = True
+    assert not np.any(G[~mask]), "dL/dF must vanish outside the rows"
+    assert np.abs(G.sum(axis=0)).max() <= 1e-12 * max(np.abs(G).sum(), 1e-300), "dL/dF must sum to zero"
+    g_pos, g_q, g_sig, g_eps = _adjoint(G, q, atom_type, mol, lj_sigma, lj_eps, params, res, mode, rows)
+    return g_pos[rows], g_q[rows], g_sig, g_eps
+
+
+def _adjoint(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result, mode, rows):
     G = _c(G, np.float64)
     q = _c(q, np.float64)
     atom_type = _c(atom_type, np.int32)
@@ -468,7 +495,8 @@ def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result
     lj_eps = _c(lj_eps, np.float64)
     s = res.s
     n = s.shape[0]
-    assert res.lists.rows is None
+    rows_a = None if rows is None else _c(rows, np.int64)
+    n_rows = n if rows is None else rows_a.shape[0]
     sy = params.system()
     L = lib()
     g_pos = np.zeros((n, 3))
@@ -477,7 +505,8 @@ def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result
     g_eps = np.zeros(params.n_types ** 2)
     rbl = mode in ("rbl", "stencil")
     L.orc_short_range_adjoint(ctypes.byref(sy), n, _p(s, _u32p), _p(q, _f64p), _p(atom_type, _i32p),
-                              _p(lj_sigma, _f64p), _p(lj_eps, _f64p), _p(res.lists.core_off, _i64p),
+                              _p(lj_sigma, _f64p), _p(lj_eps, _f64p), _p(rows_a, _i64p), n_rows,
+                              _p(res.lists.core_off, _i64p),
                               _p(_c(res.lists.core_idx, np.int32), _i32p), _p(res.lists.shell_off, _i64p),
                               _p(_c(res.lists.shell_idx, np.int32), _i32p),
                               _p(res.batch_off if rbl else None, _i64p),
@@ -485,12 +514,12 @@ def backward(G, q, atom_type, mol, lj_sigma, lj_eps, params: Params, res: Result
                               _p(_c(res.weight, np.float64) if rbl else None, _f64p),
                               _p(res.core_accept, _u8p), _p(res.accept, _u8p), int(rbl), _p(G, _f64p),
                               _p(g_pos, _f64p), _p(g_q, _f64p), _p(g_sig, _f64p), _p(g_eps, _f64p))
-    x_off, x_idx = exclusion_lists(mol)
-    L.orc_exclusions_adjoint(ctypes.byref(sy), n, _p(s, _u32p), _p(q, _f64p), _p(x_off, _i64p), _p(x_idx, _i64p),
-                             _p(G, _f64p), _p(g_pos, _f64p), _p(g_q, _f64p))
-    L.orc_kspace_adjoint(ctypes.byref(sy), n, _p(s, _u32p), _p(q, _f64p), res.kvec.shape[0],
-                         _p(res.kvec, _i32p), _p(res.wk, _f64p), _p(_c(res.rho, np.float64), _f64p), _p(G, _f64p),
-                         _p(g_pos, _f64p), _p(g_q, _f64p))
+    x_off, x_idx = exclusion_lists(mol, rows_a)
+    L.orc_exclusions_adjoint(ctypes.byref(sy), _p(s, _u32p), _p(q, _f64p), _p(rows_a, _i64p), n_rows,
+                             _p(x_off, _i64p), _p(x_idx, _i64p), _p(G, _f64p), _p(g_pos, _f64p), _p(g_q, _f64p))
+    L.orc_kspace_adjoint(ctypes.byref(sy), _p(s, _u32p), _p(q, _f64p), _p(rows_a, _i64p), n_rows,
+                         res.kvec.shape[0], _p(res.kvec, _i32p), _p(res.wk, _f64p),
+                         _p(_c(res.rho, np.float64), _f64p), _p(G, _f64p), _p(g_pos, _f64p), _p(g_q, _f64p))
     return g_pos, g_q, g_sig, g_eps
 
 

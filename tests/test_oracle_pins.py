@@ -613,6 +613,44 @@ def test_adjoint_matches_central_differences(orc, mode, skin):
         assert abs(fd - grad[0]) < 1e-5 * max(abs(grad[0]), 1.0)
 
 
+@pytest.mark.parametrize("mode,skin", [("rbl", 0.0), ("full", 0.0), ("stencil", 0.0), ("rbl", 0.1)])
+def test_row_subset_adjoint_matches_full_adjoint(orc, mode, skin):
+    """The row-subset adjoint (lists of the rows only, rho over every atom) for a
+    dL/dF that vanishes outside the rows and sums to zero equals the all-atom
+    adjoint (itself pinned by central differences above): positions and charges
+    of the rows, and the LJ table gradients."""
+    w = _water() if skin == 0.0 else _water("water4k")
+    p = orc.Params(box=w.box, skin=skin)
+    n = w.n_atoms
+    s0 = orc.quantize(w.pos, w.box)
+    pos = _moved(w, skin) if skin > 0.0 else w.pos
+    lists = orc.build_lists(s0, w.molecule, w.box, 0.5, 1.2, skin=skin) if skin > 0.0 else None
+    res = orc.forward(pos, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, mode=mode, step=5,
+                      lists=lists)
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(n, size=300, replace=False))
+    # zero-sum dL/dF on the rows: pairs of rows with opposite values
+    v = rng.standard_normal((150, 3))
+    G = np.zeros((n, 3))
+    perm = rng.permutation(rows)
+    G[perm[0::2]] = v
+    G[perm[1::2]] = -v
+    full = orc.backward(G, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, res, mode=mode)
+    lists_r = (orc.build_lists(s0, w.molecule, w.box, 0.5, 1.2, skin=skin, rows=rows) if skin > 0.0 else None)
+    res_r = orc.forward(pos, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, mode=mode, step=5,
+                        rows=rows, lists=lists_r, kspace=(res.kvec, res.wk, res.S), rho=res.rho)
+    sub = orc.backward_rows(G, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, res_r, mode=mode)
+    scale_p = np.abs(full[0][rows]).max()
+    scale_q = np.abs(full[1][rows]).max()
+    assert np.abs(sub[0] - full[0][rows]).max() < 1e-12 * scale_p
+    assert np.abs(sub[1] - full[1][rows]).max() < 1e-12 * scale_q
+    for a, b in ((sub[2], full[2]), (sub[3], full[3])):
+        assert np.abs(a - b).max() <= 1e-12 * max(np.abs(b).max(), 1e-300)
+    # the rows' gradients are not those of the rows' own terms alone: other rows'
+    # batches and core lists reach them (scatter and symmetric terms)
+    assert np.abs(full[0][rows]).max() > 0
+
+
 # --------------------------------------------------------------------------- virial tensor
 
 def _ewald_energy_sheared(w, frac, hmat, pairs, beta, ke, r_shell, m):
