@@ -54,16 +54,47 @@ def parse():
     return ap.parse_args()
 
 
-def timed_steps(fn, warmup: int, steps: int, first_step: int = 0):
+def timed_steps(fn, warmup: int, steps: int, first_step: int = 0, per_step: list | None = None):
+    """Mean wall-clock seconds per step over `steps` steps after `warmup` untimed
+    ones, synchronized on both sides; `per_step` (if given) receives each step's
+    milliseconds from events recorded between the steps on the current stream."""
     import torch
     for s in range(warmup):
         fn(first_step + s)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_step is not None else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
+        if ev is not None:
+            ev[s].record()
         fn(first_step + warmup + s)
+    if ev is not None:
+        ev[steps].record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    wall = (time.perf_counter() - t0) / steps
+    if ev is not None:
+        per_step.extend(ev[s].elapsed_time(ev[s + 1]) for s in range(steps))
+    return wall
+
+
+def copy_bandwidth():
+    """Measured HBM bandwidth: a 4 GiB device-to-device copy (bytes read plus
+    bytes written over the kernel time, best of five)."""
+    import torch
+    src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    nbytes = 2.0 * src.numel() * 4
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gb_per_s": nbytes / (best * 1e-3) / 1e9, "bytes": nbytes, "ms": best}
 
 
 def stage_times(h, fn, steps: int, first_step: int):
@@ -90,22 +121,49 @@ def measured_traffic(kernel: str, workload: str):
     return t["hbm_bytes_per_launch"]
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, args):
     """The FP64 oracle (lists rebuilt, RBL+RBE forward) on the host cores: one
-    full step of the same workload, timed once (about 10 s of CPU work)."""
+    full step of the benchmark workload (about 10 s of CPU work), and steps of the
+    98,304-atom constant-energy workload (P = 200)."""
     from oracle import oracle as orc
+
+    from paper_2204_13595_amd import inputs
     orc.lib()
     p = orc.Params(box=w.box, p_shell=args.p_shell, p_kspace=args.p_kspace)
     t0 = time.perf_counter()
     orc.forward(w.pos, w.charge, w.atom_type, w.molecule, w.lj_sigma, w.lj_eps, p, step=0, mode="rbl")
     t = time.perf_counter() - t0
     log(f"cpu oracle: one {w.n_atoms}-atom step in {t:.2f} s")
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    w2 = inputs.workload("water32k")
+    p2 = orc.Params(box=w2.box, p_shell=args.p_shell, p_kspace=200)
+    k2 = 3
+    t0 = time.perf_counter()
+    for step in range(k2):
+        orc.forward(w2.pos, w2.charge, w2.atom_type, w2.molecule, w2.lj_sigma, w2.lj_eps, p2, step=step, mode="rbl")
+    t2 = (time.perf_counter() - t0) / k2
+    threads = int(orc.lib().orc_num_threads())
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
     return {
-        "value": w.n_atoms / t, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+        "value": w.n_atoms / t, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
         "sample": (f"one full step (cell lists, core/shell lists, batches, pair forces, momentum correction, "
                    f"k samples, FP64 structure factor, k-space force) of the {w.n_atoms}-atom workload by the FP64 "
                    f"oracle with OpenMP over atoms: {t:.2f} s"),
+        "nproc": nproc, "cpu_model": cpu_model(),
+        "water32k": {"atom_steps_per_s": w2.n_atoms / t2, "s_per_step": t2, "steps": k2,
+                     "workload": "98,304 atoms (32,768 waters, L = 9.93 nm), P_s = 100, P = 200, lists rebuilt"},
     }
 
 
@@ -450,8 +508,10 @@ def main():
         h.compute_forces_backward(pos, step, G)
 
     log("timing forward")
-    ms = timed_steps(fwd, args.warmup, args.steps) * 1e3
+    per_step = []
+    ms = timed_steps(fwd, args.warmup, args.steps, per_step=per_step) * 1e3
     value = n / (ms * 1e-3)
+    ms_median = float(np.median(per_step))
     extras = {}
     if not args.no_extras:
         log("timing forward+backward")
@@ -488,6 +548,7 @@ def main():
             "algorithmic_bytes": list_bytes, "avg_launch_ms": lists_ms,
         }
         roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["measured_copy_gb_per_s"] = copy_bandwidth()["gb_per_s"]
         log("accuracy: two-seed error estimates, matched-error full list, precision")
         acc = accuracy(make, pos, G, w, args, ms, timed_steps)
         log("stencil sampling")
@@ -503,10 +564,14 @@ def main():
         log("constant-energy water32k")
         from paper_2204_13595_amd import md
         nve = {"rbl": md.run_nve(p_shell=args.p_shell), "full_list": md.run_nve(p_shell=0),
-               "note": ("32,768 rigid waters (98,304 atoms, L = 9.93 nm), P = 200, 1000 velocity-Verlet steps at "
-                        "dt = 1 fs from Maxwell velocities at 300 K (zero friction) after 2000 relaxation steps, lists "
-                        "rebuilt every step; "
-                        "drift = slope of the total energy; ms_per_step = lists + forces + integrator")}
+               "full_list_by_p": [md.run_nve(p_shell=0, p_kspace=pk) for pk in (800, 3200)],
+               "full_list_fp64_large_p": md.run_nve(p_shell=0, p_kspace=12800, precision="fp64"),
+               "note": ("32,768 rigid waters (98,304 atoms, L = 9.93 nm), 1000 velocity-Verlet steps at dt = 1 fs "
+                        "from Maxwell velocities at 300 K (zero friction) after 2000 relaxation steps, lists rebuilt "
+                        "every step; P = 200 unless stated; initial_* = slopes over the first 0.1 ps (the heating "
+                        "by the random batch Ewald force, whose variance scales as 1/P); drift = slope over the "
+                        "whole run; trace = temperature and total energy every 50 fs; ms_per_step = lists + forces "
+                        "+ integrator")}
         extras = {
             "fwd_bwd_atom_steps_per_s": n / (ms_fb * 1e-3), "ms_per_step_fwd_bwd": ms_fb,
             "forces_only_reused_lists_atom_steps_per_s": n / (ms_f * 1e-3), "ms_per_forces_only": ms_f,
@@ -532,7 +597,8 @@ def main():
         h.close()
     out = {
         "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "warmup": args.warmup, "ms_per_step": ms, "ms_per_step_median": ms_median, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: {w.n_waters} SPC/E-like waters ({n} atoms), L={w.box} nm, beta=3.0/nm, "

@@ -26,6 +26,7 @@
  * per-k work.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -948,3 +949,6 @@ int orc_exclusion_rows(int64_t n, const int32_t* mol, const int64_t* order, int6
     }
     return ORC_OK;
 }
+
+/* Threads the OpenMP loops of the oracle run on (for reporting its timing). */
+int orc_num_threads(void) { return omp_get_max_threads(); }

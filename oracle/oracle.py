@@ -61,6 +61,8 @@ def lib():
             build_library()
         L = ctypes.CDLL(_SO)
         L.orc_quantize.argtypes = [ctypes.c_int64, ctypes.c_double, _f64p, _u32p]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
         L.orc_n_cells.restype = ctypes.c_int32
         L.orc_n_cells.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_shell_reach.restype = ctypes.c_int32

@@ -189,12 +189,17 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
     velocities at T0 (K), lists rebuilt every step. The synthetic lattice start
     first relaxes for `warm_steps` Langevin steps of h/4 with strong friction
     (untimed); the velocities are then drawn afresh. The total energy
-    E_n = U(x_n) + (K_{n-1/2} + K_{n+1/2}) / 2 is sampled every `sample_every`
-    steps; its drift (least-squares slope) measures the heating by the
-    stochastic force (Sec. 2.2 notes these methods are not meant for long
-    constant-energy runs). Returns the drift in kJ/mol per ps per molecule, the
-    energies, and ms per step (wall clock of the whole loop: lists, forces,
-    integrator)."""
+    E_n = U(x_n) + (K_{n-1/2} + K_{n+1/2}) / 2 and the temperature
+    T = 2 K / (n_dof k_B) are sampled every `sample_every` steps. A stochastic
+    force heats a constant-energy run (Sec. 2.2: these methods are meant for runs
+    with a thermostat): each step adds about (dt^2 / 2m) times the force
+    variance per degree of freedom, and the variance of the random batch Ewald
+    force scales as 1/p (Eq. (2.14)), so the initial heating rate (the slope of
+    the total energy over the first 0.1 ps) scales as 1/p. (The temperature
+    also moves early on as the fresh velocities equilibrate with the relaxed
+    structure, so its slope is no measure of the heating.)
+    Returns the traces, the initial and whole-run slopes, and ms per step (wall
+    clock of the whole loop: lists, forces, integrator)."""
     import torch
 
     from . import dynamics, inputs, irbe
@@ -224,7 +229,7 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
     v0 = rng.standard_normal((n, 3)) * np.sqrt(dynamics.KB * T0 * inv_mass)[:, None]
     v0 -= (v0 / inv_mass[:, None]).sum(axis=0) / (1.0 / inv_mass).sum()  # zero total momentum
     vel.copy_(torch.tensor(v0, device=dev))
-    e_s, t_s = [], []
+    e_s, k_s, t_s = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(warm_steps, warm_steps + steps):
@@ -233,7 +238,9 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
             _, ev = h.compute_forces(pos_f, step, out=force, energy=True)
             k_prev = dyn.kinetic(vel)
             dyn.step(pos, vel, force, step, pos_copy=pos_f)
-            e_s.append(ev[:5].sum().reshape(1) + 0.5 * (k_prev + dyn.kinetic(vel)))
+            k_mid = 0.5 * (k_prev + dyn.kinetic(vel))
+            e_s.append(ev[:5].sum().reshape(1) + k_mid)
+            k_s.append(k_mid.reshape(1))
             t_s.append((step - warm_steps) * dt)
         else:
             h.compute_forces(pos_f, step, out=force)
@@ -242,12 +249,23 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     e = torch.cat(e_s).cpu().numpy() / n_waters
+    temp = 2.0 * torch.cat(k_s).cpu().numpy() / (dyn.n_dof * dynamics.KB)
     t = np.array(t_s)
     slope = float(np.polyfit(t, e, 1)[0])
+    early = t <= 0.1 + 1e-9
+    slope0 = float(np.polyfit(t[early], e[early], 1)[0]) if early.sum() >= 3 else float("nan")
     h.close()
     dyn.close()
-    return {"drift_kj_mol_per_ps_per_molecule": slope, "energy_per_molecule_first": float(e[0]),
-            "energy_per_molecule_last": float(e[-1]), "ms_per_step": 1e3 * wall / steps, "steps": steps}
+    thin = max(1, len(t) // 20)
+    return {"p_kspace": p_kspace, "p_shell": p_shell, "precision": precision,
+            "initial_drift_kj_mol_per_ps_per_molecule": slope0,
+            "drift_kj_mol_per_ps_per_molecule": slope, "energy_per_molecule_first": float(e[0]),
+            "energy_per_molecule_last": float(e[-1]), "temperature_first_K": float(temp[0]),
+            "temperature_last_K": float(temp[-1]),
+            "trace": {"t_ps": [round(float(x), 4) for x in t[::thin]],
+                      "temperature_K": [round(float(x), 2) for x in temp[::thin]],
+                      "energy_per_molecule": [round(float(x), 3) for x in e[::thin]]},
+            "ms_per_step": 1e3 * wall / steps, "steps": steps}
 
 
 def run_electrolyte(valence: int = 1, *, p_shell: int = 10, p_kspace: int = 100, r_core: float = 5.0,
