@@ -21,13 +21,16 @@
 // Candidate test. Atoms and staged candidates also carry their position
 // relative to an origin at the wavefront's cells, in units of 2^s quanta and
 // truncated to 16 bits per axis (s is the smallest shift at which every such
-// coordinate of the stencil fits). A packed 16-bit subtraction and two-term
-// integer dot products give a squared separation d2 whose components are off
-// by less than delta units each, so d2 below an inner bound proves
-// membership and d2 above an outer bound proves non-membership; only the
-// candidates in between (about one per atom) take the exact 64-bit test, on
-// positions read from memory. The LDS footprint (about 6 KB per wavefront)
-// leaves room for six or more wavefronts per SIMD.
+// coordinate of the stencil fits). A packed 16-bit subtraction, a two-term
+// integer dot product and a 24-bit multiply give a squared separation d2
+// whose components are off by less than delta units each, so d2 below an
+// inner bound proves membership and d2 above an outer bound proves
+// non-membership. The candidates in between (about one per atom) take a
+// second test on the same coordinates extended by the next 5 bits per axis
+// (kept in the unused half of the packed z word), whose band is 32 times
+// narrower; the few left after it take the exact 64-bit test on positions
+// read from memory. The LDS footprint (about 6 KB per wavefront) leaves room
+// for six or more wavefronts per SIMD.
 //
 // Layout: fixed-capacity rows (row k of atom k in cell order), entries are
 // cell-sorted atom indices. Counts beyond the capacity are still counted, so
@@ -52,11 +55,15 @@ constexpr int kNoStore = 0x7fffffff;      // buffer offset beyond any list descr
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Integer bounds on the packed squared separation d2: d2 < *_in proves
-// membership of the ball, d2 > *_out proves the opposite.
-struct PackedBounds {
-    uint32_t core_in, core_out, shell_in, shell_out, lo_in, lo_out;
+// Integer bounds on an approximate squared separation d2: d2 < *_in proves
+// membership of the ball, d2 > *_out proves the opposite. PackedBounds for
+// the packed 16-bit coordinates, MidBounds for those extended by e bits.
+template <typename T>
+struct Bounds {
+    T core_in, core_out, shell_in, shell_out, lo_in, lo_out;
 };
+using PackedBounds = Bounds<uint32_t>;
+using MidBounds = Bounds<uint64_t>;
 
 __device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
@@ -77,12 +84,38 @@ __device__ __forceinline__ uint32_t pack_rel(uint32_t c, uint32_t o, int sh)
 }
 
 // Squared separation of two packed positions (x | y << 16, z): exact in the
-// 16-bit units; the sum of the three squares stays below 2^32.
+// 16-bit units (differences modulo 2^16); the sum of the three squares stays
+// below 2^32.
 __device__ __forceinline__ uint32_t d2_packed(uint32_t cxy, uint32_t cz, uint32_t axy, uint32_t az)
 {
     const s16x2 dxy = __builtin_bit_cast(s16x2, cxy) - __builtin_bit_cast(s16x2, axy);
-    const s16x2 dz = __builtin_bit_cast(s16x2, cz) - __builtin_bit_cast(s16x2, az);
-    return (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, __builtin_amdgcn_sdot2(dz, dz, 0, false), false);
+    const int dz = (short)(cz - az);
+    return (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, dz * dz, false);
+}
+
+// The next e bits below the packed ones (e = min(s, 5)) of the three
+// coordinates relative to the origin, x | y << 5 | z << 10, kept in the upper
+// half of the packed z word.
+__device__ __forceinline__ uint32_t ext_rel(uint4 p, uint32_t ox, uint32_t oy, uint32_t oz, int sh, int e)
+{
+    const uint32_t m = (1u << e) - 1u;
+    const int se = sh - e;
+    const uint32_t x = (uint32_t)((int32_t)(p.x - ox) >> se) & m;
+    const uint32_t y = (uint32_t)((int32_t)(p.y - oy) >> se) & m;
+    const uint32_t z = (uint32_t)((int32_t)(p.z - oz) >> se) & m;
+    return (x | (y << 5) | (z << 10)) << 16;
+}
+
+// Squared separation of two packed positions in units of 2^(s - e) quanta
+// from the packed coordinates and their extension bits (each component off by
+// less than one unit, as the packed test in its own units).
+__device__ __forceinline__ uint64_t d2_mid(uint32_t cxy, uint32_t cz, uint32_t axy, uint32_t az, int e)
+{
+    auto m = [e](uint32_t p, uint32_t x) { return (int32_t)(((uint32_t)(int32_t)(int16_t)(p & 0xffffu) << e) | (x & 31u)); };
+    const int32_t dx = m(cxy, cz >> 16) - m(axy, az >> 16);
+    const int32_t dy = m(cxy >> 16, cz >> 21) - m(axy >> 16, az >> 21);
+    const int32_t dz = m(cz, cz >> 26) - m(az, az >> 26);
+    return (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
 }
 
 __device__ __forceinline__ uint64_t dist2_exact(uint4 a, uint4 b)
@@ -131,10 +164,102 @@ __device__ __forceinline__ void store_counts(int k, int cc, int cs, int cap_core
     }
 }
 
+// Wave masks of the lanes in keep that the bounds b settle as members of C(i)
+// (mc) and of S(i) (ms), and of those they leave open (amb); each mask is the
+// AND of ballots of single compares (scalar operations only).
+template <int MODE, bool CORE, typename D>
+__device__ __forceinline__ void classify(D d2, const Bounds<D>& b, uint64_t keep, uint64_t& mc, uint64_t& ms,
+                                         uint64_t& amb)
+{
+    if (CORE && MODE == kListsCoreOnly) {
+        mc = keep & ballot(d2 < b.core_in);
+        ms = 0;
+        amb = keep & ~ballot(d2 > b.core_out) & ~mc;
+    } else if (CORE && MODE == kListsSplitSkin) {
+        const uint64_t b_cin = ballot(d2 < b.core_in), b_lout = ballot(d2 > b.lo_out);
+        const uint64_t b_sin = ballot(d2 < b.shell_in);
+        mc = keep & b_cin;
+        ms = keep & b_lout & b_sin;
+        // settled: C(i) either way, and S(i) below t_lo, inside, or beyond t_shell
+        const uint64_t set_c = b_cin | ballot(d2 > b.core_out);
+        const uint64_t set_s = ballot(d2 < b.lo_in) | (b_lout & b_sin) | ballot(d2 > b.shell_out);
+        amb = keep & ~(set_c & set_s);
+    } else if (CORE) {
+        mc = keep & ballot(d2 < b.core_in);
+        ms = keep & ballot(d2 > b.core_out) & ballot(d2 < b.shell_in);
+        amb = keep & ~ballot(d2 > b.shell_out) & ~mc & ~ms;
+    } else {
+        mc = 0;
+        ms = keep & ballot(d2 < b.shell_in);
+        amb = keep & ~ballot(d2 > b.shell_out) & ~ms;
+    }
+}
+
+// One chunk per half-wave: this lane's candidate r (k_in: inside the half's
+// range) against the half's atom ap (packed x | y, packed z with extension
+// bits, exclusion id), atom index k_atom. The packed bounds settle most
+// candidates, the extended coordinates (mid bounds, e bits) nearly all of the
+// rest, and the exact test on positions read from memory the few left.
+// Members are appended to the half's rows (byte offsets hoff_s, hoff_c within
+// the descriptors) after cs and cc, which are advanced; a lane reads its own
+// bit of the member masks back for its store.
+template <int MODE, bool CORE>
+__device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x4& ap, int k_atom,
+                                           const PackedBounds& tb, const MidBounds& mb, int e, uint64_t t_core,
+                                           uint64_t t_lo, uint64_t t_shell, const uint4* __restrict__ spos, int lane,
+                                           int hsel, uint32_t lowm, int hoff_s, int hoff_c,
+                                           __amdgpu_buffer_rsrc_t rs_s, __amdgpu_buffer_rsrc_t rs_c, int& cs, int& cc)
+{
+    const uint64_t m_keep = ballot(k_in) & ballot(r.z != ap.z);
+    uint64_t m_core, m_shell, m_amb;
+    classify<MODE, CORE>(d2_packed(r.x, r.y, ap.x, ap.y), tb, m_keep, m_core, m_shell, m_amb);
+    if (__builtin_expect(m_amb != 0, 0)) {
+        // between the packed bounds (wave-uniform branch; the lanes of m_amb
+        // take its result)
+        // (the atom's operands pass through an empty asm statement, so that the
+        // compiler keeps their unpacking here instead of hoisting it to every
+        // pair's set-up)
+        uint32_t axy = ap.x, az = ap.y;
+        int ki = k_atom;
+        asm volatile("" : "+v"(axy), "+v"(az), "+v"(ki));
+        uint64_t c2, s2, a2;
+        classify<MODE, CORE>(d2_mid(r.x, r.y, axy, az, e), mb, m_amb, c2, s2, a2);
+        if (a2 != 0) {
+            const bool amb = (a2 >> lane) & 1u;
+            const uint64_t d2x = dist2_exact(spos[ki], spos[amb ? (int)r.w : ki]);
+            const bool xc = CORE && d2x <= t_core;
+            const bool xs = MODE != kListsCoreOnly &&
+                            (MODE == kListsSplitSkin ? d2x > t_lo : !xc) && d2x <= t_shell;
+            c2 = (c2 & ~a2) | (ballot(xc) & a2);
+            s2 = (s2 & ~a2) | (ballot(xs) & a2);
+        }
+        m_core = (m_core & ~m_amb) | c2;
+        m_shell = (m_shell & ~m_amb) | s2;
+    }
+    if (MODE != kListsCoreOnly) {
+        const uint32_t ms_lo = (uint32_t)m_shell, ms_hi = (uint32_t)(m_shell >> 32);
+        const int ps_lo = __popc(ms_lo);
+        // non-members store past the descriptor's range (dropped)
+        const int pos = member_pos(ms_lo, ms_hi, lowm, cs);
+        const int off = __builtin_amdgcn_inverse_ballot_w64(m_shell) ? hoff_s + (pos << 2) : kNoStore;
+        __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_s, off, 0, 0);
+        cs += ps_lo + (hsel & (__popc(ms_hi) - ps_lo));
+    }
+    if (CORE) {
+        const uint32_t mc_lo = (uint32_t)m_core, mc_hi = (uint32_t)(m_core >> 32);
+        const int pc_lo = __popc(mc_lo);
+        const int pos = member_pos(mc_lo, mc_hi, lowm, cc);
+        const int off = __builtin_amdgcn_inverse_ballot_w64(m_core) ? hoff_c + (pos << 2) : kNoStore;
+        __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_c, off, 0, 0);
+        cc += pc_lo + (hsel & (__popc(mc_hi) - pc_lo));
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
-    int n_c, int lo, int hi, int G, int prune, int trim, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb, uint64_t t_core,
-    uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const int32_t* __restrict__ smol,
+    int n_c, int lo, int hi, int G, int prune, int trim, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb,
+    MidBounds mb, int e, uint64_t t_core, uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos,
+    const int32_t* __restrict__ smol,
     const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g, int cap_core, int cap_shell,
     int32_t* __restrict__ core, int32_t* __restrict__ ncore, int32_t* __restrict__ shell,
     int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt, uint32_t* __restrict__ err)
@@ -170,7 +295,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
         const int cx = (int)(((uint64_t)si.x * (uint32_t)n_c) >> 32);
         const int ti = act ? wrap(cx - x0, n_c) : 0;  // lane's home cell in [0, gr)
         const uint32_t axy = pack_rel(si.x, orx, sh) | (pack_rel(si.y, ory, sh) << 16);
-        const uint32_t az = pack_rel(si.z, orz, sh);
+        const uint32_t az = pack_rel(si.z, orz, sh) | ext_rel(si, orx, ory, orz, sh, e);
         const uint32_t amol = (uint32_t)(mi >= 0 ? mi : -2 - k);
         const int axp = (int)(short)(axy & 0xffffu);  // packed x as a signed value
         // the rows of this chunk's atoms, one buffer descriptor per list: stores of an
@@ -242,7 +367,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         const uint4 sj = spos[j];
                         const int32_t mj = smol[j];
                         trec[t] = u32x4{pack_rel(sj.x, orx, sh) | (pack_rel(sj.y, ory, sh) << 16),
-                                        pack_rel(sj.z, orz, sh), (uint32_t)(mj >= 0 ? mj : -2 - j), (uint32_t)j};
+                                        pack_rel(sj.z, orz, sh) | ext_rel(sj, orx, ory, orz, sh, e),
+                                        (uint32_t)(mj >= 0 ? mj : -2 - j), (uint32_t)j};
                     }
                     __syncthreads();
                     if (trim && need && total <= kTileCap) {
@@ -302,79 +428,9 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                 const int hoff_c = __mul24(ka, cap_core * 4);
                                 for (int c0 = 0; c0 < chunks * 32; c0 += 32) {
                                     const u32x4 r = trec[qb + c0];
-                                    const uint32_t d2 = d2_packed(r.x, r.y, ap.x, ap.y);
-                                    // lane predicates and their wave masks, each mask the AND of
-                                    // ballots of single compares (scalar operations only)
-                                    const bool k_in = c0 < lenm, k_mol = r.z != ap.z;
-                                    const uint64_t m_keep = ballot(k_in) & ballot(k_mol);
-                                    bool in_core = false, in_shell;
-                                    uint64_t m_core = 0, m_shell, m_amb;
-                                    if (CORE && MODE == kListsCoreOnly) {
-                                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
-                                        in_core = k_in & k_mol & c_in;
-                                        in_shell = false;
-                                        m_core = m_keep & ballot(c_in);
-                                        m_shell = 0;
-                                        m_amb = m_keep & ~ballot(c_out) & ~m_core;
-                                    } else if (CORE && MODE == kListsSplitSkin) {
-                                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
-                                        const bool l_in = d2 < tb.lo_in, l_out = d2 > tb.lo_out;
-                                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
-                                        in_core = k_in & k_mol & c_in;
-                                        in_shell = k_in & k_mol & l_out & s_in;
-                                        const uint64_t b_cin = ballot(c_in), b_lout = ballot(l_out), b_sin = ballot(s_in);
-                                        m_core = m_keep & b_cin;
-                                        m_shell = m_keep & b_lout & b_sin;
-                                        // settled: C(i) either way, and S(i) below t_lo, inside, or beyond t_shell
-                                        const uint64_t set_c = b_cin | ballot(c_out);
-                                        const uint64_t set_s = ballot(l_in) | (b_lout & b_sin) | ballot(s_out);
-                                        m_amb = m_keep & ~(set_c & set_s);
-                                    } else if (CORE) {
-                                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
-                                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
-                                        in_core = k_in & k_mol & c_in;
-                                        in_shell = k_in & k_mol & c_out & s_in;
-                                        m_core = m_keep & ballot(c_in);
-                                        m_shell = m_keep & ballot(c_out) & ballot(s_in);
-                                        m_amb = m_keep & ~ballot(s_out) & ~m_core & ~m_shell;
-                                    } else {
-                                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
-                                        in_shell = k_in & k_mol & s_in;
-                                        m_shell = m_keep & ballot(s_in);
-                                        m_amb = m_keep & ~ballot(s_out) & ~m_shell;
-                                    }
-                                    if (m_amb != 0) {
-                                        // between the bounds: the exact test decides (wave-uniform
-                                        // branch; only the lanes of m_amb take its result)
-                                        const bool amb = (m_amb >> lane) & 1u;
-                                        const uint64_t d2x = dist2_exact(spos[chunk + ka], spos[amb ? (int)r.w : chunk + ka]);
-                                        const bool xc = CORE && d2x <= t_core;
-                                        const bool xs = MODE != kListsCoreOnly &&
-                                                        (MODE == kListsSplitSkin ? d2x > t_lo : !xc) && d2x <= t_shell;
-                                        in_core = amb ? xc : in_core;
-                                        in_shell = amb ? xs : in_shell;
-                                        m_core = (m_core & ~m_amb) | (ballot(xc) & m_amb);
-                                        m_shell = (m_shell & ~m_amb) | (ballot(xs) & m_amb);
-                                    }
-                                    if (MODE != kListsCoreOnly) {
-                                        const uint32_t ms_lo = (uint32_t)m_shell, ms_hi = (uint32_t)(m_shell >> 32);
-                                        const int ps_lo = __popc(ms_lo);
-                                        // non-members store past the descriptor's range (dropped)
-                                        const int pos = member_pos(ms_lo, ms_hi, lowm, cs);
-                                        const int off = in_shell ? hoff_s + (pos << 2) : kNoStore;
-                                        __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_s, off, 0, 0);
-                                        cs += ps_lo + (hsel & (__popc(ms_hi) - ps_lo));
-                                    }
-                                    if (CORE) {
-                                        const uint32_t mc_lo = (uint32_t)m_core, mc_hi = (uint32_t)(m_core >> 32);
-                                        const int pc_lo = __popc(mc_lo);
-                                        {
-                                            const int pos = member_pos(mc_lo, mc_hi, lowm, cc);
-                                            const int off = in_core ? hoff_c + (pos << 2) : kNoStore;
-                                            __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_c, off, 0, 0);
-                                        }
-                                        cc += pc_lo + (hsel & (__popc(mc_hi) - pc_lo));
-                                    }
+                                    const bool k_in = c0 < lenm;
+                                    scan_chunk<MODE, CORE>(r, k_in, ap, chunk + ka, tb, mb, e, t_core, t_lo, t_shell,
+                                                           spos, lane, hsel, lowm, hoff_s, hoff_c, rs_s, rs_c, cs, cc);
                                 }
                             };
                             if (core_row) scan(std::true_type{});
@@ -685,10 +741,16 @@ namespace {
 // With e = sum of component errors: D <= d2 + 2 delta sqrt(3 d2) + 3 delta^2
 // and D >= d2 - 2 delta sqrt(3 d2) for the exact squared separation D in the
 // same units; the bounds follow, with one unit of margin for rounding here.
+// The mid test extends each packed coordinate by the next e = min(s, 5) bits
+// (units of 2^(s - e) quanta, delta = 1, differences that no longer wrap);
+// without pruning it is switched off (every candidate stays open for the
+// exact test).
 struct PackedGeometry {
     int sh = 16;
     uint32_t ox = 0, oyz = 0;
     PackedBounds tb{};
+    MidBounds mb{};
+    int e = 0;
 };
 
 PackedGeometry packed_geometry(const Geometry& g, int G, bool prune)
@@ -708,25 +770,40 @@ PackedGeometry packed_geometry(const Geometry& g, int G, bool prune)
             }
         }
     }
-    const double unit2 = std::ldexp(1.0, 2 * p.sh);
-    auto inner = [&](uint64_t t) -> uint32_t {
-        const double T = (double)t / unit2;
+    // bounds in units of 2^s quanta (component errors below delta units), as doubles
+    auto inner = [](uint64_t t, int s, double delta) -> double {
+        const double T = (double)t / std::ldexp(1.0, 2 * s);
         const double v = std::floor(T - 2.0 * delta * std::sqrt(3.0 * T) - 3.0 * delta * delta - 1.0);
-        return v > 0.0 ? (uint32_t)v : 0u;
+        return v > 0.0 ? v : 0.0;
     };
-    auto outer = [&](uint64_t t) -> uint32_t {
-        const double T = (double)t / unit2;
+    auto outer = [](uint64_t t, int s, double delta) -> double {
+        const double T = (double)t / std::ldexp(1.0, 2 * s);
         const double r = delta * std::sqrt(3.0) + std::sqrt(3.0 * delta * delta + T);
         double o = std::ceil(r * r) + 2.0;
         while ((o + 1.0) - 2.0 * delta * std::sqrt(3.0 * (o + 1.0)) <= T + 1.0) o += 1.0;
-        return o < 4294967295.0 ? (uint32_t)o : 4294967295u;
+        return o;
     };
-    p.tb.core_in = inner(g.tl_core);
-    p.tb.core_out = outer(g.tl_core);
-    p.tb.shell_in = inner(g.tl_shell);
-    p.tb.shell_out = outer(g.tl_shell);
-    p.tb.lo_in = inner(g.tl_lo);
-    p.tb.lo_out = outer(g.tl_lo);
+    auto u32 = [](double v) { return v < 4294967295.0 ? (uint32_t)v : 4294967295u; };
+    p.tb.core_in = u32(inner(g.tl_core, p.sh, delta));
+    p.tb.core_out = u32(outer(g.tl_core, p.sh, delta));
+    p.tb.shell_in = u32(inner(g.tl_shell, p.sh, delta));
+    p.tb.shell_out = u32(outer(g.tl_shell, p.sh, delta));
+    p.tb.lo_in = u32(inner(g.tl_lo, p.sh, delta));
+    p.tb.lo_out = u32(outer(g.tl_lo, p.sh, delta));
+    if (prune && p.sh < 16) {
+        p.e = std::min(p.sh, 5);
+        const int s = p.sh - p.e;
+        auto u64 = [](double v) { return v < 1.8e19 ? (uint64_t)v : ~0ull; };
+        p.mb.core_in = u64(inner(g.tl_core, s, 1.0));
+        p.mb.core_out = u64(outer(g.tl_core, s, 1.0));
+        p.mb.shell_in = u64(inner(g.tl_shell, s, 1.0));
+        p.mb.shell_out = u64(outer(g.tl_shell, s, 1.0));
+        p.mb.lo_in = u64(inner(g.tl_lo, s, 1.0));
+        p.mb.lo_out = u64(outer(g.tl_lo, s, 1.0));
+    } else {
+        p.e = 0;
+        p.mb = MidBounds{0, ~0ull, 0, ~0ull, 0, ~0ull};
+    }
     return p;
 }
 
@@ -771,10 +848,9 @@ hipError_t launch_build_lists(irbe_ctx* h)
     // above the FP32 rounding of the row gaps: the row pruning never drops a member.
     const float tf_hi = (float)(h->stencil ? g.tl_core : g.tl_shell) * 1.000002f;
 #define IRBE_LISTS_ARGS                                                                                           \
-    n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos, \
-        h->smol,                                                                                                  \
-        h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt,   \
-        h->err
+    n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, pg.mb, pg.e, g.tl_core, g.tl_lo, g.tl_shell, tf_hi,  \
+        h->spos, h->smol, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,       \
+        h->nshell, h->maxcnt, h->err
 #define IRBE_LANES_ARGS                                                                                            \
     n_c, g.lo, g.hi, G, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi,                       \
         h->spos, h->smol, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,     \
