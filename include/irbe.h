@@ -141,8 +141,10 @@ typedef struct {
 
 /* Create a handle for one system size and parameter set; work is queued on
  * hip_stream (a hipStream_t; NULL = the default stream). On success *out is a
- * new handle. Returns IRBE_EINVAL for a bad configuration (message in
- * irbe_last_error(NULL)). */
+ * new handle. Returns IRBE_EINVAL for a bad configuration, IRBE_EUNSUPPORTED for
+ * one beyond this build's limits (more than 1000 cells per axis, shell stencils
+ * wider than 191 cells per axis, stencil sampling over more than 128 stencil
+ * rows, k tables too large); the message is in irbe_last_error(NULL). */
 irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* out);
 
 /* Set the topology and parameters (Sec. 2.1: charges q_i, LJ sigma_ij and

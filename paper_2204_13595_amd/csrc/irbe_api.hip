@@ -446,6 +446,10 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
         delete h;
         return fail(nullptr, IRBE_EUNSUPPORTED, "stencil sampling supports at most 128 stencil rows");
     }
+    if (h->geo.hi - h->geo.lo + 1 > 191) {
+        delete h;
+        return fail(nullptr, IRBE_EUNSUPPORTED, "shell stencils wider than 191 cells per axis");
+    }
     if (h->geo.n_cells > kMaxCells || h->geo.n_c > 1000) {
         delete h;
         return fail(nullptr, IRBE_EUNSUPPORTED, "too many cells");
@@ -501,6 +505,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc(h, &h->perm, n));
     ALLOC(dalloc(h, &h->rank, n));
     ALLOC(dalloc(h, &h->spos, n));
+    ALLOC(dalloc(h, &h->spk, n));
     ALLOC(dalloc_bytes(h, &h->sq_r, n * rs));
     ALLOC(dalloc(h, &h->smol, n));
     ALLOC(dalloc(h, &h->sxr, n));

@@ -137,6 +137,7 @@ struct irbe_ctx {
     int32_t* perm = nullptr;          // [N] sorted -> caller id
     int32_t* rank = nullptr;          // [N] caller id -> sorted
     uint4* spos = nullptr;            // [N] sorted {sx, sy, sz, type}
+    uint4* spk = nullptr;             // [N] sorted packed records of the list build
     void* sq_r = nullptr;             // real[N] sorted charges
     int32_t* smol = nullptr;          // [N] sorted molecule ids
 

@@ -93,28 +93,18 @@ __device__ __forceinline__ uint32_t d2_packed(uint32_t cxy, uint32_t cz, uint32_
     return (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, dz * dz, false);
 }
 
-// The next e bits below the packed ones (e = min(s, 5)) of the three
-// coordinates relative to the origin, x | y << 5 | z << 10, kept in the upper
-// half of the packed z word.
-__device__ __forceinline__ uint32_t ext_rel(uint4 p, uint32_t ox, uint32_t oy, uint32_t oz, int sh, int e)
-{
-    const uint32_t m = (1u << e) - 1u;
-    const int se = sh - e;
-    const uint32_t x = (uint32_t)((int32_t)(p.x - ox) >> se) & m;
-    const uint32_t y = (uint32_t)((int32_t)(p.y - oy) >> se) & m;
-    const uint32_t z = (uint32_t)((int32_t)(p.z - oz) >> se) & m;
-    return (x | (y << 5) | (z << 10)) << 16;
-}
-
 // Squared separation of two packed positions in units of 2^(s - e) quanta
-// from the packed coordinates and their extension bits (each component off by
-// less than one unit, as the packed test in its own units).
+// from the packed coordinates and their extension bits (x | y << 5 | z << 10
+// in the upper half of the z word); each coordinate is then known modulo
+// 2^(16 + e) units, its difference is taken in that modulus and is off by less
+// than one unit, as the packed test in its own units.
 __device__ __forceinline__ uint64_t d2_mid(uint32_t cxy, uint32_t cz, uint32_t axy, uint32_t az, int e)
 {
-    auto m = [e](uint32_t p, uint32_t x) { return (int32_t)(((uint32_t)(int32_t)(int16_t)(p & 0xffffu) << e) | (x & 31u)); };
-    const int32_t dx = m(cxy, cz >> 16) - m(axy, az >> 16);
-    const int32_t dy = m(cxy >> 16, cz >> 21) - m(axy >> 16, az >> 21);
-    const int32_t dz = m(cz, cz >> 26) - m(az, az >> 26);
+    auto m = [e](uint32_t p, uint32_t x) { return ((p & 0xffffu) << e) | (x & 31u); };
+    const int w = 16 - e;
+    const int32_t dx = (int32_t)((m(cxy, cz >> 16) - m(axy, az >> 16)) << w) >> w;
+    const int32_t dy = (int32_t)((m(cxy >> 16, cz >> 21) - m(axy >> 16, az >> 21)) << w) >> w;
+    const int32_t dz = (int32_t)((m(cz, cz >> 26) - m(az, az >> 26)) << w) >> w;
     return (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
 }
 
@@ -257,9 +247,8 @@ __device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x
 
 template <int MODE>
 __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
-    int n_c, int lo, int hi, int G, int prune, int trim, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb,
-    MidBounds mb, int e, uint64_t t_core, uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos,
-    const int32_t* __restrict__ smol,
+    int n_c, int lo, int hi, int G, int prune, int trim, int sh, PackedBounds tb, MidBounds mb, int e, uint64_t t_core,
+    uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const u32x4* __restrict__ spk,
     const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g, int cap_core, int cap_shell,
     int32_t* __restrict__ core, int32_t* __restrict__ ncore, int32_t* __restrict__ shell,
     int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt, uint32_t* __restrict__ err)
@@ -267,6 +256,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     __shared__ u32x4 trec[kTileCap + kTilePad];  // candidate: packed x | y, packed z, exclusion id, sorted index
     __shared__ u32x4 apk[kListWave];             // atom: packed x | y, packed z, exclusion id, range start | length << 16
     __shared__ int2 acnt[kListWave];             // atom: core / shell list lengths so far
+    int* const cst = reinterpret_cast<int*>(apk);  // a row's cell starts (span_u + 1 <= 4 * kListWave)
     const uint32_t* bound = bound_g;  // indexed by wave-uniform cell coordinates
     const int lane = threadIdx.x;
     const int hl = lane & 31;
@@ -284,20 +274,15 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     const int span_u = gr - 1 + span_c;       // cells of the union x range
     const int xu0 = wrap(x0 + lo, n_c);       // first cell of the union
     const int lenA = min(span_u, n_c - xu0);  // cells before the wrap
-    const uint32_t orx = bound[x0] + ox, ory = bound[cy] + oyz, orz = bound[cz] + oyz;
     int maxc = 0, maxs = 0;
     for (int chunk = a0; chunk < a1; chunk += kListWave) {
         const int k = chunk + lane;
         const bool act = k < a1;
         const int na = min(kListWave, a1 - chunk);  // atoms of this chunk
         const uint4 si = act ? spos[k] : make_uint4(0, 0, 0, 0);
-        const int32_t mi = act ? smol[k] : -1;
+        const u32x4 pk = act ? spk[k] : u32x4{0, 0, 0, 0};  // packed x | y, z with extension bits, exclusion id
         const int cx = (int)(((uint64_t)si.x * (uint32_t)n_c) >> 32);
         const int ti = act ? wrap(cx - x0, n_c) : 0;  // lane's home cell in [0, gr)
-        const uint32_t axy = pack_rel(si.x, orx, sh) | (pack_rel(si.y, ory, sh) << 16);
-        const uint32_t az = pack_rel(si.z, orz, sh) | ext_rel(si, orx, ory, orz, sh, e);
-        const uint32_t amol = (uint32_t)(mi >= 0 ? mi : -2 - k);
-        const int axp = (int)(short)(axy & 0xffffu);  // packed x as a signed value
         // the rows of this chunk's atoms, one buffer descriptor per list: stores of an
         // overflowing row stay within them (and the rebuild that follows rewrites them)
         const __amdgpu_buffer_rsrc_t rs_s = __builtin_amdgcn_make_buffer_rsrc(
@@ -347,16 +332,18 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                 const int eB = lenB > 0 ? cell_start[row + lenB] : jB;
                 const int nA = eA - jA;
                 const int total = nA + (eB - jB);
-                // lane's range in tile positions; tpos(u) = position of the first atom of tile cell u
-                auto tpos = [&](int u) {
-                    return u < lenA ? cell_start[row + xu0 + u] - jA : nA + cell_start[row + u - lenA] - jB;
-                };
+                // lane's range in tile positions: cst[u] = position of the first atom of
+                // tile cell u, one lane per cell (cst borrows the atom records' LDS,
+                // which the first tile rewrites only after every lane has read it)
+                for (int u = lane; u <= span_u; u += kListWave)
+                    cst[u] = u < lenA ? cell_start[row + xu0 + u] - jA : nA + cell_start[row + u - lenA] - jB;
+                __syncthreads();
                 int p_lo = 0, p_hi = 0, pc1 = 0, pc2 = 0;
                 if (need) {
-                    p_lo = tpos(u_lo);
-                    p_hi = tpos(u_hi + 1);
-                    pc1 = u_lo < u_hi ? tpos(u_lo + 1) : p_hi;  // end of the first cell
-                    pc2 = u_lo < u_hi ? tpos(u_hi) : p_lo;      // start of the last cell
+                    p_lo = cst[u_lo];
+                    p_hi = cst[u_hi + 1];
+                    pc1 = u_lo < u_hi ? cst[u_lo + 1] : p_hi;  // end of the first cell
+                    pc2 = u_lo < u_hi ? cst[u_hi] : p_lo;      // start of the last cell
                 }
                 for (int base = 0; base < total; base += kTileCap) {
                     const int cnt = min(kTileCap, total - base);
@@ -364,11 +351,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                     for (int t = lane; t < cnt; t += kListWave) {
                         const int p = base + t;
                         const int j = p < nA ? jA + p : jB + (p - nA);
-                        const uint4 sj = spos[j];
-                        const int32_t mj = smol[j];
-                        trec[t] = u32x4{pack_rel(sj.x, orx, sh) | (pack_rel(sj.y, ory, sh) << 16),
-                                        pack_rel(sj.z, orz, sh) | ext_rel(sj, orx, ory, orz, sh, e),
-                                        (uint32_t)(mj >= 0 ? mj : -2 - j), (uint32_t)j};
+                        trec[t] = spk[j];
                     }
                     __syncthreads();
                     if (trim && need && total <= kTileCap) {
@@ -379,7 +362,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         int a = p_lo, b = pc1;
                         while (a < b) {
                             const int m = (a + b) >> 1;
-                            if ((int)(short)(trec[m].x & 0xffffu) - axp < -ext_u) a = m + 1;
+                            if ((int)(short)((trec[m].x - pk.x) & 0xffffu) < -ext_u) a = m + 1;
                             else b = m;
                         }
                         p_lo = a;
@@ -387,7 +370,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         b = p_hi;
                         while (a < b) {
                             const int m = (a + b) >> 1;
-                            if ((int)(short)(trec[m].x & 0xffffu) - axp <= ext_u) a = m + 1;
+                            if ((int)(short)((trec[m].x - pk.x) & 0xffffu) <= ext_u) a = m + 1;
                             else b = m;
                         }
                         p_hi = a;
@@ -395,7 +378,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                     // this tile's part of the lane's range, in tile coordinates
                     const int s0 = need ? max(p_lo, base) - base : 0;
                     const int len_l = need ? max(min(p_hi, base + cnt) - base - s0, 0) : 0;
-                    apk[lane] = u32x4{axy, az, amol, (uint32_t)s0 | ((uint32_t)len_l << 16)};
+                    apk[lane] = u32x4{pk.x, pk.y, pk.z, (uint32_t)s0 | ((uint32_t)len_l << 16)};
                     __syncthreads();
                     // atoms are paired with atoms of the same number of 32-candidate
                     // chunks, so no half-wave reads past its own range (+ 31); a lone
@@ -729,6 +712,26 @@ __global__ __launch_bounds__(kBlock) void k_stencil_counts(int n_c, int lo, int 
     if ((threadIdx.x & 63) == 0) atomicMax(&maxcnt[1], m);
 }
 
+// Packed records of the sorted atoms for k_build_lists_tiled: x | y << 16 and
+// z, each fixed-point coordinate in units of 2^sh quanta taken modulo 2^16
+// (the separations within a stencil stay below 2^15 units, so their 16-bit
+// differences are exact), the next e bits of the three coordinates
+// (x | y << 5 | z << 10) in the upper half of the z word, the exclusion id
+// (molecule, or -2 - k for an atom without one) and the sorted index k.
+__global__ __launch_bounds__(kBlock) void k_pack_sorted(int64_t n, int sh, int e, const uint4* __restrict__ spos,
+                                                       const int32_t* __restrict__ smol, u32x4* __restrict__ spk)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint4 s = spos[k];
+    const int32_t m = smol[k];
+    const uint32_t mk = (1u << e) - 1u;
+    const int se = sh - e;
+    const uint32_t ext = ((s.x >> se) & mk) | (((s.y >> se) & mk) << 5) | (((s.z >> se) & mk) << 10);
+    spk[k] = u32x4{((s.x >> sh) & 0xffffu) | ((s.y >> sh) << 16), ((s.z >> sh) & 0xffffu) | (ext << 16),
+                   (uint32_t)(m >= 0 ? m : -2 - (int32_t)k), (uint32_t)k};
+}
+
 namespace {
 
 // Shift s and bounds of the packed candidate test. With a pruned stencil
@@ -837,6 +840,8 @@ hipError_t launch_build_lists(irbe_ctx* h)
     int g_cap = narrow ? std::max(1, std::min(g_want, n_c - 2 * g.reach)) : 1;
     // the lane-per-atom kernel keeps the union's cell starts in 64 LDS words
     if (lanes) g_cap = std::min(g_cap, 64 - (g.hi - g.lo + 1));
+    // the tiled kernel keeps a row's G - 1 + (2R + 1) + 1 cell starts in 4 * 64 LDS words
+    else g_cap = std::min(g_cap, 4 * kListWave - (g.hi - g.lo + 1));
     const int groups_per_row = (n_c + g_cap - 1) / g_cap;
     const int G = (n_c + groups_per_row - 1) / groups_per_row;
     const int prune = narrow ? 1 : 0;
@@ -848,8 +853,8 @@ hipError_t launch_build_lists(irbe_ctx* h)
     // above the FP32 rounding of the row gaps: the row pruning never drops a member.
     const float tf_hi = (float)(h->stencil ? g.tl_core : g.tl_shell) * 1.000002f;
 #define IRBE_LISTS_ARGS                                                                                           \
-    n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.ox, pg.oyz, pg.tb, pg.mb, pg.e, g.tl_core, g.tl_lo, g.tl_shell, tf_hi,  \
-        h->spos, h->smol, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,       \
+    n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.tb, pg.mb, pg.e, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos,      \
+        (const u32x4*)h->spk, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,  \
         h->nshell, h->maxcnt, h->err
 #define IRBE_LANES_ARGS                                                                                            \
     n_c, g.lo, g.hi, G, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi,                       \
@@ -864,14 +869,18 @@ hipError_t launch_build_lists(irbe_ctx* h)
             k_build_lists_lanes<kListsSplitSkin><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
         else
             k_build_lists_lanes<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
-    } else if (h->full_list)
-        k_build_lists_tiled<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
-    else if (h->stencil)
-        k_build_lists_tiled<kListsCoreOnly><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
-    else if (g.skin)
-        k_build_lists_tiled<kListsSplitSkin><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
-    else
-        k_build_lists_tiled<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+    } else {
+        k_pack_sorted<<<(unsigned)blocks_for(h->cfg.n_atoms, kBlock), kBlock, 0, h->stream>>>(
+            h->cfg.n_atoms, pg.sh, pg.e, h->spos, h->smol, (u32x4*)h->spk);
+        if (h->full_list)
+            k_build_lists_tiled<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+        else if (h->stencil)
+            k_build_lists_tiled<kListsCoreOnly><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+        else if (g.skin)
+            k_build_lists_tiled<kListsSplitSkin><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+        else
+            k_build_lists_tiled<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+    }
 #undef IRBE_LANES_ARGS
 #undef IRBE_LISTS_ARGS
     hipError_t e = hipGetLastError();
