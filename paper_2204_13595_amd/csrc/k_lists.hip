@@ -18,19 +18,21 @@
 // a half run over the atom's candidates and its members are compacted in
 // candidate order.
 //
-// Candidate test. Atoms and staged candidates also carry their position
-// relative to an origin at the wavefront's cells, in units of 2^s quanta and
-// truncated to 16 bits per axis (s is the smallest shift at which every such
-// coordinate of the stencil fits). A packed 16-bit subtraction, a two-term
+// Candidate test. Every sorted atom has a 16-byte packed record, written once
+// per build (k_pack_sorted) and copied into the tile: its fixed-point
+// coordinates in units of 2^s quanta taken modulo 2^16 per axis (s is the
+// smallest shift at which every separation within a stencil stays below 2^15
+// units, so 16-bit differences are exact), the next 5 bits of each coordinate,
+// its exclusion id and its index. A packed 16-bit subtraction, a two-term
 // integer dot product and a 24-bit multiply give a squared separation d2
 // whose components are off by less than delta units each, so d2 below an
 // inner bound proves membership and d2 above an outer bound proves
 // non-membership. The candidates in between (about one per atom) take a
-// second test on the same coordinates extended by the next 5 bits per axis
-// (kept in the unused half of the packed z word), whose band is 32 times
-// narrower; the few left after it take the exact 64-bit test on positions
-// read from memory. The LDS footprint (about 6 KB per wavefront) leaves room
-// for six or more wavefronts per SIMD.
+// second test on the coordinates extended by the 5 extra bits, whose band is
+// 32 times narrower; the few left after it take the exact 64-bit test on
+// positions read from memory. The LDS footprint (about 6 KB per wavefront)
+// leaves room for six or more wavefronts per SIMD. (The lane-per-atom kernel
+// for dilute cells below packs positions relative to an origin at its cells.)
 //
 // Layout: fixed-capacity rows (row k of atom k in cell order), entries are
 // cell-sorted atom indices. Counts beyond the capacity are still counted, so
