@@ -175,7 +175,9 @@ struct Math<float> {
     }
     static __device__ __forceinline__ float erf_(float x) { return erff(x); }
     static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
-    static __device__ __forceinline__ float rsqrt_(float x) { return rsqrtf(x); }
+    // the hardware reciprocal square root: the arguments are squared pair
+    // separations, far from the denormal range that rsqrtf rescales for
+    static __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
     // sin and cos of 2 pi x for a phase x in revolutions, |x| <= 1/2.
     static __device__ __forceinline__ void sincos_rev(float x, float* s, float* c)

@@ -102,14 +102,14 @@ struct PairSum {
 };
 
 template <typename real, bool EV>
-__device__ __forceinline__ void add_pair(PairSum<real>& a, uint4 si, real qi, uint4 sj, real qj, const LJ<real>* lrow,
+__device__ __forceinline__ void add_pair(PairSum<real>& a, uint4 si, real qi, uint4 sj, real qj, const LJ<real>& lje,
                                          const PairParams<real>& pp)
 {
     real dx, dy, dz;
     separation(si, sj, pp.quantum, dx, dy, dz);
     const real r2 = dx * dx + dy * dy + dz * dz;
     real uc, ul;
-    const real phi = pair_phi<real, EV>(r2, qi * qj, lrow[sj.w], pp, uc, ul);
+    const real phi = pair_phi<real, EV>(r2, qi * qj, lje, pp, uc, ul);
     a.fx += phi * dx;
     a.fy += phi * dy;
     a.fz += phi * dz;
@@ -340,14 +340,13 @@ constexpr int kCoopBlock = 256;
 // Coulomb part of phi plus qq / r^3, without LJ. Forces only.
 template <typename real>
 __device__ __forceinline__ void add_pair_or_excl(PairSum<real>& pc, PairSum<real>& px, uint4 si, real qi, uint4 sj,
-                                                 real qj, const LJ<real>* lrow, const PairParams<real>& pp, bool ex)
+                                                 real qj, const LJ<real>& lj, const PairParams<real>& pp, bool ex)
 {
     using M = Math<real>;
     real dx, dy, dz;
     separation(si, sj, pp.quantum, dx, dy, dz);
     const real r2 = dx * dx + dy * dy + dz * dz;
     const real qq = qi * qj;
-    const LJ<real> lj = lrow[sj.w];
     const real rinv = M::rsqrt_(r2);
     const real r = r2 * rinv;
     const real br = pp.beta * r;
@@ -387,14 +386,14 @@ __device__ __forceinline__ void add_excl(PairSum<real>& px, uint4 si, real qi, u
     }
 }
 
-template <typename real, bool FULL, bool EV, bool STENCIL>
+template <typename real, bool FULL, bool EV, bool STENCIL, bool SKIN>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
     int p_stride, const uint16_t* __restrict__ ranks, StencilArgs sa, uint64_t t_core, uint64_t t_shell,
-    bool skin, real* __restrict__ fsr, double* __restrict__ part)
+    real* __restrict__ fsr, double* __restrict__ part)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -404,7 +403,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t gw = blk * (kCoopBlock / 64) + (threadIdx.x >> 6);
+    // the wavefront's index as a wave-uniform value, so that its atoms' indices and
+    // row addresses are scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t gw = blk * (kCoopBlock / 64) + wave;
     const int64_t a0 = gw * apw;
     const int64_t a1 = min(n, a0 + apw);
     double fc_sum[3] = {0.0, 0.0, 0.0};
@@ -417,7 +419,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int h_ns = nshell[ah];
     const int2 h_x = sxr[ah];
     const int h_mol = STENCIL ? sa.smol[ah] : 0;
-    const int wave = threadIdx.x >> 6;
+    // shell weight N_S / p~ (1 when every member is taken), one division per lane
+    const real h_w = (!FULL && h_ns > p_shell) ? (real)((double)h_ns / (double)p_shell) : (real)1;
     const int nrows = sa.span * sa.span;
     int tcell = -1;  // the cell whose stencil rows sit in srows[wave]
     // first-level indices of one atom's first pass: the lane's first core entry,
@@ -462,7 +465,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const uint4 si = make_uint4(bcast(h_s.x, t), bcast(h_s.y, t), bcast(h_s.z, t),
                                     bcast(h_s.w, t));
         const real qi = bcast(h_q, t) * pp.ke;
-        const LJ<real>* lrow = lj + (int)si.w * n_types;
+        // LJ coefficients of the pair types (32-bit LDS indexing; n_types^2 <= 256)
+        const int li = (int)si.w * n_types;
+        auto ljof = [&](uint4 sj) -> const LJ<real>& { return lj[(li + (int)sj.w) & 255]; };
         const int nc = bcast(h_nc, t);
         const int ns = bcast(h_ns, t);
         const int2 xr = make_int2(bcast(h_x.x, t), bcast(h_x.y, t));
@@ -471,7 +476,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
         const bool sample = !FULL && ns > p_shell;
         const int cnt = sample ? p_shell : ns;
-        const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
+        const real w = bcast(h_w, t);
         PairSum<real> pc, ps, px;
         const int js0 = STENCIL ? r0 : (r0 >= 0 ? srow[r0] : -1);
         const int js1 = STENCIL ? r1 : (r1 >= 0 ? srow[r1] : -1);
@@ -489,34 +494,34 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const real qjx = kFold ? qjc : sqr[max(jx, 0)];
         // skin: a core entry counts inside r_core, a list shell entry inside the annulus
         // (the whole ball in full-list mode), at these positions
-        auto core_ok = [&](uint4 sj) { return !skin || dist2_q(si, sj) <= t_core; };
+        auto core_ok = [&](uint4 sj) { return !SKIN || dist2_q(si, sj) <= t_core; };
         auto shell_ok = [&](uint4 sj) {
-            if (!skin) return true;
+            if (!SKIN) return true;
             const uint64_t d2 = dist2_q(si, sj);
             return d2 <= t_shell && (FULL || d2 > t_core);
         };
         if (kFold) {
-            if (jc >= 0 && (lane >= nc || core_ok(pjc))) add_pair_or_excl(pc, px, si, qi, pjc, qjc, lrow, pp, lane >= nc);
+            if (jc >= 0 && (lane >= nc || core_ok(pjc))) add_pair_or_excl(pc, px, si, qi, pjc, qjc, ljof(pjc), pp, lane >= nc);
         } else {
-            if (jc >= 0 && core_ok(pjc)) add_pair<real, EV>(pc, si, qi, pjc, qjc, lrow, pp);
+            if (jc >= 0 && core_ok(pjc)) add_pair<real, EV>(pc, si, qi, pjc, qjc, ljof(pjc), pp);
             if (jx >= 0) add_excl<real, EV>(px, si, qi, pjx, qjx, pp);
         }
         if (STENCIL ? stencil_member(a, js0, mi, mj0, si, pj0, t_core, t_shell) : (js0 >= 0 && shell_ok(pj0)))
-            add_pair<real, EV>(ps, si, qi, pj0, qj0, lrow, pp);
+            add_pair<real, EV>(ps, si, qi, pj0, qj0, ljof(pj0), pp);
         if (STENCIL ? stencil_member(a, js1, mi, mj1, si, pj1, t_core, t_shell) : (js1 >= 0 && shell_ok(pj1)))
-            add_pair<real, EV>(ps, si, qi, pj1, qj1, lrow, pp);
+            add_pair<real, EV>(ps, si, qi, pj1, qj1, ljof(pj1), pp);
         // the rest (long lists and large batches)
         if (kFold) {
             for (int c = lane + 64; c < nc + xr.y; c += 64) {
                 const int j = c < nc ? crow[c] : sxidx[xr.x + c - nc];
                 const uint4 sj = spos[j];
-                if (c >= nc || core_ok(sj)) add_pair_or_excl(pc, px, si, qi, sj, sqr[j], lrow, pp, c >= nc);
+                if (c >= nc || core_ok(sj)) add_pair_or_excl(pc, px, si, qi, sj, sqr[j], ljof(sj), pp, c >= nc);
             }
         } else {
             for (int c = lane + 64; c < nc; c += 64) {
                 const int j = crow[c];
                 const uint4 sj = spos[j];
-                if (core_ok(sj)) add_pair<real, EV>(pc, si, qi, sj, sqr[j], lrow, pp);
+                if (core_ok(sj)) add_pair<real, EV>(pc, si, qi, sj, sqr[j], ljof(sj), pp);
             }
             for (int c = lane + 64; c < xr.y; c += 64) {
                 const int j = sxidx[xr.x + c];
@@ -536,11 +541,11 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
                 const int j = stencil_rows_atom(srows[wave], nrows, sample ? (int)rrow[c] : c);
                 const uint4 sj = spos[j];
                 if (stencil_member(a, j, mi, sa.smol[j], si, sj, t_core, t_shell))
-                    add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
+                    add_pair<real, EV>(ps, si, qi, sj, sqr[j], ljof(sj), pp);
             } else {
                 const int j = srow[sample ? (int)rrow[c] : c];
                 const uint4 sj = spos[j];
-                if (shell_ok(sj)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], lrow, pp);
+                if (shell_ok(sj)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], ljof(sj), pp);
             }
         }
         // one set of sums: the excluded-pair forces cancel pairwise, so the momentum
@@ -607,7 +612,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
     if (a < n) {
         const uint4 si = spos[a];
         const real qi = sqr[a] * pp.ke;
-        const LJ<real>* lrow = lj + (int)si.w * n_types;
+        // LJ coefficients of the pair types (32-bit LDS indexing; n_types^2 <= 256)
+        const int li = (int)si.w * n_types;
+        auto ljof = [&](uint4 sj) -> const LJ<real>& { return lj[(li + (int)sj.w) & 255]; };
         PairSum<real> pc, ps, px;
         const int nc = ncore[a];
         const int32_t* crow = core + a * (int64_t)cap_core;
@@ -626,7 +633,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (j[u] >= 0 && (!skin || dist2_q(si, sj[u]) <= t_core))
-                    add_pair<real, EV>(pc, si, qi, sj[u], qj[u], lrow, pp);
+                    add_pair<real, EV>(pc, si, qi, sj[u], qj[u], ljof(sj[u]), pp);
         }
         const int2 xr = sxr[a];
         for (int c = 0; c < xr.y; ++c) {
@@ -654,7 +661,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (j[u] >= 0 && (!skin || in_annulus(si, sj[u], t_core, t_shell)))
-                    add_pair<real, EV>(ps, si, qi, sj[u], qj[u], lrow, pp);
+                    add_pair<real, EV>(ps, si, qi, sj[u], qj[u], ljof(sj[u]), pp);
         }
         const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
         const real fx = pc.fx + w * ps.fx + px.fx;
@@ -764,7 +771,7 @@ static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
     return e;
 }
 
-template <typename real, bool FULL, bool EV, bool STENCIL>
+template <typename real, bool FULL, bool EV, bool STENCIL, bool SKIN>
 static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
 {
     const int64_t n = h->cfg.n_atoms;
@@ -781,10 +788,10 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     const int64_t waves = blocks_for(n, apw);
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
-    k_pair_coop<real, FULL, EV, STENCIL><<<nb, kCoopBlock, 0, h->stream>>>(
+    k_pair_coop<real, FULL, EV, STENCIL, SKIN><<<nb, kCoopBlock, 0, h->stream>>>(
         n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
-        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part);
+        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
     return hipGetLastError();
 }
@@ -810,6 +817,20 @@ static hipError_t launch_thread_t(irbe_ctx* h, uint64_t step)
     return hipGetLastError();
 }
 
+// The cooperative kernel for the list mode, energies and skin.
+template <typename real, bool SKIN>
+static hipError_t launch_coop_s(irbe_ctx* h, uint64_t step, bool ev)
+{
+    if (h->full_list)
+        return ev ? launch_coop_t<real, true, true, false, SKIN>(h, step)
+                  : launch_coop_t<real, true, false, false, SKIN>(h, step);
+    if (h->stencil)
+        return ev ? launch_coop_t<real, false, true, true, SKIN>(h, step)
+                  : launch_coop_t<real, false, false, true, SKIN>(h, step);
+    return ev ? launch_coop_t<real, false, true, false, SKIN>(h, step)
+              : launch_coop_t<real, false, false, false, SKIN>(h, step);
+}
+
 // Split lists whose longest core list plus batch stays within this many entries
 // take the thread-per-atom kernel.
 constexpr int kSparsePairs = 32;
@@ -819,11 +840,7 @@ static hipError_t launch_coop_r(irbe_ctx* h, uint64_t step, bool ev)
 {
     if (!h->full_list && !h->stencil && h->max_core + std::min(h->max_shell, h->cfg.p_shell) <= kSparsePairs)
         return ev ? launch_thread_t<real, true>(h, step) : launch_thread_t<real, false>(h, step);
-    if (h->full_list)
-        return ev ? launch_coop_t<real, true, true, false>(h, step) : launch_coop_t<real, true, false, false>(h, step);
-    if (h->stencil)
-        return ev ? launch_coop_t<real, false, true, true>(h, step) : launch_coop_t<real, false, false, true>(h, step);
-    return ev ? launch_coop_t<real, false, true, false>(h, step) : launch_coop_t<real, false, false, false>(h, step);
+    return h->geo.skin ? launch_coop_s<real, true>(h, step, ev) : launch_coop_s<real, false>(h, step, ev);
 }
 
 // Reduce the per-block partials in a fixed order, in two stages: stage 1 sums
@@ -1067,7 +1084,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         for (int u = 0; u < n_types; ++u) any |= ljraw_g[threadIdx.x * n_types + u] != (real)0;
         lj_row[threadIdx.x] = any;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wavefront's index as a wave-uniform value (scalar atom indices and row addresses)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (WANT_LJ)
         for (int t = lane; t < NLJ; t += 64) ljacc[wave][t] = 0.0;
     if (BK) {
@@ -1094,6 +1112,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const int h_nsym = FULL ? nshell[ah] : ncore[ah];
     const int h_ns = FULL ? 0 : nshell[ah];
     const int2 h_x = sxr[ah];
+    // shell weight N_S / p~ (1 when every member is taken), one division per lane
+    const real h_w = h_ns > p_shell ? (real)((double)h_ns / (double)p_shell) : (real)1;
     // first-level indices of one atom's first pass: the lane's first symmetric-list
     // entry, its two batch ranks (or shell positions) and its first excluded partner
     auto first_level = [&](int64_t a, int t, int& jc, int& r0, int& r1, int& jx) {
@@ -1143,7 +1163,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const int32_t* srow = shell + a * (int64_t)cap_shell;
         const bool sample = ns > p_shell;
         const int cnt = sample ? p_shell : ns;
-        const real w = sample ? (real)((double)ns / (double)p_shell) : (real)1;
+        const real w = bcast(h_w, t_a);
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
 
         // symmetric sets (core pairs, or the whole list in full-list mode, and the
