@@ -122,13 +122,18 @@ __device__ __forceinline__ void add_pair(PairSum<real>& a, uint4 si, real qi, ui
 }
 
 // One Floyd step: draw r in [0, t], insert r or (if taken) t into the bitmap
-// (word w of this thread's bitmap at bits[w * stride]).
+// (word w of this thread's bitmap at bits[w * stride]). The words of r and of
+// t are read together (one memory round trip per step); either one is then
+// updated. Every element inserted before this step is below t, so t's own bit
+// is clear.
 __device__ __forceinline__ int floyd_step(WordStream& st, uint32_t* bits, int stride, int t)
 {
     const int r = (int)st.below((uint32_t)t + 1u);
-    const bool taken = (bits[(r >> 5) * stride] >> (r & 31)) & 1u;
+    const uint32_t wr = bits[(r >> 5) * stride];
+    const uint32_t wt = bits[(t >> 5) * stride];
+    const bool taken = (wr >> (r & 31)) & 1u;
     const int v = taken ? t : r;
-    bits[(v >> 5) * stride] |= 1u << (v & 31);
+    bits[(v >> 5) * stride] = (taken ? wt : wr) | (1u << (v & 31));
     return v;
 }
 
