@@ -94,7 +94,11 @@ typedef struct {
     int32_t abi_version;   /* IRBE_ABI_VERSION                                       */
     int32_t precision;     /* IRBE_MIXED_FP32: pair and k-space arithmetic in FP32,
                               structure factor, momentum correction, energies and
-                              virial accumulated in FP64. IRBE_FP64: all FP64.      */
+                              virial accumulated in FP64; the pair terms (forward
+                              and adjoint) take each charge rounded to 19 mantissa
+                              bits (relative change below 2^-20), which lets a pair
+                              read position, charge and type in one 16-byte load.
+                              IRBE_FP64: all FP64, exact charges.                  */
     int64_t n_atoms;       /* N >= 1                                                 */
     double box_length;     /* L, cubic periodic box                                  */
     double ewald_beta;     /* beta = sqrt(alpha): erfc(beta r) real-space split      */

@@ -2,6 +2,8 @@
 // positions, cell histogram, exclusive scan, scatter, in-cell ordering by
 // (x coordinate, atom id), and the gather of a cell-sorted structure-of-arrays
 // copy of the system.
+#include <type_traits>
+
 #include "irbe_device.hpp"
 #include "irbe_internal.hpp"
 
@@ -192,6 +194,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_rank(int64_t n, const int32_t* 
     perm[b + r] = i;
 }
 
+// The FP32 pair kernels' record of an atom: the fixed-point coordinates and the
+// charge rounded to 19 mantissa bits (to nearest, ties away from zero), whose
+// freed 4 low bits carry the type (n_types <= 16).
+__device__ __forceinline__ uint4 pos_charge_record(uint4 s, float q, int32_t type)
+{
+    const uint32_t b = (__float_as_uint(q) + 8u) & ~15u;
+    return make_uint4(s.x, s.y, s.z, b | ((uint32_t)type & 15u));
+}
+
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n, const int32_t* __restrict__ perm,
                                                           const uint4* __restrict__ sq,
@@ -199,8 +210,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n, const int32
                                                           const real* __restrict__ q, const int32_t* __restrict__ mol,
                                                           const int32_t* __restrict__ xoff,
                                                           uint4* __restrict__ spos, real* __restrict__ sqr,
-                                                          int32_t* __restrict__ smol, int2* __restrict__ sxr,
-                                                          int32_t* __restrict__ rank)
+                                                          uint4* __restrict__ spq, int32_t* __restrict__ smol,
+                                                          int2* __restrict__ sxr, int32_t* __restrict__ rank)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -208,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n, const int32
     const uint4 s = sq[i];
     spos[k] = make_uint4(s.x, s.y, s.z, (uint32_t)type[i]);
     sqr[k] = q[i];
+    if (std::is_same<real, float>::value) spq[k] = pos_charge_record(s, (float)q[i], type[i]);
     smol[k] = mol[i];
     sxr[k] = make_int2(xoff[i], xoff[i + 1] - xoff[i]);
     rank[i] = (int32_t)k;
@@ -244,11 +256,11 @@ hipError_t launch_bin(irbe_ctx* h, const void* pos)
     if (h->fp64)
         k_gather_sorted<double><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const double*)h->q_orig,
                                                               h->mol_orig, h->xoff, h->spos, (double*)h->sq_r,
-                                                              h->smol, h->sxr, h->rank);
+                                                              nullptr, h->smol, h->sxr, h->rank);
     else
         k_gather_sorted<float><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const float*)h->q_orig,
-                                                             h->mol_orig, h->xoff, h->spos, (float*)h->sq_r, h->smol,
-                                                             h->sxr, h->rank);
+                                                             h->mol_orig, h->xoff, h->spos, (float*)h->sq_r, h->spq,
+                                                             h->smol, h->sxr, h->rank);
     if (h->n_excl > 0)
         k_excl_sorted<<<(unsigned)blocks_for(h->n_excl, kBlock), kBlock, 0, h->stream>>>(h->n_excl, h->xidx, h->rank,
                                                                                         h->sxidx);
@@ -262,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_requantize(int64_t n, const real* __
                                                        const int32_t* __restrict__ rank,
                                                        const int32_t* __restrict__ type, const real* __restrict__ q,
                                                        uint4* __restrict__ sq, uint4* __restrict__ spos,
-                                                       real* __restrict__ sqr, uint32_t* err)
+                                                       real* __restrict__ sqr, uint4* __restrict__ spq, uint32_t* err)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -274,6 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_requantize(int64_t n, const real* __
     sq[i] = make_uint4(sx, sy, sz, sq[i].w);
     spos[k] = make_uint4(sx, sy, sz, (uint32_t)type[i]);
     sqr[k] = q[i];
+    if (std::is_same<real, float>::value)
+        spq[k] = pos_charge_record(make_uint4(sx, sy, sz, 0u), (float)q[i], type[i]);
     if (bad) atomicOr(err, ERR_NONFINITE);
 }
 
@@ -284,11 +298,11 @@ hipError_t launch_requantize(irbe_ctx* h, const void* pos)
     if (h->fp64)
         k_requantize<double><<<nb, kBlock, 0, h->stream>>>(n, (const double*)pos, h->geo.inv_l, h->rank, h->type_orig,
                                                            (const double*)h->q_orig, h->sq, h->spos,
-                                                           (double*)h->sq_r, h->err);
+                                                           (double*)h->sq_r, nullptr, h->err);
     else
         k_requantize<float><<<nb, kBlock, 0, h->stream>>>(n, (const float*)pos, h->geo.inv_l, h->rank, h->type_orig,
                                                           (const float*)h->q_orig, h->sq, h->spos, (float*)h->sq_r,
-                                                          h->err);
+                                                          h->spq, h->err);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 // positions, core entries counting only at D^2 <= T_c, shell entries only at
 // T_c < D^2 <= T_s and full-list entries only at D^2 <= T_s.
 #include <algorithm>
+#include <type_traits>
 
 #include "irbe_device.hpp"
 #include "irbe_internal.hpp"
@@ -28,6 +29,29 @@ struct PairParams {
     real beta;
     real cgauss;    // 2 beta / sqrt(pi)
     real ke;
+};
+
+// Position (type in .w) and charge of sorted atom j. FP32 evaluations read one
+// 16-byte record: the fixed-point coordinates and, in the fourth word, the
+// charge rounded to 19 mantissa bits (relative change below 2^-20) with the
+// atom's type in the 4 bits this frees, so that a pair costs one gather
+// instead of two; FP64 evaluations read the position and the exact charge.
+template <typename real>
+struct Atoms {
+    const uint4* __restrict__ spos;
+    const real* __restrict__ sqr;
+    const uint4* __restrict__ spq;
+    __device__ __forceinline__ void get(int64_t j, uint4& p, real& q) const
+    {
+        if constexpr (std::is_same<real, float>::value) {
+            const uint4 r = spq[j];
+            p = make_uint4(r.x, r.y, r.z, r.w & 15u);
+            q = __uint_as_float(r.w & ~15u);
+        } else {
+            p = spos[j];
+            q = sqr[j];
+        }
+    }
 };
 
 // Exact squared separation in quanta (minimum image through 32-bit wrap-around).
@@ -394,11 +418,11 @@ __device__ __forceinline__ void add_excl(PairSum<real>& px, uint4 si, real qi, u
 template <typename real, bool FULL, bool EV, bool STENCIL, bool SKIN>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
-    const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
-    const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
-    const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
-    int p_stride, const uint16_t* __restrict__ ranks, StencilArgs sa, uint64_t t_core, uint64_t t_shell,
-    real* __restrict__ fsr, double* __restrict__ part)
+    const uint4* __restrict__ spq, const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx,
+    const int32_t* __restrict__ core, const int32_t* __restrict__ ncore, int cap_core,
+    const int32_t* __restrict__ shell, const int32_t* __restrict__ nshell, int cap_shell,
+    const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, int p_stride, const uint16_t* __restrict__ ranks,
+    StencilArgs sa, uint64_t t_core, uint64_t t_shell, real* __restrict__ fsr, double* __restrict__ part)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -416,10 +440,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int64_t a1 = min(n, a0 + apw);
     double fc_sum[3] = {0.0, 0.0, 0.0};
     PairSum<real> ev;  // per-lane energy/virial totals (forces unused)
+    const Atoms<real> at{spos, sqr, spq};
     // per-atom headers of the wavefront's atoms, one atom per lane, read once
     const int64_t ah = min(a0 + min(lane, apw - 1), n - 1);
-    const uint4 h_s = spos[ah];
-    const real h_q = sqr[ah];
+    uint4 h_s;
+    real h_q;
+    at.get(ah, h_s, h_q);
     const int h_nc = FULL ? 0 : ncore[ah];
     const int h_ns = nshell[ah];
     const int2 h_x = sxr[ah];
@@ -489,14 +515,17 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const int mj0 = STENCIL ? sa.smol[max(js0, 0)] : 0;
         const int mj1 = STENCIL ? sa.smol[max(js1, 0)] : 0;
         // (unused slots load atom 0, so that every position is one 16-byte load)
-        const uint4 pjc = spos[max(jc, 0)];
-        const real qjc = sqr[max(jc, 0)];
-        const uint4 pj0 = spos[max(js0, 0)];
-        const real qj0 = sqr[max(js0, 0)];
-        const uint4 pj1 = spos[max(js1, 0)];
-        const real qj1 = sqr[max(js1, 0)];
-        const uint4 pjx = kFold ? pjc : spos[max(jx, 0)];
-        const real qjx = kFold ? qjc : sqr[max(jx, 0)];
+        uint4 pjc, pj0, pj1, pjx;
+        real qjc, qj0, qj1, qjx;
+        at.get(max(jc, 0), pjc, qjc);
+        at.get(max(js0, 0), pj0, qj0);
+        at.get(max(js1, 0), pj1, qj1);
+        if (kFold) {
+            pjx = pjc;
+            qjx = qjc;
+        } else {
+            at.get(max(jx, 0), pjx, qjx);
+        }
         // skin: a core entry counts inside r_core, a list shell entry inside the annulus
         // (the whole ball in full-list mode), at these positions
         auto core_ok = [&](uint4 sj) { return !SKIN || dist2_q(si, sj) <= t_core; };
@@ -519,18 +548,24 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         if (kFold) {
             for (int c = lane + 64; c < nc + xr.y; c += 64) {
                 const int j = c < nc ? crow[c] : sxidx[xr.x + c - nc];
-                const uint4 sj = spos[j];
-                if (c >= nc || core_ok(sj)) add_pair_or_excl(pc, px, si, qi, sj, sqr[j], ljof(sj), pp, c >= nc);
+                uint4 sj;
+                real qj;
+                at.get(j, sj, qj);
+                if (c >= nc || core_ok(sj)) add_pair_or_excl(pc, px, si, qi, sj, qj, ljof(sj), pp, c >= nc);
             }
         } else {
             for (int c = lane + 64; c < nc; c += 64) {
                 const int j = crow[c];
-                const uint4 sj = spos[j];
-                if (core_ok(sj)) add_pair<real, EV>(pc, si, qi, sj, sqr[j], ljof(sj), pp);
+                uint4 sj;
+                real qj;
+                at.get(j, sj, qj);
+                if (core_ok(sj)) add_pair<real, EV>(pc, si, qi, sj, qj, ljof(sj), pp);
             }
             for (int c = lane + 64; c < xr.y; c += 64) {
-                const int j = sxidx[xr.x + c];
-                add_excl<real, EV>(px, si, qi, spos[j], sqr[j], pp);
+                uint4 sj;
+                real qj;
+                at.get(sxidx[xr.x + c], sj, qj);
+                add_excl<real, EV>(px, si, qi, sj, qj, pp);
             }
         }
         if (STENCIL && cnt > 128) {
@@ -544,13 +579,17 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         for (int c = lane + 128; c < cnt; c += 64) {
             if (STENCIL) {
                 const int j = stencil_rows_atom(srows[wave], nrows, sample ? (int)rrow[c] : c);
-                const uint4 sj = spos[j];
+                uint4 sj;
+                real qj;
+                at.get(j, sj, qj);
                 if (stencil_member(a, j, mi, sa.smol[j], si, sj, t_core, t_shell))
-                    add_pair<real, EV>(ps, si, qi, sj, sqr[j], ljof(sj), pp);
+                    add_pair<real, EV>(ps, si, qi, sj, qj, ljof(sj), pp);
             } else {
                 const int j = srow[sample ? (int)rrow[c] : c];
-                const uint4 sj = spos[j];
-                if (shell_ok(sj)) add_pair<real, EV>(ps, si, qi, sj, sqr[j], ljof(sj), pp);
+                uint4 sj;
+                real qj;
+                at.get(j, sj, qj);
+                if (shell_ok(sj)) add_pair<real, EV>(ps, si, qi, sj, qj, ljof(sj), pp);
             }
         }
         // one set of sums: the excluded-pair forces cancel pairwise, so the momentum
@@ -599,11 +638,11 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
 template <typename real, bool EV>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
     int64_t n, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
-    const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
-    const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
-    const int32_t* __restrict__ nshell, int cap_shell, const LJ<real>* __restrict__ lj_g, int n_types, int p_shell,
-    int p_stride, const uint16_t* __restrict__ ranks, uint64_t t_core, uint64_t t_shell, bool skin,
-    real* __restrict__ fsr, double* __restrict__ part)
+    const uint4* __restrict__ spq, const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx,
+    const int32_t* __restrict__ core, const int32_t* __restrict__ ncore, int cap_core,
+    const int32_t* __restrict__ shell, const int32_t* __restrict__ nshell, int cap_shell,
+    const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, int p_stride, const uint16_t* __restrict__ ranks,
+    uint64_t t_core, uint64_t t_shell, bool skin, real* __restrict__ fsr, double* __restrict__ part)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -614,9 +653,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
     const int64_t a = blk * kCoopBlock + threadIdx.x;
     double vals[kPairPartials];
     for (int c = 0; c < kPairPartials; ++c) vals[c] = 0.0;
+    const Atoms<real> at{spos, sqr, spq};
     if (a < n) {
-        const uint4 si = spos[a];
-        const real qi = sqr[a] * pp.ke;
+        uint4 si;
+        real qi;
+        at.get(a, si, qi);
+        qi *= pp.ke;
         // LJ coefficients of the pair types (32-bit LDS indexing; n_types^2 <= 256)
         const int li = (int)si.w * n_types;
         auto ljof = [&](uint4 sj) -> const LJ<real>& { return lj[(li + (int)sj.w) & 255]; };
@@ -631,10 +673,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
 #pragma unroll
             for (int u = 0; u < 4; ++u) j[u] = c0 + u < nc ? crow[c0 + u] : -1;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                sj[u] = spos[max(j[u], 0)];
-                qj[u] = sqr[max(j[u], 0)];
-            }
+            for (int u = 0; u < 4; ++u) at.get(max(j[u], 0), sj[u], qj[u]);
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (j[u] >= 0 && (!skin || dist2_q(si, sj[u]) <= t_core))
@@ -642,8 +681,10 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
         }
         const int2 xr = sxr[a];
         for (int c = 0; c < xr.y; ++c) {
-            const int j = sxidx[xr.x + c];
-            add_excl<real, EV>(px, si, qi, spos[j], sqr[j], pp);
+            uint4 sj;
+            real qj;
+            at.get(sxidx[xr.x + c], sj, qj);
+            add_excl<real, EV>(px, si, qi, sj, qj, pp);
         }
         const int ns = nshell[a];
         const bool sample = ns > p_shell;
@@ -659,10 +700,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
 #pragma unroll
             for (int u = 0; u < 4; ++u) j[u] = r[u] >= 0 ? srow[r[u]] : -1;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                sj[u] = spos[max(j[u], 0)];
-                qj[u] = sqr[max(j[u], 0)];
-            }
+            for (int u = 0; u < 4; ++u) at.get(max(j[u], 0), sj[u], qj[u]);
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (j[u] >= 0 && (!skin || in_annulus(si, sj[u], t_core, t_shell)))
@@ -794,7 +832,7 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     k_pair_coop<real, FULL, EV, STENCIL, SKIN><<<nb, kCoopBlock, 0, h->stream>>>(
-        n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
+        n, apw, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
         h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
@@ -815,7 +853,7 @@ static hipError_t launch_thread_t(irbe_ctx* h, uint64_t step)
     const unsigned nb = (unsigned)blocks_for(n, kCoopBlock);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     k_pair_thread<real, EV><<<nb, kCoopBlock, 0, h->stream>>>(
-        n, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core, h->shell, h->nshell,
+        n, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core, h->shell, h->nshell,
         h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride, h->ranks, h->geo.t_core,
         h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part);
     h->pair_nb = nb;
@@ -1054,7 +1092,7 @@ __device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_
 template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
-    const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
+    const uint4* __restrict__ spq, const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const real* __restrict__ ljraw_g, int n_types, int p_shell,
     int p_stride, const uint16_t* __restrict__ ranks, const int32_t* __restrict__ batch_j, uint64_t t_core,
@@ -1109,10 +1147,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     // cell row of the block's first atom: the block's atoms lie in rows row0, row0 + 1, ...
     const int row0 = BK ? cell_row(spos[min(blk * NW * apw, n - 1)], bk.n_c) : 0;
     real lane_max = 0;  // largest |component| of the records this lane staged
+    const Atoms<real> at{spos, sqr, spq};
     // per-atom headers of the wavefront's atoms, one atom per lane, read once
     const int64_t ah = min(a0 + min(lane, apw - 1), n - 1);
-    const uint4 h_s = spos[ah];
-    const real h_q = sqr[ah];
+    uint4 h_s;
+    real h_q;
+    at.get(ah, h_s, h_q);
     const real h_gx = gs[3 * ah], h_gy = gs[3 * ah + 1], h_gz = gs[3 * ah + 2];
     const int h_nsym = FULL ? nshell[ah] : ncore[ah];
     const int h_ns = FULL ? 0 : nshell[ah];
@@ -1265,13 +1305,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const int js0 = STENCIL ? r0 : ((!FULL && r0 >= 0) ? srow[r0] : -1);
         const int js1 = STENCIL ? r1 : ((!FULL && r1 >= 0) ? srow[r1] : -1);
         const int ic = max(jc, 0), i0 = max(js0, 0), i1 = max(js1, 0), ix = max(jx, 0);
-        const uint4 pjc = spos[ic];
-        const real qjc = sqr[ic];
+        uint4 pjc, pj0, pj1;
+        real qjc, qj0, qj1;
+        at.get(ic, pjc, qjc);
         const real gcx = gs[3 * (int64_t)ic], gcy = gs[3 * (int64_t)ic + 1], gcz = gs[3 * (int64_t)ic + 2];
-        const uint4 pj0 = spos[i0];
-        const real qj0 = sqr[i0];
-        const uint4 pj1 = spos[i1];
-        const real qj1 = sqr[i1];
+        at.get(i0, pj0, qj0);
+        at.get(i1, pj1, qj1);
         (void)jx;
         (void)ix;
         // skin: a symmetric-list entry counts inside r_core (r_shell for the full
@@ -1285,21 +1324,27 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         // the rest (long lists and large batches)
         for (int c = lane + 64; c < nsym + xr.y; c += 64) {
             const int j = c < nsym ? srow_sym[c] : sxidx[xr.x + c - nsym];
-            const uint4 sj = spos[j];
+            uint4 sj;
+            real qj;
+            at.get(j, sj, qj);
             if (c >= nsym || sym_ok(sj))
-                sym_pair(sj, sqr[j], gs[3 * (int64_t)j], gs[3 * (int64_t)j + 1], gs[3 * (int64_t)j + 2], c >= nsym);
+                sym_pair(sj, qj, gs[3 * (int64_t)j], gs[3 * (int64_t)j + 1], gs[3 * (int64_t)j + 2], c >= nsym);
         }
         if (!FULL)
             for (int c = lane + 128; c < cnt; c += 64) {
                 if (STENCIL) {
                     const int j = batch_j[a * (int64_t)p_stride + c];
                     if (j < 0) continue;
-                    const uint4 sj = spos[j];
-                    if (in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, sqr[j]);
+                    uint4 sj;
+                    real qj;
+                    at.get(j, sj, qj);
+                    if (in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, qj);
                 } else {
                     const int j = srow[sample ? (int)rrow[c] : c];
-                    const uint4 sj = spos[j];
-                    if (!skin || in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, sqr[j]);
+                    uint4 sj;
+                    real qj;
+                    at.get(j, sj, qj);
+                    if (!skin || in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, qj);
                 }
             }
         rx = wave_sum_r(rx);
@@ -1491,7 +1536,7 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     h->adj_nb = nb;
     k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL><<<nb, kCoopBlock, lds, h->stream>>>(
-        n, apw, pp, h->spos, (const real*)h->sq_r, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
+        n, apw, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
         h->p_stride, h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, h->geo.skin, (real)h->cfg.lj_cut,
         (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
