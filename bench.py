@@ -571,7 +571,8 @@ def main():
                         "every step; P = 200 unless stated; initial_* = slopes over the first 0.1 ps (the heating "
                         "by the random batch Ewald force, whose variance scales as 1/P); drift = slope over the "
                         "whole run; trace = temperature and total energy every 50 fs; ms_per_step = lists + forces "
-                        "+ integrator")}
+                        "+ integrator; a run that heats until the rigid constraints fail stops at the check (every "
+                        "100 steps) that found it: constraints_failed_by_ps, and the samples up to the check before")}
         extras = {
             "fwd_bwd_atom_steps_per_s": n / (ms_fb * 1e-3), "ms_per_step_fwd_bwd": ms_fb,
             "forces_only_reused_lists_atom_steps_per_s": n / (ms_f * 1e-3), "ms_per_forces_only": ms_f,

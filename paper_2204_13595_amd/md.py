@@ -197,7 +197,10 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
     force scales as 1/p (Eq. (2.14)), so the initial heating rate (the slope of
     the total energy over the first 0.1 ps) scales as 1/p. (The temperature
     also moves early on as the fresh velocities equilibrate with the relaxed
-    structure, so its slope is no measure of the heating.)
+    structure, so its slope is no measure of the heating.) A run that heats far
+    enough for the rigid constraints to fail stops there: the state is checked
+    every 100 steps, and the result then records the time of the last good check
+    and keeps the samples up to it.
     Returns the traces, the initial and whole-run slopes, and ms per step (wall
     clock of the whole loop: lists, forces, integrator)."""
     import torch
@@ -230,6 +233,7 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
     v0 -= (v0 / inv_mass[:, None]).sum(axis=0) / (1.0 / inv_mass).sum()  # zero total momentum
     vel.copy_(torch.tensor(v0, device=dev))
     e_s, k_s, t_s = [], [], []
+    good, done, executed, failed_at = 0, 0, 0, None  # samples and steps up to the last good check
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(warm_steps, warm_steps + steps):
@@ -245,9 +249,22 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
         else:
             h.compute_forces(pos_f, step, out=force)
             dyn.step(pos, vel, force, step, pos_copy=pos_f)
-    dyn.check()
+        executed = step - warm_steps + 1
+        if executed % 100 == 0 or executed == steps:
+            try:
+                dyn.check()
+            except irbe.IRBEError:
+                failed_at = executed * dt
+                break
+            good, done = len(e_s), executed
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    e_s, k_s, t_s = e_s[:good], k_s[:good], t_s[:good]
+    if len(t_s) < 3:
+        h.close()
+        dyn.close()
+        return {"p_kspace": p_kspace, "p_shell": p_shell, "precision": precision, "steps": done,
+                "constraints_failed_by_ps": failed_at, "ms_per_step": 1e3 * wall / max(executed, 1)}
     e = torch.cat(e_s).cpu().numpy() / n_waters
     temp = 2.0 * torch.cat(k_s).cpu().numpy() / (dyn.n_dof * dynamics.KB)
     t = np.array(t_s)
@@ -265,7 +282,8 @@ def run_nve(n_waters: int = 32768, box: float = 9.93, *, p_shell: int = 100, p_k
             "trace": {"t_ps": [round(float(x), 4) for x in t[::thin]],
                       "temperature_K": [round(float(x), 2) for x in temp[::thin]],
                       "energy_per_molecule": [round(float(x), 3) for x in e[::thin]]},
-            "ms_per_step": 1e3 * wall / steps, "steps": steps}
+            "ms_per_step": 1e3 * wall / max(executed, 1), "steps": done,
+            "constraints_failed_by_ps": failed_at}
 
 
 def run_electrolyte(valence: int = 1, *, p_shell: int = 10, p_kspace: int = 100, r_core: float = 5.0,
