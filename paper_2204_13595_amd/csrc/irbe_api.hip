@@ -507,6 +507,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     ALLOC(dalloc(h, &h->spos, n));
     ALLOC(dalloc(h, &h->spk, n));
     if (!h->fp64) ALLOC(dalloc(h, &h->spq, n));
+    if (h->geo.skin) ALLOC(dalloc(h, &h->brow, n));
     ALLOC(dalloc_bytes(h, &h->sq_r, n * rs));
     ALLOC(dalloc(h, &h->smol, n));
     ALLOC(dalloc(h, &h->sxr, n));

@@ -138,6 +138,7 @@ struct irbe_ctx {
     int32_t* rank = nullptr;          // [N] caller id -> sorted
     uint4* spos = nullptr;            // [N] sorted {sx, sy, sz, type}
     uint4* spk = nullptr;             // [N] sorted packed records of the list build
+    int32_t* brow = nullptr;          // [N] cell (z << 16 | y) at the build of each sorted atom (lists with a skin)
     uint4* spq = nullptr;             // [N] sorted {sx, sy, sz, FP32 charge with the type in its low 4 bits}
                                       //     (FP32 evaluations; the FP64 ones read spos and sq_r)
     void* sq_r = nullptr;             // real[N] sorted charges

@@ -211,12 +211,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n, const int32
                                                           const int32_t* __restrict__ xoff,
                                                           uint4* __restrict__ spos, real* __restrict__ sqr,
                                                           uint4* __restrict__ spq, int32_t* __restrict__ smol,
-                                                          int2* __restrict__ sxr, int32_t* __restrict__ rank)
+                                                          int2* __restrict__ sxr, int32_t* __restrict__ rank,
+                                                          int n_c, int32_t* __restrict__ brow)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int32_t i = perm[k];
     const uint4 s = sq[i];
+    if (brow) {
+        // the cell's (z, y) at this build (s.w is the cell id)
+        const uint32_t row = s.w / (uint32_t)n_c;
+        brow[k] = (int32_t)(((row / (uint32_t)n_c) << 16) | (row % (uint32_t)n_c));
+    }
     spos[k] = make_uint4(s.x, s.y, s.z, (uint32_t)type[i]);
     sqr[k] = q[i];
     if (std::is_same<real, float>::value) spq[k] = pos_charge_record(s, (float)q[i], type[i]);
@@ -256,11 +262,12 @@ hipError_t launch_bin(irbe_ctx* h, const void* pos)
     if (h->fp64)
         k_gather_sorted<double><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const double*)h->q_orig,
                                                               h->mol_orig, h->xoff, h->spos, (double*)h->sq_r,
-                                                              nullptr, h->smol, h->sxr, h->rank);
+                                                              nullptr, h->smol, h->sxr, h->rank, h->geo.n_c,
+                                                              h->brow);
     else
         k_gather_sorted<float><<<nb, kBlock, 0, h->stream>>>(n, h->perm, h->sq, h->type_orig, (const float*)h->q_orig,
                                                              h->mol_orig, h->xoff, h->spos, (float*)h->sq_r, h->spq,
-                                                             h->smol, h->sxr, h->rank);
+                                                             h->smol, h->sxr, h->rank, h->geo.n_c, h->brow);
     if (h->n_excl > 0)
         k_excl_sorted<<<(unsigned)blocks_for(h->n_excl, kBlock), kBlock, 0, h->stream>>>(h->n_excl, h->xidx, h->rank,
                                                                                         h->sxidx);

@@ -1053,6 +1053,8 @@ struct BucketArgs {
     void* rec_c;                  // real[4 * total]
     uint16_t* rec_j;              // [total]
     unsigned long long* n_atomic; // records that took device atomics instead of a bucket
+    const int32_t* brow;          // cell (z, y) at the build of each sorted atom (z << 16 | y), used for the keys
+                                  // when positions may have moved since (lists with a skin); null: from positions
 };
 
 __device__ __forceinline__ int64_t bucket_start(const BucketArgs& bk, int row)
@@ -1066,6 +1068,21 @@ __device__ __forceinline__ int cell_row(uint4 s, int n_c)
     const int cz = (int)(((uint64_t)s.z * (uint32_t)n_c) >> 32);
     const int cy = (int)(((uint64_t)s.y * (uint32_t)n_c) >> 32);
     return cz * n_c + cy;
+}
+
+// Cell coordinates (z, y) of sorted atom k for the bucket keys: those of its
+// cell at the list build when the positions may have moved since, else those
+// of its position.
+__device__ __forceinline__ void key_cell(const BucketArgs& bk, int64_t k, uint4 s, int& z, int& y)
+{
+    if (bk.brow) {
+        const int b = bk.brow[k];
+        z = b >> 16;
+        y = b & 0xffff;
+    } else {
+        z = (int)(((uint64_t)s.z * (uint32_t)bk.n_c) >> 32);
+        y = (int)(((uint64_t)s.y * (uint32_t)bk.n_c) >> 32);
+    }
 }
 
 // Offset d = c_j - c_i of a stencil cell mapped into [lo, lo + span).
@@ -1145,7 +1162,13 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     const int64_t a0 = gw * apw;
     const int64_t a1 = min(n, a0 + apw);
     // cell row of the block's first atom: the block's atoms lie in rows row0, row0 + 1, ...
-    const int row0 = BK ? cell_row(spos[min(blk * NW * apw, n - 1)], bk.n_c) : 0;
+    int row0 = 0;
+    if (BK) {
+        const int64_t f = min(blk * NW * apw, n - 1);
+        int z, y;
+        key_cell(bk, f, spos[f], z, y);
+        row0 = z * bk.n_c + y;
+    }
     real lane_max = 0;  // largest |component| of the records this lane staged
     const Atoms<real> at{spos, sqr, spq};
     // per-atom headers of the wavefront's atoms, one atom per lane, read once
@@ -1192,6 +1215,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const uint4 si = make_uint4(bcast(h_s.x, t_a), bcast(h_s.y, t_a), bcast(h_s.z, t_a),
                                     bcast(h_s.w, t_a));
         const int ti = (int)si.w;
+        int zi = 0, yi = 0;  // the atom's cell for the bucket keys
+        if (BK) key_cell(bk, a, si, zi, yi);
         // with every sigma of its row zero, the atom has no LJ term and no LJ gradient
         const bool lj_i = WANT_LJ && lj_row[ti];
         const real qi = bcast(h_q, t_a);
@@ -1255,16 +1280,14 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             const real jq_ = w * (-ke * qi * g.a_coul) * gdi;
             bool staged = false;
             if (BK) {
-                // key: (source row - row0, row offset of j); positions moved since the
-                // lists were built can leave the window, and then take the atomics
+                // key: (source row - row0, row offset of j), on the cells of the build
+                // when positions may have moved since
                 const int nc_ = bk.n_c;
-                const int src = cell_row(si, nc_) - row0;  // wave-uniform
-                const int kz = stencil_offset((int)(((uint64_t)sj.z * (uint32_t)nc_) >> 32),
-                                              (int)(((uint64_t)si.z * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
-                               bk.lo;
-                const int ky = stencil_offset((int)(((uint64_t)sj.y * (uint32_t)nc_) >> 32),
-                                              (int)(((uint64_t)si.y * (uint32_t)nc_) >> 32), bk.lo, bk.span, nc_) -
-                               bk.lo;
+                const int src = zi * nc_ + yi - row0;  // wave-uniform
+                int zj, yj;
+                key_cell(bk, j, sj, zj, yj);
+                const int kz = stencil_offset(zj, zi, bk.lo, bk.span, nc_) - bk.lo;
+                const int ky = stencil_offset(yj, yi, bk.lo, bk.span, nc_) - bk.lo;
                 if (src >= 0 && src < 2 && kz >= 0 && kz < bk.span && ky >= 0 && ky < bk.span) {
                     const int key = src * span2 + kz * bk.span + ky;
                     const uint64_t m = __ballot(1);
@@ -1611,6 +1634,7 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
         e = launch_fill_i32(h->stream, (int32_t*)h->adj_atomics, 0, 2);
         if (e != hipSuccess) return e;
         bk.n_atomic = h->adj_atomics;
+        bk.brow = h->geo.skin ? h->brow : nullptr;
         bk.cell_start = h->cell_start;
         bk.cursor = h->bk_cursor;
         bk.rowmax = h->bk_cursor + rows;
