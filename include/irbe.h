@@ -314,6 +314,17 @@ const char* irbe_last_error(irbe_handle h);
 /* Wait for the handle's work and free everything it owns. */
 irbe_status irbe_destroy(irbe_handle h);
 
+/* Measured ceilings of the current HIP device, for reading the roofline
+ * figures beside the published peaks; no handle needed. valu_lane_ops_per_s
+ * (if not NULL): the rate of full-rate 32-bit integer VALU operations, from
+ * independent 24-bit multiply-add chains in every lane of 32 wavefronts per
+ * CU (lane operations per second). copy_bytes_per_s (if not NULL): bytes read
+ * plus written per second by a streaming 16-byte copy of 1 GiB. Each is timed
+ * with HIP events on hip_stream after one untimed launch; the call allocates
+ * and frees its own buffers (up to 2 GiB), waits for the stream, and returns
+ * IRBE_ENOMEM or IRBE_EHIP on failure. */
+irbe_status irbe_probe_rates(void* hip_stream, double* valu_lane_ops_per_s, double* copy_bytes_per_s);
+
 /* ------------------------------------------------------------------------
  * Langevin dynamics (Algorithm 1's last step, "integrate the equations of
  * motion with a thermostat"): the underdamped Langevin equations of Sec. 3,

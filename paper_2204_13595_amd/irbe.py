@@ -35,7 +35,7 @@ _DBG_DTYPE = {1: np.int64, 2: np.int64, 3: np.int64, 4: np.int32, 5: np.int64, 6
 STATUS = {0: "IRBE_OK", -1: "IRBE_EINVAL", -2: "IRBE_ENOMEM", -3: "IRBE_EHIP", -4: "IRBE_ECAPACITY",
           -5: "IRBE_ESTATE", -6: "IRBE_EUNSUPPORTED", -7: "IRBE_ENONFINITE", -8: "IRBE_ECONVERGENCE"}
 
-EXPORTED = ("irbe_create", "irbe_set_system", "irbe_update_parameters", "irbe_build_lists", "irbe_compute_forces",
+EXPORTED = ("irbe_probe_rates", "irbe_create", "irbe_set_system", "irbe_update_parameters", "irbe_build_lists", "irbe_compute_forces",
             "irbe_compute_forces_backward", "irbe_compute_forces_noalloc", "irbe_sync", "irbe_enable_timing", "irbe_get_timing", "irbe_get_debug",
             "irbe_get_debug_rows", "irbe_last_error", "irbe_destroy", "irbe_dyn_create", "irbe_dyn_set_system",
             "irbe_dyn_step", "irbe_dyn_kinetic", "irbe_dyn_msd", "irbe_dyn_rdf", "irbe_dyn_thermostat_state",
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         raise FileNotFoundError(f"{path} is missing: build it with `python -m paper_2204_13595_amd.build`")
     L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
+    L.irbe_probe_rates.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.irbe_create.argtypes = [ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]
     L.irbe_set_system.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.irbe_update_parameters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -118,6 +119,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def probe_rates(stream=None) -> dict:
+    """Measured VALU lane-operation rate and streaming-copy bandwidth of the
+    current device (irbe_probe_rates), on `stream` (default: torch's current)."""
+    L = load_library()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    valu, copy = ctypes.c_double(), ctypes.c_double()
+    st = L.irbe_probe_rates(ctypes.c_void_p(s.cuda_stream), ctypes.byref(valu), ctypes.byref(copy))
+    if st != 0:
+        raise IRBEError(st, L.irbe_last_error(None).decode())
+    return {"valu_lane_ops_per_s": valu.value, "copy_bytes_per_s": copy.value}
 
 
 def _ptr(t: torch.Tensor | None):
