@@ -1106,14 +1106,14 @@ __device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_
 // One wavefront per atom (cell order), lanes over the atom's lists. BK: the
 // shell scatter goes through the LDS-staged buckets (dynamic LDS: rec_cap
 // records of 4 reals + j + key, then 7 ints per key).
-template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL>
+template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL, bool SKIN>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const uint4* __restrict__ spq, const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
     const int32_t* __restrict__ ncore, int cap_core, const int32_t* __restrict__ shell,
     const int32_t* __restrict__ nshell, int cap_shell, const real* __restrict__ ljraw_g, int n_types, int p_shell,
     int p_stride, const uint16_t* __restrict__ ranks, const int32_t* __restrict__ batch_j, uint64_t t_core,
-    uint64_t t_shell, bool skin, real lj_cut, const real* __restrict__ gs, const double* __restrict__ gmean_d,
+    uint64_t t_shell, real lj_cut, const real* __restrict__ gs, const double* __restrict__ gmean_d,
     real* __restrict__ gself, real* __restrict__ gscat, real* __restrict__ gqself, real* __restrict__ gqscat,
     double* __restrict__ ljpart, BucketArgs bk, int rec_cap)
 {
@@ -1215,6 +1215,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const uint4 si = make_uint4(bcast(h_s.x, t_a), bcast(h_s.y, t_a), bcast(h_s.z, t_a),
                                     bcast(h_s.w, t_a));
         const int ti = (int)si.w;
+        const int li = __mul24(ti, n_types);  // the atom's row of the LJ table
         int zi = 0, yi = 0;  // the atom's cell for the bucket keys
         if (BK) key_cell(bk, a, si, zi, yi);
         // with every sigma of its row zero, the atom has no LJ term and no LJ gradient
@@ -1243,7 +1244,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
             const real r2 = dx * dx + dy * dy + dz * dz;
-            const LJGrad<real>& L = ljg[ti * n_types + (int)sj.w];
+            const LJGrad<real>& L = ljg[li + (int)sj.w];
             const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp, xp);
             const real ex_ = gjx - gx, ey_ = gjy - gy, ez_ = gjz - gz;
             const real gd = dx * ex_ + dy * ey_ + dz * ez_;
@@ -1267,7 +1268,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
             real dx, dy, dz;
             separation(si, sj, pp.quantum, dx, dy, dz);
             const real r2 = dx * dx + dy * dy + dz * dz;
-            const LJGrad<real>& L = ljg[ti * n_types + (int)sj.w];
+            const LJGrad<real>& L = ljg[li + (int)sj.w];
             const PairGrad<real> g = pair_grad(r2, ke * qi * qj, L, pp);
             const real gdi = dx * pgx + dy * pgy + dz * pgz;
             const real jx_ = w * (g.phi * pgx + g.dphi_r * dx * gdi);
@@ -1339,8 +1340,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         // skin: a symmetric-list entry counts inside r_core (r_shell for the full
         // list), a list shell entry inside the annulus, at these positions
         const uint64_t t_sym = FULL ? t_shell : t_core;
-        auto sym_ok = [&](uint4 sj) { return !skin || dist2_q(si, sj) <= t_sym; };
-        const bool shell_test = STENCIL || skin;
+        auto sym_ok = [&](uint4 sj) { return !SKIN || dist2_q(si, sj) <= t_sym; };
+        constexpr bool shell_test = STENCIL || SKIN;
         if (jc >= 0 && (lane >= nsym || sym_ok(pjc))) sym_pair(pjc, qjc, gcx, gcy, gcz, lane >= nsym);
         if (js0 >= 0 && (!shell_test || in_annulus(si, pj0, t_core, t_shell))) shell_pair(js0, pj0, qj0);
         if (js1 >= 0 && (!shell_test || in_annulus(si, pj1, t_core, t_shell))) shell_pair(js1, pj1, qj1);
@@ -1367,7 +1368,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
                     uint4 sj;
                     real qj;
                     at.get(j, sj, qj);
-                    if (!skin || in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, qj);
+                    if (!SKIN || in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, qj);
                 }
             }
         rx = wave_sum_r(rx);
@@ -1558,12 +1559,16 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     h->adj_nb = nb;
-    k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL><<<nb, kCoopBlock, lds, h->stream>>>(
-        n, apw, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
-        h->shell, h->nshell, h->cap_shell, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell,
-        h->p_stride, h->ranks, h->batch_j, h->geo.t_core, h->geo.t_shell, h->geo.skin, (real)h->cfg.lj_cut,
-        (const real*)h->gs, h->gmean, (real*)h->gself, (real*)h->gscat, (real*)h->gqself,
-        (real*)h->gqscat, h->ljpart, bk, rec_cap);
+#define IRBE_ADJ_ARGS                                                                                         \
+    n, apw, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core, h->shell, \
+        h->nshell, h->cap_shell, (const real*)h->lj_raw, h->cfg.n_types, h->cfg.p_shell, h->p_stride, h->ranks,  \
+        h->batch_j, h->geo.t_core, h->geo.t_shell, (real)h->cfg.lj_cut, (const real*)h->gs, h->gmean,             \
+        (real*)h->gself, (real*)h->gscat, (real*)h->gqself, (real*)h->gqscat, h->ljpart, bk, rec_cap
+    if (h->geo.skin)
+        k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL, true><<<nb, kCoopBlock, lds, h->stream>>>(IRBE_ADJ_ARGS);
+    else
+        k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL, false><<<nb, kCoopBlock, lds, h->stream>>>(IRBE_ADJ_ARGS);
+#undef IRBE_ADJ_ARGS
     e = hipGetLastError();
     if (e != hipSuccess || !BK) return e;
     const unsigned rows = (unsigned)((int64_t)bk.n_c * bk.n_c);
