@@ -195,14 +195,15 @@ __device__ __forceinline__ void classify(D d2, const Bounds<D>& b, uint64_t keep
 // Members are appended to the half's rows (byte offsets hoff_s, hoff_c within
 // the descriptors) after cs and cc, which are advanced; a lane reads its own
 // bit of the member masks back for its store.
-template <int MODE, bool CORE>
+template <int MODE, bool CORE, bool LAST>
 __device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x4& ap, int k_atom,
                                            const PackedBounds& tb, const MidBounds& mb, int e, uint64_t t_core,
                                            uint64_t t_lo, uint64_t t_shell, const uint4* __restrict__ spos, int lane,
                                            int hsel, uint32_t lowm, int hoff_s, int hoff_c,
                                            __amdgpu_buffer_rsrc_t rs_s, __amdgpu_buffer_rsrc_t rs_c, int& cs, int& cc)
 {
-    const uint64_t m_keep = ballot(k_in) & ballot(r.z != ap.z);
+    // (only an atom pair's last chunk holds lanes past the end of a range)
+    const uint64_t m_keep = (LAST ? ballot(k_in) : ~0ull) & ballot(r.z != ap.z);
     uint64_t m_core, m_shell, m_amb;
     classify<MODE, CORE>(d2_packed(r.x, r.y, ap.x, ap.y), tb, m_keep, m_core, m_shell, m_amb);
     if (__builtin_expect(m_amb != 0, 0)) {
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                     if (rem < 0.0f) {
                         need = false;
                     } else {
-                        const uint32_t ext = (uint32_t)(sqrtf(rem) * 1.000002f) + 2u;
+                        const uint32_t ext = (uint32_t)(__builtin_amdgcn_sqrtf(rem) * 1.000002f) + 2u;
                         ext_i = (int32_t)ext;
                         const int cl = (int)(((uint64_t)(uint32_t)(si.x - ext) * (uint32_t)n_c) >> 32);
                         const int ch = (int)(((uint64_t)(uint32_t)(si.x + ext) * (uint32_t)n_c) >> 32);
@@ -411,12 +412,16 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                             auto scan = [&](auto core_tag) {
                                 constexpr bool CORE = decltype(core_tag)::value;
                                 const int hoff_c = __mul24(ka, cap_core * 4);
-                                for (int c0 = 0; c0 < chunks * 32; c0 += 32) {
-                                    const u32x4 r = trec[qb + c0];
-                                    const bool k_in = c0 < lenm;
-                                    scan_chunk<MODE, CORE>(r, k_in, ap, chunk + ka, tb, mb, e, t_core, t_lo, t_shell,
-                                                           spos, lane, hsel, lowm, hoff_s, hoff_c, rs_s, rs_c, cs, cc);
-                                }
+                                // the two atoms have the same number of chunks: every lane of
+                                // all chunks but the last lies inside its half's range
+                                const int last = (chunks - 1) * 32;
+                                for (int c0 = 0; c0 < last; c0 += 32)
+                                    scan_chunk<MODE, CORE, false>(trec[qb + c0], true, ap, chunk + ka, tb, mb, e,
+                                                                  t_core, t_lo, t_shell, spos, lane, hsel, lowm,
+                                                                  hoff_s, hoff_c, rs_s, rs_c, cs, cc);
+                                scan_chunk<MODE, CORE, true>(trec[qb + last], last < lenm, ap, chunk + ka, tb, mb, e,
+                                                             t_core, t_lo, t_shell, spos, lane, hsel, lowm, hoff_s,
+                                                             hoff_c, rs_s, rs_c, cs, cc);
                             };
                             if (core_row) scan(std::true_type{});
                             else scan(std::false_type{});
@@ -533,7 +538,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                     if (rem < 0.0f) {
                         need = false;
                     } else {
-                        const uint32_t ext = (uint32_t)(sqrtf(rem) * 1.000002f) + 2u;
+                        const uint32_t ext = (uint32_t)(__builtin_amdgcn_sqrtf(rem) * 1.000002f) + 2u;
                         const int cl = (int)(((uint64_t)(uint32_t)(si.x - ext) * (uint32_t)n_c) >> 32);
                         const int ch = (int)(((uint64_t)(uint32_t)(si.x + ext) * (uint32_t)n_c) >> 32);
                         int ol = cl - cx, oh = ch - cx;
