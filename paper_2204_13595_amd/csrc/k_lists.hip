@@ -32,7 +32,7 @@
 // 32 times narrower; the few left after it take the exact 64-bit test on
 // positions read from memory. The LDS footprint (about 6 KB per wavefront)
 // leaves room for six or more wavefronts per SIMD. (The lane-per-atom kernel
-// for dilute cells below packs positions relative to an origin at its cells.)
+// for dilute cells below uses the same records.)
 //
 // Layout: fixed-capacity rows (row k of atom k in cell order), entries are
 // cell-sorted atom indices. Counts beyond the capacity are still counted, so
@@ -77,12 +77,6 @@ __device__ __forceinline__ uint32_t slab_gap(uint32_t s, int d, int c, const uin
     if (d > 0) return bound[c] - s;
     if (d < 0) return s - (bound[c + 1] - 1u);
     return 0u;
-}
-
-// Coordinate c relative to origin o, in units of 2^sh quanta, as 16 bits.
-__device__ __forceinline__ uint32_t pack_rel(uint32_t c, uint32_t o, int sh)
-{
-    return (uint32_t)(((int32_t)(c - o)) >> sh) & 0xffffu;
 }
 
 // Squared separation of two packed positions (x | y << 16, z): exact in the
@@ -463,31 +457,32 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
 // LDS as above; each lane computes its own cell range in it (row pruning) and
 // the lanes then walk their ranges in lockstep, lane a testing its k-th
 // candidate at step k. A lane appends its shell members (or full-list
-// members) to a ring of 16 entries in LDS and every 8 steps the lanes whose
-// ring holds 8 unwritten entries store them as one aligned 32-byte segment of
-// their list row; core members are stored directly. Candidates between the
-// packed bounds take the exact test on full positions staged beside the
-// packed ones. (In dense cells, such as water's ~13 atoms per cell, the
+// members) to a ring of 8 entries in LDS and every 4 steps the lanes whose
+// ring holds 4 unwritten entries store them as one aligned 16-byte segment of
+// their list row (at most 3 + 4 entries wait in the ring); core members are
+// stored directly. Candidates between the
+// packed bounds take the exact test on full positions read from memory (the
+// LDS footprint, about 4.4 KB, leaves room for the wavefronts that hide the
+// per-row latencies). (In dense cells, such as water's ~13 atoms per cell, the
 // lanes' ranges spread over the staged row and the half-wave form is faster.)
 // ---------------------------------------------------------------------------
-constexpr int kLaneTile = 256;           // staged candidates per pass of a row
-constexpr int kRing = 16;                // ring entries per lane
-constexpr int kSeg = 8;                  // entries per stored segment (32 bytes)
+constexpr int kLaneTile = 128;           // staged candidates per pass of a row
+constexpr int kRing = 8;                 // ring entries per lane
+constexpr int kSeg = 4;                  // entries per stored segment (16 bytes)
 constexpr int kRingStride = kRing + 1;   // words per lane's ring (odd: conflict-free lanes)
 constexpr double kLaneGroupAtoms = 60.0; // atoms per group the launch aims at (at most 64 per pass)
 constexpr double kLaneMaxPerCell = 4.0;  // mean atoms per cell below which the launch takes this form
 
 template <int MODE>
 __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
-    int n_c, int lo, int hi, int G, int sh, uint32_t ox, uint32_t oyz, PackedBounds tb,
-    uint64_t t_core, uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos,
-    const int32_t* __restrict__ smol, const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g,
+    int n_c, int lo, int hi, int G, PackedBounds tb, uint64_t t_core, uint64_t t_lo, uint64_t t_shell, float tfs_hi,
+    const uint4* __restrict__ spos, const u32x4* __restrict__ spk, const int32_t* __restrict__ cell_start,
+    const uint32_t* __restrict__ bound_g,
     int cap_core, int cap_shell, int32_t* __restrict__ core, int32_t* __restrict__ ncore,
     int32_t* __restrict__ shell, int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt,
     uint32_t* __restrict__ err)
 {
     __shared__ u32x4 trec[kLaneTile + 1];          // packed x | y, packed z, exclusion id, sorted index
-    __shared__ uint32_t tfx[kLaneTile], tfy[kLaneTile], tfz[kLaneTile];  // full fixed-point positions
     __shared__ int32_t ring[kListWave * kRingStride];
     __shared__ int32_t tcs[64];                    // union positions of the row's cells (segment A, then B)
     const uint32_t* bound = bound_g;
@@ -504,19 +499,16 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
     const int span_u = gr - 1 + span;           // cells of the union x range
     const int xu0 = wrap(x0 + lo, n_c);         // first cell of the union
     const int lenA = min(span_u, n_c - xu0);    // cells before the wrap
-    const uint32_t orx = bound[x0] + ox, ory = bound[cy] + oyz, orz = bound[cz] + oyz;
     int32_t* const myring = ring + lane * kRingStride;
     int maxc = 0, maxs = 0;
     for (int chunk = a0; chunk < a1; chunk += kListWave) {
         const int k = chunk + lane;
         const bool act = k < a1;
         const uint4 si = act ? spos[k] : make_uint4(0, 0, 0, 0);
-        const int32_t mi = act ? smol[k] : -1;
         const int cx = (int)(((uint64_t)si.x * (uint32_t)n_c) >> 32);
         const int ti = act ? wrap(cx - x0, n_c) : 0;  // lane's home cell in [0, gr)
-        const uint32_t axy = pack_rel(si.x, orx, sh) | (pack_rel(si.y, ory, sh) << 16);
-        const uint32_t az = pack_rel(si.z, orz, sh);
-        const uint32_t amol = (uint32_t)(mi >= 0 ? mi : -2 - k);
+        const u32x4 pk = act ? spk[k] : u32x4{0, 0, 0, 0};  // packed x | y, z, exclusion id
+        const uint32_t axy = pk.x, az = pk.y, amol = pk.z;
         int32_t* const crow = core + (int64_t)k * cap_core;
         int32_t* const srow = shell + (int64_t)k * cap_shell;
         int cc = 0, cs = 0;  // list lengths so far
@@ -569,13 +561,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                     for (int t = lane; t < cnt; t += kListWave) {
                         const int p = base + t;
                         const int j = p < nA ? jA + p : jB + (p - nA);
-                        const uint4 sj = spos[j];
-                        const int32_t mj = smol[j];
-                        trec[t] = u32x4{pack_rel(sj.x, orx, sh) | (pack_rel(sj.y, ory, sh) << 16),
-                                        pack_rel(sj.z, orz, sh), (uint32_t)(mj >= 0 ? mj : -2 - j), (uint32_t)j};
-                        tfx[t] = sj.x;
-                        tfy[t] = sj.y;
-                        tfz[t] = sj.z;
+                        trec[t] = spk[j];
                     }
                     __syncthreads();
                     // this tile's part of the range, in tile positions
@@ -613,9 +599,10 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                         }
                         if (amb) {
                             // between the bounds: the exact test on full positions decides
-                            const int32_t dx = (int32_t)(tfx[tp] - si.x);
-                            const int32_t dy2 = (int32_t)(tfy[tp] - si.y);
-                            const int32_t dz2 = (int32_t)(tfz[tp] - si.z);
+                            const uint4 sj = spos[(int)r.w];
+                            const int32_t dx = (int32_t)(sj.x - si.x);
+                            const int32_t dy2 = (int32_t)(sj.y - si.y);
+                            const int32_t dz2 = (int32_t)(sj.z - si.z);
                             const uint64_t d2x = (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy2 * dy2) +
                                                  (uint64_t)((int64_t)dz2 * dz2);
                             in_core = MODE != kListsFull && d2x <= t_core;
@@ -631,14 +618,11 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                             ++cc;
                         }
                         if (MODE != kListsCoreOnly && (st & (kSeg - 1)) == kSeg - 1) {
-                            // lanes with a full segment store it (at most one per 8 steps)
+                            // lanes with a full segment store it (at most one per kSeg steps)
                             if (cs - fs >= kSeg) {
                                 const int o = fs & (kRing - 1);
-                                if (fs + kSeg <= cap_shell) {
-                                    int4* dst = (int4*)(srow + fs);
-                                    dst[0] = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
-                                    dst[1] = make_int4(myring[o + 4], myring[o + 5], myring[o + 6], myring[o + 7]);
-                                }
+                                if (fs + kSeg <= cap_shell)
+                                    *(int4*)(srow + fs) = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
                                 fs += kSeg;
                             }
                         }
@@ -647,11 +631,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                         // at most one full segment waits after the last step
                         if (cs - fs >= kSeg) {
                             const int o = fs & (kRing - 1);
-                            if (fs + kSeg <= cap_shell) {
-                                int4* dst = (int4*)(srow + fs);
-                                dst[0] = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
-                                dst[1] = make_int4(myring[o + 4], myring[o + 5], myring[o + 6], myring[o + 7]);
-                            }
+                            if (fs + kSeg <= cap_shell)
+                                *(int4*)(srow + fs) = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
                             fs += kSeg;
                         }
                     }
@@ -742,10 +723,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_sorted(int64_t n, int sh, int e
 namespace {
 
 // Shift s and bounds of the packed candidate test. With a pruned stencil
-// every relative coordinate of a wavefront lies within
-// max(R + G/2, R + 1) cell edges (+ rounding) of its origin; s is the
-// smallest shift that fits that in 16 signed bits with two units to spare,
-// and each packed component is then off by less than delta = 1 unit. When
+// every separation a lane tests (an atom and a candidate of its own stencil)
+// lies within R + 1 cell edges (+ rounding) per axis; s is the smallest shift
+// that fits that in 16 signed bits with two units to spare, so the 16-bit
+// differences of the packed global coordinates are exact modulo 2^16, and each
+// packed component is off by less than delta = 1 unit. When
 // the stencil wraps the box, the top 16 bits of the coordinates are used
 // (s = 16, modular differences, delta = 3).
 // With e = sum of component errors: D <= d2 + 2 delta sqrt(3 d2) + 3 delta^2
@@ -757,25 +739,22 @@ namespace {
 // exact test).
 struct PackedGeometry {
     int sh = 16;
-    uint32_t ox = 0, oyz = 0;
     PackedBounds tb{};
     MidBounds mb{};
     int e = 0;
 };
 
-PackedGeometry packed_geometry(const Geometry& g, int G, bool prune)
+PackedGeometry packed_geometry(const Geometry& g, bool prune)
 {
     PackedGeometry p;
     const double E = 4294967296.0 / (double)g.n_c;
     double delta = 3.0;
     if (prune) {
-        const double M = std::max(g.reach + 0.5 * G, g.reach + 1.0) * E + 4.0;
+        const double M = (g.reach + 1.0) * E + 4.0;
         for (int s = 0; s <= 15; ++s) {
             if (M <= std::ldexp(1.0, 15 + s) - std::ldexp(1.0, s + 1)) {
                 p.sh = s;
                 delta = 1.0;
-                p.ox = (uint32_t)(0.5 * G * E);
-                p.oyz = (uint32_t)(0.5 * E);
                 break;
             }
         }
@@ -853,7 +832,7 @@ hipError_t launch_build_lists(irbe_ctx* h)
     const int G = (n_c + groups_per_row - 1) / groups_per_row;
     const int prune = narrow ? 1 : 0;
     const int64_t groups = (int64_t)n_c * n_c * ((n_c + G - 1) / G);
-    const PackedGeometry pg = packed_geometry(g, G, narrow);
+    const PackedGeometry pg = packed_geometry(g, narrow);
     // packed x is monotone along a cell only when no relative coordinate wraps
     const int trim = narrow && pg.sh < 16 ? 1 : 0;
     // FP32 threshold of the outermost list with a relative margin of 2e-6, far
@@ -864,10 +843,15 @@ hipError_t launch_build_lists(irbe_ctx* h)
         (const u32x4*)h->spk, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,  \
         h->nshell, h->maxcnt, h->err
 #define IRBE_LANES_ARGS                                                                                            \
-    n_c, g.lo, g.hi, G, pg.sh, pg.ox, pg.oyz, pg.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi,                       \
-        h->spos, h->smol, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,     \
-        h->nshell, h->maxcnt, h->err
+    n_c, g.lo, g.hi, G, pl.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos, (const u32x4*)h->spk, h->cell_start, \
+        h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt, h->err
     if (lanes) {
+        // the packed records as for one cell per group: only a lane's own candidates
+        // (within the stencil of its cell) are tested, so 16-bit differences of the
+        // global coordinates are exact
+        const PackedGeometry pl = packed_geometry(g, true);
+        k_pack_sorted<<<(unsigned)blocks_for(h->cfg.n_atoms, kBlock), kBlock, 0, h->stream>>>(
+            h->cfg.n_atoms, pl.sh, pl.e, h->spos, h->smol, (u32x4*)h->spk);
         if (h->full_list)
             k_build_lists_lanes<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LANES_ARGS);
         else if (h->stencil)
