@@ -548,22 +548,38 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                 const int lenB = span_u - lenA;
                 const int jB = cell_start[row];
                 const int total = nA + (lenB > 0 ? cell_start[row + lenB] - jB : 0);
+                // the row's cell starts and its first tile's records, loaded together
+                // (one memory round trip per row)
+                const int cst_l = lane <= span_u ? (lane < lenA ? cell_start[row + xu0 + lane] - jA
+                                                                : nA + cell_start[row + lane - lenA] - jB)
+                                                 : 0;
+                const int cnt0 = min(kLaneTile, total);
+                u32x4 rec[kLaneTile / kListWave];
+#pragma unroll
+                for (int h = 0; h < kLaneTile / kListWave; ++h) {
+                    const int t = h * kListWave + lane;
+                    rec[h] = t < cnt0 ? spk[t < nA ? jA + t : jB + (t - nA)] : u32x4{0, 0, 0, 0};
+                }
                 __syncthreads();  // the previous row's tables are no longer read
-                if (lane <= span_u)
-                    tcs[lane] = lane < lenA ? cell_start[row + xu0 + lane] - jA
-                                            : nA + cell_start[row + lane - lenA] - jB;
+                if (lane <= span_u) tcs[lane] = cst_l;
+#pragma unroll
+                for (int h = 0; h < kLaneTile / kListWave; ++h)
+                    if (h * kListWave + lane < cnt0) trec[h * kListWave + lane] = rec[h];
                 __syncthreads();
                 const int p_lo = need ? tcs[u_lo] : 0;
                 const int p_hi = need ? tcs[u_hi + 1] : 0;
                 for (int base = 0; base < total; base += kLaneTile) {
                     const int cnt = min(kLaneTile, total - base);
-                    if (base > 0) __syncthreads();
-                    for (int t = lane; t < cnt; t += kListWave) {
-                        const int p = base + t;
-                        const int j = p < nA ? jA + p : jB + (p - nA);
-                        trec[t] = spk[j];
+                    if (base > 0) {
+                        // a row longer than one tile (crowded cells): its later tiles
+                        __syncthreads();
+                        for (int t = lane; t < cnt; t += kListWave) {
+                            const int p = base + t;
+                            const int j = p < nA ? jA + p : jB + (p - nA);
+                            trec[t] = spk[j];
+                        }
+                        __syncthreads();
                     }
-                    __syncthreads();
                     // this tile's part of the range, in tile positions
                     const int s0 = need ? max(p_lo, base) - base : 0;
                     const int len = need ? max(min(p_hi, base + cnt) - base - s0, 0) : 0;
