@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the headline forward figure")
     ap.add_argument("--with-backward", action="store_true",
                     help="with --no-extras: also run the forward+backward steps once (for profiles)")
+    ap.add_argument("--electrolyte", type=int, default=0,
+                    help="only the electrolyte comparison at this many ions (one JSON line; for profiles)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (reference for the HBM byte counters of a profile)")
     return ap.parse_args()
@@ -357,7 +359,7 @@ def skin_lists(make, pos, G, w, args, ms_full, timed_steps, every=10):
     return out
 
 
-def electrolyte_scaling(timed_steps):
+def electrolyte_scaling(timed_steps, sizes=(1_000_000, 10_000_000)):
     """The 1:1 primitive-model electrolyte of the paper's scaling runs (density
     0.01 sigma^-3, reduced units, shifted-truncated LJ, alpha = 0.03, p = 100,
     r_c = 15) at 10^6 and 10^7 ions: forward step time of RBL+RBE (r_core = 5,
@@ -368,7 +370,7 @@ def electrolyte_scaling(timed_steps):
     from paper_2204_13595_amd import inputs, irbe
     dev = torch.device("cuda", 0)
     out = {}
-    for n in (1_000_000, 10_000_000):
+    for n in sizes:
         box = (n / 0.01) ** (1.0 / 3.0)
         w = inputs.electrolyte(1, n_anions=n // 2, box=box)
         pos = torch.tensor(w.pos, dtype=torch.float32, device=dev)
@@ -457,6 +459,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.electrolyte:
+        log(f"electrolyte comparison at {args.electrolyte} ions")
+        print(json.dumps({"electrolyte": electrolyte_scaling(timed_steps, (args.electrolyte,))}), flush=True)
+        return
     log(f"generating {args.workload}")
     w = inputs.workload(args.workload)
     n = w.n_atoms
