@@ -183,6 +183,68 @@ __device__ __forceinline__ void floyd_row(int64_t k, int ns, const int32_t* __re
     for (; c < p_shell; ++c) out[c] = (uint16_t)floyd_step(st, bits, stride, t0 + c);
 }
 
+// The same ranks, four steps at a time, for bitmaps in LDS. The four words of
+// one Philox block serve steps c .. c+3. Unless a lane's multiply-shift needs
+// its rejection test (low product word below the bound: about one draw in
+// 10^7), the four draws r are then known before any bitmap access, and their
+// membership tests go to LDS together as test-and-set operations, which return
+// each word as it was before their own bit was set: r is taken when its bit was
+// already set, or when it equals the t of an earlier step of the four that was
+// taken (that t is inserted only after the four). A free r is inserted by its
+// own test-and-set. From the first block in which some lane of the wavefront
+// needs the rejection test, and for the steps after the last full block, the
+// one-step form continues with the same word stream.
+__device__ __forceinline__ void floyd_row_lds(int64_t k, int ns, const int32_t* __restrict__ perm, int p_shell,
+                                              int p_stride, uint64_t seed, uint64_t step, uint32_t* bits, int stride,
+                                              uint16_t* __restrict__ ranks)
+{
+    const int words = (ns + 31) >> 5;
+    for (int t = 0; t < words; ++t) bits[t * stride] = 0u;
+    WordStream st(seed, step, (uint32_t)perm[k], kTagShell);
+    uint16_t* out = ranks + k * (int64_t)p_stride;
+    const int t0 = ns - p_shell;
+    int c = 0;
+    for (; c + 4 <= p_shell; c += 4) {
+        const Words4 b = philox10(st.c0, st.block, st.c2, st.c3, st.k0, st.k1);
+        const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+        uint32_t r[4];
+        bool hard = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t bound = (uint32_t)(t0 + c + j) + 1u;
+            const uint64_t m = (uint64_t)w[j] * bound;
+            hard |= (uint32_t)m < bound;
+            r[j] = (uint32_t)(m >> 32);
+        }
+        if (__builtin_amdgcn_ballot_w64(hard) != 0) break;  // this block again, one step at a time
+        ++st.block;
+        uint32_t old[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            old[j] = __hip_atomic_fetch_or(&bits[(r[j] >> 5) * stride], 1u << (r[j] & 31), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+        uint32_t v[4];
+        bool taken[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t t = (uint32_t)(t0 + c + j);
+            bool tk = (old[j] >> (r[j] & 31)) & 1u;
+#pragma unroll
+            for (int i = 0; i < j; ++i) tk |= taken[i] && r[j] == t - (uint32_t)(j - i);
+            taken[j] = tk;
+            v[j] = tk ? t : r[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t t = (uint32_t)(t0 + c + j);
+            __hip_atomic_fetch_or(&bits[(t >> 5) * stride], taken[j] ? 1u << (t & 31) : 0u, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+        *(uint2*)(out + c) = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+    }
+    for (; c < p_shell; ++c) out[c] = (uint16_t)floyd_step(st, bits, stride, t0 + c);
+}
+
 // ---------------------------------------------------------------------------
 // Forward, cooperative form: the shell batch ranks are drawn first (one thread
 // per atom, Floyd's algorithm into a row of 16-bit ranks), then one wavefront
@@ -202,7 +264,7 @@ __global__ __launch_bounds__(BLOCK) void k_draw_batches(int64_t n, const int32_t
     if (k >= n) return;
     const int ns = nshell[k];
     if (ns <= p_shell) return;
-    floyd_row(k, ns, perm, p_shell, p_stride, seed, step, bitmap + threadIdx.x, BLOCK, ranks);
+    floyd_row_lds(k, ns, perm, p_shell, p_stride, seed, step, bitmap + threadIdx.x, BLOCK, ranks);
 }
 
 // The same with the bitmaps in device memory, for lists too long for LDS: a

@@ -91,6 +91,32 @@ def test_batches_and_kvectors_bit_exact(orc, step):
     h.close()
 
 
+def test_batches_with_rejected_draws_bit_exact(orc):
+    """Step 17 of water4k (seed 13595), where two atoms' Floyd draws meet the
+    rejection of the bounded multiply-shift (low product word below
+    2^32 mod bound, about one draw in 10^7): the draw kernel hands such blocks
+    to its one-step form. Every atom's batch against the oracle."""
+    w = inputs.workload("water4k")
+    step = 17
+    h, pos, q, pos_np, q_np = _setup(w, "mixed")
+    h.build_lists(pos, step)
+    h.compute_forces(pos, step)
+    p = _oracle_params(orc, w)
+    s = orc.quantize(pos_np, w.box)
+    lists = orc.build_lists(s, w.molecule, w.box, 0.5, 1.2)
+    ns = np.diff(lists.shell_off)
+    # (atom, Floyd step) whose word is rejected: the first rejection of each atom's stream,
+    # so the step's word is word c of the stream (block c // 4 of the generator)
+    for atom, c in [(5699, 1), (8234, 82)]:
+        bound = int(ns[atom]) - p.p_shell + c + 1
+        word = int(orc.philox4x32_10([atom, c // 4, step, 0], [p.seed & 0xffffffff, p.seed >> 32])[c % 4])
+        assert (word * bound) % 2 ** 32 < (2 ** 32 - bound) % bound
+    b_off, b_rank, _ = orc.shell_batches(p.seed, step, lists, p.p_shell)
+    assert np.array_equal(h.debug("batch_off"), b_off)
+    assert np.array_equal(h.debug("batch_rank"), b_rank)
+    h.close()
+
+
 @pytest.mark.parametrize("precision,p_shell,tol_f,tol_e", [("fp64", 100, 1e-11, 1e-10), ("fp64", 0, 1e-11, 1e-10),
                                                             ("mixed", 100, 1e-5, 2e-5), ("mixed", 0, 1e-5, 2e-5)])
 @pytest.mark.parametrize("name", ["water512", "water4k"])
