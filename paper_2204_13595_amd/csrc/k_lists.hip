@@ -454,7 +454,11 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
 // so a half-wave per atom and row idles most of its lanes; here one wavefront
 // takes up to 64 atoms of consecutive cells of one cell row, one atom per lane.
 // For every stencil row (dz, dy) the union of the atoms' x ranges is staged in
-// LDS as above; each lane computes its own cell range in it (row pruning) and
+// LDS as above. The first atom and atom count of every row's union (two index
+// ranges at most) are loaded once per group into a table held in registers,
+// so that a row's cell starts and the records of its first tile are loaded in
+// one memory round trip, issued before the pruning of the rows that follow.
+// Each lane computes its own cell range in the union (row pruning) and
 // the lanes then walk their ranges in lockstep, lane a testing its k-th
 // candidate at step k. A lane appends its shell members (or full-list
 // members) to a ring of 8 entries in LDS and every 4 steps the lanes whose
@@ -472,6 +476,15 @@ constexpr int kSeg = 4;                  // entries per stored segment (16 bytes
 constexpr int kRingStride = kRing + 1;   // words per lane's ring (odd: conflict-free lanes)
 constexpr double kLaneGroupAtoms = 60.0; // atoms per group the launch aims at (at most 64 per pass)
 constexpr double kLaneMaxPerCell = 4.0;  // mean atoms per cell below which the launch takes this form
+
+// A stencil row of the lane-per-atom kernel as loaded: its union's two segments
+// (first atom and atoms of A; first atom of B; atoms of both), this lane's raw
+// cell start in the union and the records of its first tile.
+struct RowLoad {
+    int jA, nA, jB, total;
+    int cst;
+    u32x4 rec[kLaneTile / kListWave];
+};
 
 template <int MODE>
 __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
@@ -500,6 +513,46 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
     const int xu0 = wrap(x0 + lo, n_c);         // first cell of the union
     const int lenA = min(span_u, n_c - xu0);    // cells before the wrap
     int32_t* const myring = ring + lane * kRingStride;
+    // every stencil row's union: first atom and atom count of segment A (cells
+    // xu0 .. xu0 + lenA - 1) and of segment B (cells 0 .. lenB - 1, past the wrap),
+    // row ri = (dz, dy) = (lo + ri / span, lo + ri % span) in lane ri % 64 of
+    // rtab[ri / 64], loaded once for the group
+    const int nrows = span * span;  // at most 2 * kListWave (checked at the launch)
+    const int lenB = span_u - lenA;
+    int4 rtab[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ri = h * kListWave + lane;
+        rtab[h] = make_int4(0, 0, 0, 0);
+        if (ri < nrows) {
+            const int row = (wrap(cz + lo + ri / span, n_c) * n_c + wrap(cy + lo + ri % span, n_c)) * n_c;
+            const int ja = cell_start[row + xu0], jb = cell_start[row];
+            rtab[h] = make_int4(ja, cell_start[row + xu0 + lenA] - ja, jb, lenB > 0 ? cell_start[row + lenB] - jb : 0);
+        }
+    }
+    // a row's union from the table, this lane's cell start in it and the records of
+    // its first tile, issued together (one memory round trip)
+    auto row_load = [&](int ri) __attribute__((always_inline)) {
+        RowLoad d;
+        const int h = ri >> 6, rl = ri & (kListWave - 1);
+        d.jA = __builtin_amdgcn_readlane(h ? rtab[1].x : rtab[0].x, rl);
+        d.nA = __builtin_amdgcn_readlane(h ? rtab[1].y : rtab[0].y, rl);
+        d.jB = __builtin_amdgcn_readlane(h ? rtab[1].z : rtab[0].z, rl);
+        d.total = d.nA + __builtin_amdgcn_readlane(h ? rtab[1].w : rtab[0].w, rl);
+        const int row = (wrap(cz + lo + ri / span, n_c) * n_c + wrap(cy + lo + ri % span, n_c)) * n_c;
+        // (every lane loads, from an index inside the arrays, so that no load sits
+        // in a branch and the waits for these registers can be counted exactly;
+        // lanes past the union or the tile do not use theirs)
+        const int lc = min(lane, span_u);
+        d.cst = cell_start[lc < lenA ? row + xu0 + lc : row + lc - lenA];
+        const int cnt0 = min(kLaneTile, d.total);
+#pragma unroll
+        for (int q = 0; q < kLaneTile / kListWave; ++q) {
+            const int t = q * kListWave + lane;
+            d.rec[q] = spk[t < cnt0 ? (t < d.nA ? d.jA + t : d.jB + (t - d.nA)) : a0];
+        }
+        return d;
+    };
     int maxc = 0, maxs = 0;
     for (int chunk = a0; chunk < a1; chunk += kListWave) {
         const int k = chunk + lane;
@@ -513,19 +566,18 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
         int32_t* const srow = shell + (int64_t)k * cap_shell;
         int cc = 0, cs = 0;  // list lengths so far
         int fs = 0;          // shell entries already stored (a multiple of kSeg)
-        for (int dz = lo; dz <= hi; ++dz) {
-            const int z = wrap(cz + dz, n_c);
-            const float gz = (float)slab_gap(si.z, dz, z, bound);
-            for (int dy = lo; dy <= hi; ++dy) {
-                const int y = wrap(cy + dy, n_c);
-                const int row = (z * n_c + y) * n_c;
-                const bool core_row = MODE != kListsFull && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
-                if (MODE == kListsCoreOnly && !core_row) continue;
-                // the lane's range: cells [u_lo, u_hi] of the union, pruned by the row gap
-                int u_lo = ti, u_hi = ti + span - 1;
-                bool need = act;
+        // the lane's range in row ri: cells [u_lo, u_hi] of the union, pruned by the
+        // row gap; the first row at or after ri that some lane needs (nrows: none)
+        auto next_row = [&](int ri, int& u_lo, int& u_hi, bool& need) __attribute__((always_inline)) -> int {
+            for (; ri < nrows; ++ri) {
+                const int dz = lo + ri / span, dy = lo + ri % span;
+                if (MODE == kListsCoreOnly && (dz < -1 || dz > 1 || dy < -1 || dy > 1)) continue;
+                u_lo = ti;
+                u_hi = ti + span - 1;
+                need = act;
                 if (act) {
-                    const float gy = (float)slab_gap(si.y, dy, y, bound);
+                    const float gz = (float)slab_gap(si.z, dz, wrap(cz + dz, n_c), bound);
+                    const float gy = (float)slab_gap(si.y, dy, wrap(cy + dy, n_c), bound);
                     const float rem = tfs_hi - gy * gy - gz * gz;
                     if (rem < 0.0f) {
                         need = false;
@@ -542,109 +594,98 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                         u_hi = ti + (min(oh, hi) - lo);
                     }
                 }
-                if (ballot(need) == 0) continue;
-                const int jA = cell_start[row + xu0];
-                const int nA = cell_start[row + xu0 + lenA] - jA;
-                const int lenB = span_u - lenA;
-                const int jB = cell_start[row];
-                const int total = nA + (lenB > 0 ? cell_start[row + lenB] - jB : 0);
-                // the row's cell starts and its first tile's records, loaded together
-                // (one memory round trip per row)
-                const int cst_l = lane <= span_u ? (lane < lenA ? cell_start[row + xu0 + lane] - jA
-                                                                : nA + cell_start[row + lane - lenA] - jB)
-                                                 : 0;
-                const int cnt0 = min(kLaneTile, total);
-                u32x4 rec[kLaneTile / kListWave];
+                if (ballot(need) != 0) return ri;
+            }
+            return nrows;
+        };
+        int u_lo = 0, u_hi = 0;
+        bool need = false;
+        int rc = next_row(0, u_lo, u_hi, need);
+        while (rc < nrows) {
+            // the row's loads are in flight while the next needed row is found
+            const RowLoad cur = row_load(rc);
+            int u_lo_n = 0, u_hi_n = 0;
+            bool need_n = false;
+            const int rn = next_row(rc + 1, u_lo_n, u_hi_n, need_n);
+            const int dz = lo + rc / span, dy = lo + rc % span;
+            const bool core_row = MODE != kListsFull && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
+            const int jA = cur.jA, nA = cur.nA, jB = cur.jB, total = cur.total;
+            // (LDS accesses of the one wavefront of the workgroup take effect in
+            // order: the previous row's reads precede these writes)
+            if (lane <= span_u) tcs[lane] = cur.cst - (lane < lenA ? jA : jB - nA);
 #pragma unroll
-                for (int h = 0; h < kLaneTile / kListWave; ++h) {
-                    const int t = h * kListWave + lane;
-                    rec[h] = t < cnt0 ? spk[t < nA ? jA + t : jB + (t - nA)] : u32x4{0, 0, 0, 0};
+            for (int h = 0; h < kLaneTile / kListWave; ++h)
+                if (h * kListWave + lane < min(kLaneTile, total)) trec[h * kListWave + lane] = cur.rec[h];
+            asm volatile("" ::: "memory");
+            const int p_lo = need ? tcs[u_lo] : 0;
+            const int p_hi = need ? tcs[u_hi + 1] : 0;
+            for (int base = 0; base < total; base += kLaneTile) {
+                const int cnt = min(kLaneTile, total - base);
+                if (base > 0) {
+                    // a row longer than one tile (crowded cells): its later tiles
+                    __syncthreads();
+                    for (int t = lane; t < cnt; t += kListWave) {
+                        const int p = base + t;
+                        const int j = p < nA ? jA + p : jB + (p - nA);
+                        trec[t] = spk[j];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();  // the previous row's tables are no longer read
-                if (lane <= span_u) tcs[lane] = cst_l;
+                // this tile's part of the range, in tile positions
+                const int s0 = need ? max(p_lo, base) - base : 0;
+                const int len = need ? max(min(p_hi, base + cnt) - base - s0, 0) : 0;
+                int steps = len;
 #pragma unroll
-                for (int h = 0; h < kLaneTile / kListWave; ++h)
-                    if (h * kListWave + lane < cnt0) trec[h * kListWave + lane] = rec[h];
-                __syncthreads();
-                const int p_lo = need ? tcs[u_lo] : 0;
-                const int p_hi = need ? tcs[u_hi + 1] : 0;
-                for (int base = 0; base < total; base += kLaneTile) {
-                    const int cnt = min(kLaneTile, total - base);
-                    if (base > 0) {
-                        // a row longer than one tile (crowded cells): its later tiles
-                        __syncthreads();
-                        for (int t = lane; t < cnt; t += kListWave) {
-                            const int p = base + t;
-                            const int j = p < nA ? jA + p : jB + (p - nA);
-                            trec[t] = spk[j];
-                        }
-                        __syncthreads();
+                for (int off = 32; off > 0; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
+                for (int st = 0; st < steps; ++st) {
+                    const bool k_in = st < len;
+                    const int tp = k_in ? s0 + st : kLaneTile;
+                    const u32x4 r = trec[tp];
+                    const uint32_t d2 = d2_packed(r.x, r.y, axy, az);
+                    const bool keep = k_in && r.z != amol;
+                    bool in_core = false, in_shell = false, amb;
+                    if (MODE == kListsCoreOnly) {
+                        in_core = keep && d2 < tb.core_in;
+                        amb = keep && !in_core && d2 <= tb.core_out;
+                    } else if (MODE == kListsSplitSkin) {
+                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
+                        const bool l_in = d2 < tb.lo_in, l_out = d2 > tb.lo_out;
+                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
+                        in_core = keep && c_in;
+                        in_shell = keep && l_out && s_in;
+                        amb = keep && !((c_in || c_out) && (l_in || (l_out && s_in) || s_out));
+                    } else if (MODE == kListsSplit) {
+                        const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
+                        const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
+                        in_core = keep && c_in;
+                        in_shell = keep && c_out && s_in;
+                        amb = keep && !c_in && !in_shell && !s_out;
+                    } else {
+                        in_shell = keep && d2 < tb.shell_in;
+                        amb = keep && !in_shell && d2 <= tb.shell_out;
                     }
-                    // this tile's part of the range, in tile positions
-                    const int s0 = need ? max(p_lo, base) - base : 0;
-                    const int len = need ? max(min(p_hi, base + cnt) - base - s0, 0) : 0;
-                    int steps = len;
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
-                    for (int st = 0; st < steps; ++st) {
-                        const bool k_in = st < len;
-                        const int tp = k_in ? s0 + st : kLaneTile;
-                        const u32x4 r = trec[tp];
-                        const uint32_t d2 = d2_packed(r.x, r.y, axy, az);
-                        const bool keep = k_in && r.z != amol;
-                        bool in_core = false, in_shell = false, amb;
-                        if (MODE == kListsCoreOnly) {
-                            in_core = keep && d2 < tb.core_in;
-                            amb = keep && !in_core && d2 <= tb.core_out;
-                        } else if (MODE == kListsSplitSkin) {
-                            const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
-                            const bool l_in = d2 < tb.lo_in, l_out = d2 > tb.lo_out;
-                            const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
-                            in_core = keep && c_in;
-                            in_shell = keep && l_out && s_in;
-                            amb = keep && !((c_in || c_out) && (l_in || (l_out && s_in) || s_out));
-                        } else if (MODE == kListsSplit) {
-                            const bool c_in = d2 < tb.core_in, c_out = d2 > tb.core_out;
-                            const bool s_in = d2 < tb.shell_in, s_out = d2 > tb.shell_out;
-                            in_core = keep && c_in;
-                            in_shell = keep && c_out && s_in;
-                            amb = keep && !c_in && !in_shell && !s_out;
-                        } else {
-                            in_shell = keep && d2 < tb.shell_in;
-                            amb = keep && !in_shell && d2 <= tb.shell_out;
-                        }
-                        if (amb) {
-                            // between the bounds: the exact test on full positions decides
-                            const uint4 sj = spos[(int)r.w];
-                            const int32_t dx = (int32_t)(sj.x - si.x);
-                            const int32_t dy2 = (int32_t)(sj.y - si.y);
-                            const int32_t dz2 = (int32_t)(sj.z - si.z);
-                            const uint64_t d2x = (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy2 * dy2) +
-                                                 (uint64_t)((int64_t)dz2 * dz2);
-                            in_core = MODE != kListsFull && d2x <= t_core;
-                            in_shell = MODE != kListsCoreOnly &&
-                                       (MODE == kListsSplitSkin ? d2x > t_lo : !in_core) && d2x <= t_shell;
-                        }
-                        if (MODE != kListsCoreOnly && in_shell) {
-                            myring[cs & (kRing - 1)] = (int32_t)r.w;
-                            ++cs;
-                        }
-                        if (MODE != kListsFull && core_row && in_core) {
-                            if (cc < cap_core) crow[cc] = (int32_t)r.w;
-                            ++cc;
-                        }
-                        if (MODE != kListsCoreOnly && (st & (kSeg - 1)) == kSeg - 1) {
-                            // lanes with a full segment store it (at most one per kSeg steps)
-                            if (cs - fs >= kSeg) {
-                                const int o = fs & (kRing - 1);
-                                if (fs + kSeg <= cap_shell)
-                                    *(int4*)(srow + fs) = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
-                                fs += kSeg;
-                            }
-                        }
+                    if (amb) {
+                        // between the bounds: the exact test on full positions decides
+                        const uint4 sj = spos[(int)r.w];
+                        const int32_t dx = (int32_t)(sj.x - si.x);
+                        const int32_t dy2 = (int32_t)(sj.y - si.y);
+                        const int32_t dz2 = (int32_t)(sj.z - si.z);
+                        const uint64_t d2x = (uint64_t)((int64_t)dx * dx) + (uint64_t)((int64_t)dy2 * dy2) +
+                                             (uint64_t)((int64_t)dz2 * dz2);
+                        in_core = MODE != kListsFull && d2x <= t_core;
+                        in_shell = MODE != kListsCoreOnly &&
+                                   (MODE == kListsSplitSkin ? d2x > t_lo : !in_core) && d2x <= t_shell;
                     }
-                    if (MODE != kListsCoreOnly) {
-                        // at most one full segment waits after the last step
+                    if (MODE != kListsCoreOnly && in_shell) {
+                        myring[cs & (kRing - 1)] = (int32_t)r.w;
+                        ++cs;
+                    }
+                    if (MODE != kListsFull && core_row && in_core) {
+                        if (cc < cap_core) crow[cc] = (int32_t)r.w;
+                        ++cc;
+                    }
+                    if (MODE != kListsCoreOnly && (st & (kSeg - 1)) == kSeg - 1) {
+                        // lanes with a full segment store it (at most one per kSeg steps)
                         if (cs - fs >= kSeg) {
                             const int o = fs & (kRing - 1);
                             if (fs + kSeg <= cap_shell)
@@ -653,7 +694,20 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                         }
                     }
                 }
+                if (MODE != kListsCoreOnly) {
+                    // at most one full segment waits after the last step
+                    if (cs - fs >= kSeg) {
+                        const int o = fs & (kRing - 1);
+                        if (fs + kSeg <= cap_shell)
+                            *(int4*)(srow + fs) = make_int4(myring[o], myring[o + 1], myring[o + 2], myring[o + 3]);
+                        fs += kSeg;
+                    }
+                }
             }
+            rc = rn;
+            u_lo = u_lo_n;
+            u_hi = u_hi_n;
+            need = need_n;
         }
         if (MODE != kListsCoreOnly) {
             // the last, partial segment
@@ -835,7 +889,8 @@ hipError_t launch_build_lists(irbe_ctx* h)
     const double per_cell = (double)h->cfg.n_atoms / (double)g.n_cells;
     // dilute cells take the lane-per-atom kernel (up to 64 atoms per pass of its
     // wavefront, its groups aiming at kLaneGroupAtoms)
-    const bool lanes = narrow && per_cell < kLaneMaxPerCell;
+    const int span = g.hi - g.lo + 1;
+    const bool lanes = narrow && per_cell < kLaneMaxPerCell && span * span <= 2 * kListWave;
     const double g_atoms = lanes ? kLaneGroupAtoms : (h->stencil ? 76.0 : 40.0);
     const double g_min = lanes ? 1.0 : (h->stencil ? 6.0 : 3.0);
     const int g_want = (int)std::lround(std::min(64.0, std::max(g_min, g_atoms / std::max(per_cell, 0.75))));
