@@ -84,7 +84,24 @@ __global__ __launch_bounds__(kBlock) void k_quantize_hist(int64_t n, const real*
     const uint32_t sz = quantize1((double)pos[3 * i + 2], inv_l, bad);
     const uint32_t cell = (cell_coord(sz, n_c) * (uint32_t)n_c + cell_coord(sy, n_c)) * (uint32_t)n_c + cell_coord(sx, n_c);
     sq[i] = make_uint4(sx, sy, sz, cell);
-    slot[i] = atomicAdd(&cell_count[cell], 1);  // the atom's place among its cell's atoms
+    // the atom's place among its cell's atoms (any order: each cell is sorted later).
+    // Consecutive lanes in one cell (a molecule's atoms, neighbouring molecules of an
+    // ordered input) form a run whose first lane takes the run's places with one
+    // atomic; the active lanes of a wavefront are a prefix of it.
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t prev = (uint32_t)__shfl_up((int)cell, 1, 64);
+    const bool head = lane == 0 || prev != cell;
+    const uint64_t heads = __builtin_amdgcn_ballot_w64(head);
+    const uint64_t active = __builtin_amdgcn_ballot_w64(true);
+    const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane (all ones for lane 63)
+    const int first = 63 - __builtin_clzll(heads & upto);
+    int base = 0;
+    if (head) {
+        const uint64_t later = heads & ~upto;
+        const int end = later ? __builtin_ctzll(later) : 64 - __builtin_clzll(active);
+        base = atomicAdd(&cell_count[cell], end - lane);
+    }
+    slot[i] = __shfl(base, first, 64) + (lane - first);
     if (bad) atomicOr(err, ERR_NONFINITE);
 }
 

@@ -532,14 +532,21 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
     }
     // a row's union from the table, this lane's cell start in it and the records of
     // its first tile, issued together (one memory round trip)
-    auto row_load = [&](int ri) __attribute__((always_inline)) {
+    // the row after (dz, dy) in the stencil's lexicographic order
+    auto step_row = [&](int& dz, int& dy) __attribute__((always_inline)) {
+        if (++dy > hi) {
+            dy = lo;
+            ++dz;
+        }
+    };
+    auto row_load = [&](int ri, int dz, int dy) __attribute__((always_inline)) {
         RowLoad d;
         const int h = ri >> 6, rl = ri & (kListWave - 1);
         d.jA = __builtin_amdgcn_readlane(h ? rtab[1].x : rtab[0].x, rl);
         d.nA = __builtin_amdgcn_readlane(h ? rtab[1].y : rtab[0].y, rl);
         d.jB = __builtin_amdgcn_readlane(h ? rtab[1].z : rtab[0].z, rl);
         d.total = d.nA + __builtin_amdgcn_readlane(h ? rtab[1].w : rtab[0].w, rl);
-        const int row = (wrap(cz + lo + ri / span, n_c) * n_c + wrap(cy + lo + ri % span, n_c)) * n_c;
+        const int row = (wrap(cz + dz, n_c) * n_c + wrap(cy + dy, n_c)) * n_c;
         // (every lane loads, from an index inside the arrays, so that no load sits
         // in a branch and the waits for these registers can be counted exactly;
         // lanes past the union or the tile do not use theirs)
@@ -566,11 +573,12 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
         int32_t* const srow = shell + (int64_t)k * cap_shell;
         int cc = 0, cs = 0;  // list lengths so far
         int fs = 0;          // shell entries already stored (a multiple of kSeg)
-        // the lane's range in row ri: cells [u_lo, u_hi] of the union, pruned by the
-        // row gap; the first row at or after ri that some lane needs (nrows: none)
-        auto next_row = [&](int ri, int& u_lo, int& u_hi, bool& need) __attribute__((always_inline)) -> int {
-            for (; ri < nrows; ++ri) {
-                const int dz = lo + ri / span, dy = lo + ri % span;
+        // the lane's range in row ri = (dz, dy): cells [u_lo, u_hi] of the union, pruned by
+        // the row gap; the first row at or after ri that some lane needs (nrows: none),
+        // with (dz, dy) advanced to it
+        auto next_row = [&](int ri, int& dz, int& dy, int& u_lo, int& u_hi, bool& need)
+                            __attribute__((always_inline)) -> int {
+            for (; ri < nrows; ++ri, step_row(dz, dy)) {
                 if (MODE == kListsCoreOnly && (dz < -1 || dz > 1 || dy < -1 || dy > 1)) continue;
                 u_lo = ti;
                 u_hi = ti + span - 1;
@@ -600,14 +608,16 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
         };
         int u_lo = 0, u_hi = 0;
         bool need = false;
-        int rc = next_row(0, u_lo, u_hi, need);
+        int dz = lo, dy = lo;
+        int rc = next_row(0, dz, dy, u_lo, u_hi, need);
         while (rc < nrows) {
             // the row's loads are in flight while the next needed row is found
-            const RowLoad cur = row_load(rc);
+            const RowLoad cur = row_load(rc, dz, dy);
             int u_lo_n = 0, u_hi_n = 0;
             bool need_n = false;
-            const int rn = next_row(rc + 1, u_lo_n, u_hi_n, need_n);
-            const int dz = lo + rc / span, dy = lo + rc % span;
+            int dz_n = dz, dy_n = dy;
+            step_row(dz_n, dy_n);
+            const int rn = next_row(rc + 1, dz_n, dy_n, u_lo_n, u_hi_n, need_n);
             const bool core_row = MODE != kListsFull && dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
             const int jA = cur.jA, nA = cur.nA, jB = cur.jB, total = cur.total;
             // (LDS accesses of the one wavefront of the workgroup take effect in
@@ -705,6 +715,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                 }
             }
             rc = rn;
+            dz = dz_n;
+            dy = dy_n;
             u_lo = u_lo_n;
             u_hi = u_hi_n;
             need = need_n;
