@@ -647,6 +647,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                 int steps = len;
 #pragma unroll
                 for (int off = 32; off > 0; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
+                steps = __builtin_amdgcn_readfirstlane(steps);  // (every lane holds the maximum)
                 for (int st = 0; st < steps; ++st) {
                     const bool k_in = st < len;
                     const int tp = k_in ? s0 + st : kLaneTile;
