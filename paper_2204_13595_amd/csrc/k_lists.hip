@@ -532,6 +532,17 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
     }
     // a row's union from the table, this lane's cell start in it and the records of
     // its first tile, issued together (one memory round trip)
+    // first and last coordinates of the stencil's z and y cell slabs, lane l for the
+    // offset lo + l (span <= 11 here), read back with readlane
+    const int ls = min(lane, span - 1);
+    const int zs = wrap(cz + lo + ls, n_c), ys = wrap(cy + lo + ls, n_c);
+    const uint32_t zlo = bound[zs], zhi = bound[zs + 1] - 1u, ylo = bound[ys], yhi = bound[ys + 1] - 1u;
+    // distance from coordinate s to the slab at offset d (as slab_gap)
+    auto gap = [](uint32_t s, int d, uint32_t lo_t, uint32_t hi_t, int idx) __attribute__((always_inline)) {
+        if (d > 0) return (uint32_t)__builtin_amdgcn_readlane((int)lo_t, idx) - s;
+        if (d < 0) return s - (uint32_t)__builtin_amdgcn_readlane((int)hi_t, idx);
+        return 0u;
+    };
     // the row after (dz, dy) in the stencil's lexicographic order
     auto step_row = [&](int& dz, int& dy) __attribute__((always_inline)) {
         if (++dy > hi) {
@@ -584,8 +595,8 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_lanes(
                 u_hi = ti + span - 1;
                 need = act;
                 if (act) {
-                    const float gz = (float)slab_gap(si.z, dz, wrap(cz + dz, n_c), bound);
-                    const float gy = (float)slab_gap(si.y, dy, wrap(cy + dy, n_c), bound);
+                    const float gz = (float)gap(si.z, dz, zlo, zhi, dz - lo);
+                    const float gy = (float)gap(si.y, dy, ylo, yhi, dy - lo);
                     const float rem = tfs_hi - gy * gy - gz * gz;
                     if (rem < 0.0f) {
                         need = false;
