@@ -183,14 +183,14 @@ __device__ __forceinline__ void classify(D d2, const Bounds<D>& b, uint64_t keep
 
 // One chunk per half-wave: this lane's candidate r (k_in: inside the half's
 // range) against the half's atom ap (packed x | y, packed z with extension
-// bits, exclusion id), atom index k_atom. The packed bounds settle most
+// bits, exclusion id), atom index k_base + k_rel. The packed bounds settle most
 // candidates, the extended coordinates (mid bounds, e bits) nearly all of the
 // rest, and the exact test on positions read from memory the few left.
 // Members are appended to the half's rows (byte offsets hoff_s, hoff_c within
 // the descriptors) after cs and cc, which are advanced; a lane reads its own
 // bit of the member masks back for its store.
 template <int MODE, bool CORE, bool LAST>
-__device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x4& ap, int k_atom,
+__device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x4& ap, int k_base, int k_rel,
                                            const PackedBounds& tb, const MidBounds& mb, int e, uint64_t t_core,
                                            uint64_t t_lo, uint64_t t_shell, const uint4* __restrict__ spos, int lane,
                                            int hsel, uint32_t lowm, int hoff_s, int hoff_c,
@@ -203,12 +203,14 @@ __device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x
     if (__builtin_expect(m_amb != 0, 0)) {
         // between the packed bounds (wave-uniform branch; the lanes of m_amb
         // take its result)
-        // (the atom's operands pass through an empty asm statement, so that the
-        // compiler keeps their unpacking here instead of hoisting it to every
-        // pair's set-up)
-        uint32_t axy = ap.x, az = ap.y;
-        int ki = k_atom;
-        asm volatile("" : "+v"(axy), "+v"(az), "+v"(ki));
+        // (the atom's operands are copied by an asm statement in this branch, so that
+        // the compiler keeps their unpacking, and the copies, here instead of hoisting
+        // them to every pair's set-up)
+        uint32_t axy, az;
+        int ki;
+        asm volatile("v_mov_b32 %0, %3\n\tv_mov_b32 %1, %4\n\tv_add_u32 %2, %5, %6"
+                     : "=&v"(axy), "=&v"(az), "=&v"(ki)
+                     : "v"(ap.x), "v"(ap.y), "s"(k_base), "v"(k_rel));
         uint64_t c2, s2, a2;
         classify<MODE, CORE>(d2_mid(r.x, r.y, axy, az, e), mb, m_amb, c2, s2, a2);
         if (a2 != 0) {
@@ -409,11 +411,16 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                 // the two atoms have the same number of chunks: every lane of
                                 // all chunks but the last lies inside its half's range
                                 const int last = (chunks - 1) * 32;
-                                for (int c0 = 0; c0 < last; c0 += 32)
-                                    scan_chunk<MODE, CORE, false>(trec[qb + c0], true, ap, chunk + ka, tb, mb, e,
-                                                                  t_core, t_lo, t_shell, spos, lane, hsel, lowm,
-                                                                  hoff_s, hoff_c, rs_s, rs_c, cs, cc);
-                                scan_chunk<MODE, CORE, true>(trec[qb + last], last < lenm, ap, chunk + ka, tb, mb, e,
+                                if (chunks > 1) {
+                                    int c0 = 0;
+                                    do {
+                                        scan_chunk<MODE, CORE, false>(trec[qb + c0], true, ap, chunk, ka, tb, mb, e,
+                                                                      t_core, t_lo, t_shell, spos, lane, hsel, lowm,
+                                                                      hoff_s, hoff_c, rs_s, rs_c, cs, cc);
+                                        c0 += 32;
+                                    } while (c0 < last);
+                                }
+                                scan_chunk<MODE, CORE, true>(trec[qb + last], last < lenm, ap, chunk, ka, tb, mb, e,
                                                              t_core, t_lo, t_shell, spos, lane, hsel, lowm, hoff_s,
                                                              hoff_c, rs_s, rs_c, cs, cc);
                             };
