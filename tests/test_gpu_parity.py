@@ -91,6 +91,42 @@ def test_batches_and_kvectors_bit_exact(orc, step):
     h.close()
 
 
+@pytest.mark.parametrize("order", ["by_cell", "one_cell", "shuffled"])
+def test_cell_binning_orders_bit_exact(orc, order):
+    """Cell binning of 1000 atoms (the last wavefront partly filled) in three input
+    orders: sorted by cell (runs of one cell across wavefront boundaries, which take
+    their histogram places together), all in one cell, and shuffled; cell starts and
+    the cell-sorted order against the oracle."""
+    from paper_2204_13595_amd import irbe
+    w = inputs.workload("water4k")
+    n = 1000
+    rng = np.random.default_rng(11)
+    n_c = orc.n_cells(w.box, 0.5)
+    if order == "one_cell":
+        cell = w.box / n_c
+        pos_np = (rng.uniform(0.1, 0.9, (n, 3)) + np.array([3.0, 5.0, 7.0])) * cell
+    else:
+        pos_np = w.pos[rng.choice(w.n_atoms, n, replace=False)]
+        s = orc.quantize(pos_np, w.box)
+        cid = ((s[:, 2].astype(np.uint64) * n_c >> 32) * n_c + (s[:, 1].astype(np.uint64) * n_c >> 32)) * n_c + \
+              (s[:, 0].astype(np.uint64) * n_c >> 32)
+        pos_np = pos_np[np.argsort(cid, kind="stable")] if order == "by_cell" else pos_np
+    dev = torch.device("cuda", 0)
+    h = irbe.Handle(n, w.box, p_shell=100, p_kspace=10, device=dev)
+    pos = torch.tensor(pos_np, dtype=torch.float32, device=dev)
+    h.set_system(torch.tensor(np.arange(n) % 2, dtype=torch.int32, device=dev),
+                 torch.tensor(np.where(np.arange(n) % 2 == 0, 0.5, -0.5), dtype=torch.float32, device=dev),
+                 torch.tensor(np.arange(n), dtype=torch.int32, device=dev), w.lj_sigma, w.lj_eps)
+    h.build_lists(pos, 0)
+    s = orc.quantize(pos.double().cpu().numpy(), w.box)
+    start, atoms = orc.cell_lists(s, n_c)
+    if order == "one_cell":
+        assert np.diff(start).max() == n
+    assert np.array_equal(h.debug("cell_start"), start)
+    assert np.array_equal(h.debug("cell_atoms"), atoms)
+    h.close()
+
+
 def test_batches_with_rejected_draws_bit_exact(orc):
     """Step 17 of water4k (seed 13595), where two atoms' Floyd draws meet the
     rejection of the bounded multiply-shift (low product word below
