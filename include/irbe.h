@@ -183,7 +183,12 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step);
  *   [0] U_coul,short* [1] U_lj* [2] U_long* [3] U_self [4] U_excl
  *   [5..10] W_xx W_yy W_zz W_xy W_xz W_yz,
  * W_ab = sum over pairs of (r_i - r_j)_a f_ij,b plus the k-space term; the
- * starred terms are the estimators matching Eq. (2.3) in expectation. */
+ * starred terms are the estimators matching Eq. (2.3) in expectation.
+ * When the last forward of the handle was followed by a backward, a forward with
+ * list-drawn batches also writes its batch atoms (N x p_shell int32 in a buffer
+ * that backward allocated), which irbe_compute_forces_backward at the same step
+ * reads in place of the ranks and shell rows (results bitwise the same); a forward
+ * not followed by a backward stops this for the next one. */
 irbe_status irbe_compute_forces(irbe_handle h, const void* pos, uint64_t step, void* force, uint32_t flags,
                                 double* energy_virial);
 
@@ -279,7 +284,11 @@ irbe_status irbe_get_timing(irbe_handle h, double* ms_host, int64_t capacity, in
  *                                           (core, shell) of the last build
  *   IRBE_DBG_ADJ_ATOMICS int64 [1]          shell-adjoint records of the last
  *                                           compute_forces_backward added with FP
- *                                           atomics (-1: all of them) */
+ *                                           atomics (-1: all of them)
+ *   IRBE_DBG_ADJ_BATCH   int64 [1]          1 when the last compute_forces_backward
+ *                                           read the batch atoms written by the
+ *                                           forward, 0 when it read the ranks and
+ *                                           the shell rows */
 enum {
     IRBE_DBG_CELL_START = 1,
     IRBE_DBG_CELL_ATOMS = 2,
@@ -295,7 +304,8 @@ enum {
     IRBE_DBG_SCALARS = 12,
     IRBE_DBG_COUNTS = 13,
     IRBE_DBG_BATCH_ATOMS = 14,
-    IRBE_DBG_ADJ_ATOMICS = 15
+    IRBE_DBG_ADJ_ATOMICS = 15,
+    IRBE_DBG_ADJ_BATCH = 16
 };
 irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written);
 

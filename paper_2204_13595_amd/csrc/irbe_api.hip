@@ -848,6 +848,13 @@ irbe_status irbe_compute_forces_backward(irbe_handle h, const void* pos, uint64_
     if (!h->have_lists) return fail(h, IRBE_ESTATE, "backward before irbe_build_lists");
     if (grad_lj && h->cfg.n_types > kMaxTypesGrad)
         return fail(h, IRBE_EUNSUPPORTED, "LJ gradients need n_types <= 4");
+    // a backward that follows a forward: the next forward with list-drawn batches
+    // also writes the batch atoms, for the backward expected after it
+    if (h->fwd_pending && !h->stencil && !h->full_list) {
+        IRBE_TRY(h, ensure_batch_atoms(h), "allocating the batch atoms");
+        h->keep_batch = true;
+    }
+    h->fwd_pending = false;
     IRBE_STAGE(h, IRBE_STAGE_QUANTIZE, launch_requantize(h, pos), "quantize");
     IRBE_STAGE(h, IRBE_STAGE_KSAMPLE, launch_ksample(h, step), "k sampling");
     IRBE_STAGE(h, IRBE_STAGE_GRAD_GATHER, launch_gather_grad(h, grad_force), "gather dL/dF");
@@ -990,6 +997,11 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
             v[1] += b[i];
         }
         copy_out(v, 8, 4);
+        return IRBE_OK;
+    }
+    case IRBE_DBG_ADJ_BATCH: {
+        const int64_t v = h->adj_used_batch ? 1 : 0;
+        copy_out(&v, 8, 1);
         return IRBE_OK;
     }
     case IRBE_DBG_ADJ_ATOMICS: {

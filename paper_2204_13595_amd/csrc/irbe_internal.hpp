@@ -182,9 +182,14 @@ struct irbe_ctx {
     unsigned long long* adj_atomics = nullptr;  // [1] shell-adjoint records of the last backward added by atomics
     bool adj_all_atomic = false;      // the last backward added every shell-adjoint record by atomics
     uint16_t* ranks = nullptr;        // [N * p_stride] shell batch ranks of the current step
-    int32_t* batch_j = nullptr;       // [N * p_stride] stencil sampling: the drawn atoms (sorted index, -1: i or
-                                      // i's molecule), for the adjoint and read-back, allocated on first use
+    int32_t* batch_j = nullptr;       // [N * p_stride] the drawn atoms (sorted index) of the current ranks: with
+                                      // stencil sampling (-1: i or i's molecule) for the adjoint and read-back,
+                                      // with list-drawn batches written by the forward for the backward that
+                                      // follows it; allocated on first use
     bool batch_j_valid = false;       // batch_j holds the decode of the current ranks
+    bool keep_batch = false;          // the next forward writes batch_j (the last forward had a backward)
+    bool fwd_pending = false;         // a forward ran and no backward has followed it yet
+    bool adj_used_batch = false;      // the last backward read batch_j instead of the ranks and shell rows
     int32_t* scell = nullptr;         // [N] stencil sampling: cell of each sorted atom at the last build
     uint32_t* draw_bits = nullptr;    // Floyd bitmaps in device memory for lists too long for LDS
     size_t draw_bits_words = 0;

@@ -484,7 +484,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int32_t* __restrict__ core, const int32_t* __restrict__ ncore, int cap_core,
     const int32_t* __restrict__ shell, const int32_t* __restrict__ nshell, int cap_shell,
     const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, int p_stride, const uint16_t* __restrict__ ranks,
-    StencilArgs sa, uint64_t t_core, uint64_t t_shell, real* __restrict__ fsr, double* __restrict__ part)
+    StencilArgs sa, uint64_t t_core, uint64_t t_shell, real* __restrict__ fsr, double* __restrict__ part,
+    int32_t* __restrict__ bj_out)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -573,6 +574,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         PairSum<real> pc, ps, px;
         const int js0 = STENCIL ? r0 : (r0 >= 0 ? srow[r0] : -1);
         const int js1 = STENCIL ? r1 : (r1 >= 0 ? srow[r1] : -1);
+        if (!STENCIL && !FULL && bj_out) {
+            // the batch atoms, for the backward expected at this step
+            int32_t* o = bj_out + a * (int64_t)p_stride;
+            if (lane < cnt) o[lane] = js0;
+            if (lane + 64 < cnt) o[lane + 64] = js1;
+        }
         const int mi = STENCIL ? bcast(h_mol, t) : 0;
         const int mj0 = STENCIL ? sa.smol[max(js0, 0)] : 0;
         const int mj1 = STENCIL ? sa.smol[max(js1, 0)] : 0;
@@ -648,6 +655,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
                     add_pair<real, EV>(ps, si, qi, sj, qj, ljof(sj), pp);
             } else {
                 const int j = srow[sample ? (int)rrow[c] : c];
+                if (!FULL && bj_out) bj_out[a * (int64_t)p_stride + c] = j;
                 uint4 sj;
                 real qj;
                 at.get(j, sj, qj);
@@ -893,11 +901,15 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     const int64_t waves = blocks_for(n, apw);
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
+    // the batch atoms for the backward, when one followed the last forward (into a
+    // buffer that backward allocated: a forward allocates nothing here)
+    int32_t* bj_out = (!STENCIL && !FULL && h->keep_batch) ? h->batch_j : nullptr;
     k_pair_coop<real, FULL, EV, STENCIL, SKIN><<<nb, kCoopBlock, 0, h->stream>>>(
         n, apw, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
-        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part);
+        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part, bj_out);
     h->pair_nb = nb;
+    if (bj_out) h->batch_j_valid = true;
     return hipGetLastError();
 }
 
@@ -994,7 +1006,11 @@ hipError_t launch_pair_reduce(irbe_ctx* h)
 
 hipError_t launch_pair_forces(irbe_ctx* h, uint64_t step, bool ev)
 {
-    return h->fp64 ? launch_coop_r<double>(h, step, ev) : launch_coop_r<float>(h, step, ev);
+    const hipError_t e = h->fp64 ? launch_coop_r<double>(h, step, ev) : launch_coop_r<float>(h, step, ev);
+    // each forward renews the prediction: a backward after it sets keep_batch again
+    h->keep_batch = false;
+    h->fwd_pending = true;
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -1168,7 +1184,10 @@ __device__ __forceinline__ void scatter_atomic(real* gscat, real* gqscat, int64_
 // One wavefront per atom (cell order), lanes over the atom's lists. BK: the
 // shell scatter goes through the LDS-staged buckets (dynamic LDS: rec_cap
 // records of 4 reals + j + key, then 7 ints per key).
-template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL, bool SKIN>
+// STENCIL: the batch of stencil sampling, decoded (drawn atoms, -1: none); BATCH:
+// the list-drawn batch as the forward wrote it (batch_j), in place of the ranks
+// and the shell rows.
+template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL, bool SKIN, bool BATCH>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const uint4* __restrict__ spq, const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx, const int32_t* __restrict__ core,
@@ -1256,8 +1275,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         const int32_t* srow_sym = FULL ? shell + a * (int64_t)cap_shell : core + a * (int64_t)cap_core;
         // the excluded partners follow the symmetric list (entries nsym .. nsym + nx - 1)
         jc = lane < nsym ? srow_sym[lane] : (lane < nsym + xr.y ? sxidx[xr.x + lane - nsym] : -1);
-        if (STENCIL) {
-            // the decoded batch (atoms, -1 for i itself and i's molecule) in place of ranks
+        if (STENCIL || BATCH) {
+            // the decoded batch (atoms; with stencil sampling -1 for i itself and i's
+            // molecule) in place of ranks
             const int32_t* brow = batch_j + a * (int64_t)p_stride;
             r0 = lane < cnt ? brow[lane] : -1;
             r1 = lane + 64 < cnt ? brow[lane + 64] : -1;
@@ -1388,8 +1408,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         };
         // first pass, every load of the dependent levels issued together (unused
         // slots load atom 0)
-        const int js0 = STENCIL ? r0 : ((!FULL && r0 >= 0) ? srow[r0] : -1);
-        const int js1 = STENCIL ? r1 : ((!FULL && r1 >= 0) ? srow[r1] : -1);
+        const int js0 = (STENCIL || BATCH) ? r0 : ((!FULL && r0 >= 0) ? srow[r0] : -1);
+        const int js1 = (STENCIL || BATCH) ? r1 : ((!FULL && r1 >= 0) ? srow[r1] : -1);
         const int ic = max(jc, 0), i0 = max(js0, 0), i1 = max(js1, 0), ix = max(jx, 0);
         uint4 pjc, pj0, pj1;
         real qjc, qj0, qj1;
@@ -1418,13 +1438,13 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_adjoint(
         }
         if (!FULL)
             for (int c = lane + 128; c < cnt; c += 64) {
-                if (STENCIL) {
+                if (STENCIL || BATCH) {
                     const int j = batch_j[a * (int64_t)p_stride + c];
                     if (j < 0) continue;
                     uint4 sj;
                     real qj;
                     at.get(j, sj, qj);
-                    if (in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, qj);
+                    if (!shell_test || in_annulus(si, sj, t_core, t_shell)) shell_pair(j, sj, qj);
                 } else {
                     const int j = srow[sample ? (int)rrow[c] : c];
                     uint4 sj;
@@ -1599,7 +1619,7 @@ __global__ __launch_bounds__(512) void k_bucket_reduce(BucketArgs bk, real* __re
     }
 }
 
-template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL>
+template <typename real, bool FULL, bool WANT_LJ, bool BK, bool STENCIL, bool BATCH = false>
 static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const BucketArgs& bk, int rec_cap, size_t lds)
 {
     const int64_t n = h->cfg.n_atoms;
@@ -1627,9 +1647,10 @@ static hipError_t launch_adj_t(irbe_ctx* h, uint64_t step, int apw, const Bucket
         h->batch_j, h->geo.t_core, h->geo.t_shell, (real)h->cfg.lj_cut, (const real*)h->gs, h->gmean,             \
         (real*)h->gself, (real*)h->gscat, (real*)h->gqself, (real*)h->gqscat, h->ljpart, bk, rec_cap
     if (h->geo.skin)
-        k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL, true><<<nb, kCoopBlock, lds, h->stream>>>(IRBE_ADJ_ARGS);
+        k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL, true, BATCH><<<nb, kCoopBlock, lds, h->stream>>>(IRBE_ADJ_ARGS);
     else
-        k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL, false><<<nb, kCoopBlock, lds, h->stream>>>(IRBE_ADJ_ARGS);
+        k_pair_adjoint<real, FULL, WANT_LJ, BK, STENCIL, false, BATCH><<<nb, kCoopBlock, lds, h->stream>>>(IRBE_ADJ_ARGS);
+    h->adj_used_batch = BATCH;
 #undef IRBE_ADJ_ARGS
     e = hipGetLastError();
     if (e != hipSuccess || !BK) return e;
@@ -1648,6 +1669,13 @@ static hipError_t launch_adj_r(irbe_ctx* h, uint64_t step, bool want_lj, int apw
     if (h->stencil)
         return want_lj ? launch_adj_t<real, false, true, BK, true>(h, step, apw, bk, rec_cap, lds)
                        : launch_adj_t<real, false, false, BK, true>(h, step, apw, bk, rec_cap, lds);
+    // the batch atoms the forward wrote, when they are those of this step's ranks
+    // (launch_draw keeps them unless it draws again)
+    hipError_t e = launch_draw(h, step);
+    if (e != hipSuccess) return e;
+    if (h->batch_j_valid)
+        return want_lj ? launch_adj_t<real, false, true, BK, false, true>(h, step, apw, bk, rec_cap, lds)
+                       : launch_adj_t<real, false, false, BK, false, true>(h, step, apw, bk, rec_cap, lds);
     return want_lj ? launch_adj_t<real, false, true, BK, false>(h, step, apw, bk, rec_cap, lds)
                    : launch_adj_t<real, false, false, BK, false>(h, step, apw, bk, rec_cap, lds);
 }

@@ -26,11 +26,11 @@ SHELL_SOURCE = {"list": 0, "stencil": 1}
 DBG = {
     "cell_start": 1, "cell_atoms": 2, "core_off": 3, "core_idx": 4, "shell_off": 5, "shell_idx": 6,
     "batch_off": 7, "batch_rank": 8, "kvec": 9, "rho": 10, "fcorr": 11, "scalars": 12, "counts": 13,
-    "batch_atoms": 14, "adj_atomics": 15,
+    "batch_atoms": 14, "adj_atomics": 15, "adj_batch": 16,
 }
 _DBG_DTYPE = {1: np.int64, 2: np.int64, 3: np.int64, 4: np.int32, 5: np.int64, 6: np.int32, 7: np.int64,
               8: np.int32, 9: np.int32, 10: np.float64, 11: np.float64, 12: np.float64, 13: np.int64, 14: np.int32,
-              15: np.int64}
+              15: np.int64, 16: np.int64}
 
 STATUS = {0: "IRBE_OK", -1: "IRBE_EINVAL", -2: "IRBE_ENOMEM", -3: "IRBE_EHIP", -4: "IRBE_ECAPACITY",
           -5: "IRBE_ESTATE", -6: "IRBE_EUNSUPPORTED", -7: "IRBE_ENONFINITE", -8: "IRBE_ECONVERGENCE"}

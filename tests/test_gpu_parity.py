@@ -296,6 +296,43 @@ def test_backward_is_deterministic(precision):
     h.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_backward_reads_forward_batch(precision):
+    """Once a backward has followed a forward, the next forward on the handle also
+    writes its batch atoms and the backward at that step reads them in place of the
+    ranks and the shell rows: its gradients equal bit for bit those of handles that
+    read the ranks; a backward at another step than the forward's reads the ranks."""
+    w = inputs.workload("water4k")
+    ha, pos, q, pos_np, q_np = _setup(w, precision)
+    G = torch.tensor(np.random.default_rng(9).standard_normal((w.n_atoms, 3)), dtype=pos.dtype, device=pos.device)
+
+    def fresh(step):
+        h, *_ = _setup(w, precision)
+        h.build_lists(pos, step)
+        h.compute_forces(pos, step)
+        g = h.compute_forces_backward(pos, step, G)
+        assert int(h.debug("adj_batch")[0]) == 0
+        h.close()
+        return g
+
+    for step in (1, 2):
+        ha.build_lists(pos, step)
+        ha.compute_forces(pos, step)
+        got = ha.compute_forces_backward(pos, step, G)
+        assert int(ha.debug("adj_batch")[0]) == (1 if step == 2 else 0)
+    ref = fresh(2)
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
+    # forward at step 3, backward at step 4: the batch written is not that of step 4
+    ha.compute_forces(pos, 3)
+    got = ha.compute_forces_backward(pos, 4, G)
+    assert int(ha.debug("adj_batch")[0]) == 0
+    ref = fresh(4)
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
+    ha.close()
+
+
 @pytest.mark.slow
 def test_gpu_estimator_is_unbiased(orc):
     """Mean of the GPU RBL+RBE force over many steps (independent samples) tends
