@@ -151,6 +151,33 @@ def test_skin_backward_after_moves(orc, mode, precision, tol):
     h.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_skin_backward_reads_forward_batch(precision):
+    """Skin lists kept over steps at moved positions: after a forward and a
+    backward, the forward of the next step writes its batch atoms and the backward
+    reads them (with the membership test at the moved positions); its gradients
+    equal bit for bit those of a handle that reads the ranks."""
+    w = inputs.workload("water4k")
+    skin = 0.1
+    ha, pos, q, pos_np, q_np = _setup(w, precision, skin, "rbl")
+    hb, *_ = _setup(w, precision, skin, "rbl")
+    ha.build_lists(pos, 5)
+    hb.build_lists(pos, 5)
+    pos_m = torch.tensor(_moved(pos_np, skin), dtype=pos.dtype, device=pos.device)
+    G = torch.tensor(np.random.default_rng(12).standard_normal((w.n_atoms, 3)), dtype=pos.dtype, device=pos.device)
+    for step in (6, 7):
+        ha.compute_forces(pos_m, step)
+        got = ha.compute_forces_backward(pos_m, step, G)
+    assert int(ha.debug("adj_batch")[0]) == 1
+    hb.compute_forces(pos_m, 7)
+    ref = hb.compute_forces_backward(pos_m, 7, G)
+    assert int(hb.debug("adj_batch")[0]) == 0
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
+    ha.close()
+    hb.close()
+
+
 def test_skin_lists_with_all_members_equal_fresh_lists():
     """With p~ above every list length, skin lists at moved positions give the
     forces of skin-free lists built at those positions (GPU against GPU; the
