@@ -712,7 +712,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
     const int32_t* __restrict__ core, const int32_t* __restrict__ ncore, int cap_core,
     const int32_t* __restrict__ shell, const int32_t* __restrict__ nshell, int cap_shell,
     const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, int p_stride, const uint16_t* __restrict__ ranks,
-    uint64_t t_core, uint64_t t_shell, bool skin, real* __restrict__ fsr, double* __restrict__ part)
+    uint64_t t_core, uint64_t t_shell, bool skin, real* __restrict__ fsr, double* __restrict__ part,
+    int32_t* __restrict__ bj_out)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
@@ -769,6 +770,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
             for (int u = 0; u < 4; ++u) r[u] = c0 + u < cnt ? (sample ? (int)rrow[c0 + u] : c0 + u) : -1;
 #pragma unroll
             for (int u = 0; u < 4; ++u) j[u] = r[u] >= 0 ? srow[r[u]] : -1;
+            if (bj_out) {
+                // the batch atoms, for the backward expected at this step
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c0 + u < cnt) bj_out[a * (int64_t)p_stride + c0 + u] = j[u];
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) at.get(max(j[u], 0), sj[u], qj[u]);
 #pragma unroll
@@ -926,11 +933,14 @@ static hipError_t launch_thread_t(irbe_ctx* h, uint64_t step)
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)blocks_for(n, kCoopBlock);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
+    // the batch atoms for the backward, as in launch_coop_t
+    int32_t* bj_out = h->keep_batch ? h->batch_j : nullptr;
     k_pair_thread<real, EV><<<nb, kCoopBlock, 0, h->stream>>>(
         n, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core, h->shell, h->nshell,
         h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride, h->ranks, h->geo.t_core,
-        h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part);
+        h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part, bj_out);
     h->pair_nb = nb;
+    if (bj_out) h->batch_j_valid = true;
     return hipGetLastError();
 }
 

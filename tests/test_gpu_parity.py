@@ -333,6 +333,47 @@ def test_backward_reads_forward_batch(precision):
     ha.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sparse_backward_reads_forward_batch(precision):
+    """The same for the 1:1 electrolyte (a batch of 10 per atom: the thread-per-atom
+    pair kernel writes the batch atoms), against a handle that reads the ranks: bit
+    for bit when no shell record takes the atomic fallback, else to the rounding of
+    the atomics' order (some do at this size, with or without the batch)."""
+    from paper_2204_13595_amd import irbe
+    w = inputs.electrolyte(1)
+    dev = torch.device("cuda", 0)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    pos = torch.tensor(w.pos, dtype=dt, device=dev)
+    G = torch.tensor(np.random.default_rng(18).standard_normal((w.n_atoms, 3)), dtype=dt, device=dev)
+
+    def handle():
+        h = irbe.Handle(w.n_atoms, w.box, beta=math.sqrt(0.03), r_core=5.0, r_shell=15.0, p_shell=10,
+                        p_kspace=100, coulomb_k=1.0, precision=precision, device=dev)
+        h.set_system(torch.tensor(w.atom_type, device=dev), torch.tensor(w.charge, dtype=dt, device=dev),
+                     torch.tensor(w.molecule, device=dev), w.lj_sigma, w.lj_eps)
+        return h
+
+    ha, hb = handle(), handle()
+    for step in (1, 2):
+        ha.build_lists(pos, step)
+        ha.compute_forces(pos, step)
+        got = ha.compute_forces_backward(pos, step, G)
+    assert int(ha.debug("adj_batch")[0]) == 1
+    hb.build_lists(pos, 2)
+    hb.compute_forces(pos, 2)
+    ref = hb.compute_forces_backward(pos, 2, G)
+    assert int(hb.debug("adj_batch")[0]) == 0
+    atomics = int(hb.debug("adj_atomics")[0]) != 0
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    for x, y in zip(got, ref):
+        if atomics:
+            assert float((x - y).abs().max()) <= tol * float(y.abs().max())
+        else:
+            assert torch.equal(x, y)
+    ha.close()
+    hb.close()
+
+
 @pytest.mark.slow
 def test_gpu_estimator_is_unbiased(orc):
     """Mean of the GPU RBL+RBE force over many steps (independent samples) tends
