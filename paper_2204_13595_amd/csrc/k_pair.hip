@@ -1723,6 +1723,11 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
     const int rec_budget = h->fp64 ? kBucketRecD : kBucketRecF;
     const int rec_max = h->fp64 ? kBucketRecMaxD : kBucketRecMaxF;
     int apw = std::min(kAtomsPerWave, std::max(2, rec_budget / (waves_pb * p_eff)));
+    // a block's atoms within two cell rows, the source rows its keys cover: at most
+    // 0.9 of a row's mean population per block (dilute small boxes), else the rest
+    // of its shell records would take the atomic fallback
+    const double row_atoms = (double)n / ((double)bk.n_c * (double)bk.n_c);
+    apw = std::min(apw, std::max(2, (int)(0.9 * row_atoms / waves_pb)));
     if (waves_pb * apw * p_eff > rec_max) apw = rec_max / (waves_pb * p_eff);
     const int rec_cap = waves_pb * std::max(apw, 1) * p_eff;
     const int nkeys = 2 * bk.span * bk.span;
