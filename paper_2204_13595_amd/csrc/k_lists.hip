@@ -389,44 +389,55 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         const int chunks = __builtin_amdgcn_readlane(nch, __builtin_ctzll(left));
                         uint64_t pend = left & ballot(nch == chunks);
                         left &= ~pend;
-                        while (pend) {
-                            // the next two atoms: a in the lower half, b in the upper
-                            const int a = __builtin_ctzll(pend);
-                            pend &= pend - 1;
-                            const bool has_b = pend != 0;
-                            const int b = has_b ? __builtin_ctzll(pend) : a;
-                            if (has_b) pend &= pend - 1;
-                            const int drow = b - a;
-                            const int ka = a + (hsel & drow);  // this half's atom
-                            const u32x4 ap = apk[ka];
-                            const int2 cn = acnt[ka];
-                            const int lenm = (int)(ap.w >> 16) - hl;
-                            const int qb = (int)(ap.w & 0xffffu) + hl;
-                            int cs = cn.y, cc = cn.x;  // this half's atom: list lengths so far
-                            // byte offsets of this half's atom's rows in the wave's list rows
-                            const int hoff_s = __mul24(ka, cap_shell * 4);
-                            auto scan = [&](auto core_tag) {
-                                constexpr bool CORE = decltype(core_tag)::value;
-                                const int hoff_c = __mul24(ka, cap_core * 4);
-                                // the two atoms have the same number of chunks: every lane of
-                                // all chunks but the last lies inside its half's range
-                                const int last = (chunks - 1) * 32;
-                                if (chunks > 1) {
-                                    int c0 = 0;
-                                    do {
-                                        scan_chunk<MODE, CORE, false>(trec[qb + c0], true, ap, chunk, ka, tb, mb, e,
-                                                                      t_core, t_lo, t_shell, spos, lane, hsel, lowm,
-                                                                      hoff_s, hoff_c, rs_s, rs_c, cs, cc);
-                                        c0 += 32;
-                                    } while (c0 < last);
+                        // the pairs of this chunk count; MULTI: more than one chunk (a wave-uniform
+                        // choice made here, once for the chunk count, not per pair)
+                        auto pairs = [&](auto multi_tag, auto core_tag) {
+                            constexpr bool MULTI = decltype(multi_tag)::value;
+                            constexpr bool CORE = decltype(core_tag)::value;
+                            while (pend) {
+                                // the next two atoms: a in the lower half, b in the upper
+                                const int a = __builtin_ctzll(pend);
+                                pend &= pend - 1;
+                                const bool has_b = pend != 0;
+                                const int b = has_b ? __builtin_ctzll(pend) : a;
+                                if (has_b) pend &= pend - 1;
+                                const int drow = b - a;
+                                const int ka = a + (hsel & drow);  // this half's atom
+                                const u32x4 ap = apk[ka];
+                                const int2 cn = acnt[ka];
+                                const int lenm = (int)(ap.w >> 16) - hl;
+                                const int qb = (int)(ap.w & 0xffffu) + hl;
+                                int cs = cn.y, cc = cn.x;  // this half's atom: list lengths so far
+                                // byte offsets of this half's atom's rows in the wave's list rows
+                                const int hoff_s = __mul24(ka, cap_shell * 4);
+                                {
+                                    const int hoff_c = __mul24(ka, cap_core * 4);
+                                    // the two atoms have the same number of chunks: every lane of
+                                    // all chunks but the last lies inside its half's range
+                                    const int last = MULTI ? (chunks - 1) * 32 : 0;
+                                    if (MULTI) {
+                                        int c0 = 0;
+                                        do {
+                                            scan_chunk<MODE, CORE, false>(trec[qb + c0], true, ap, chunk, ka, tb, mb,
+                                                                          e, t_core, t_lo, t_shell, spos, lane, hsel,
+                                                                          lowm, hoff_s, hoff_c, rs_s, rs_c, cs, cc);
+                                            c0 += 32;
+                                        } while (c0 < last);
+                                    }
+                                    scan_chunk<MODE, CORE, true>(trec[qb + last], last < lenm, ap, chunk, ka, tb, mb,
+                                                                 e, t_core, t_lo, t_shell, spos, lane, hsel, lowm,
+                                                                 hoff_s, hoff_c, rs_s, rs_c, cs, cc);
                                 }
-                                scan_chunk<MODE, CORE, true>(trec[qb + last], last < lenm, ap, chunk, ka, tb, mb, e,
-                                                             t_core, t_lo, t_shell, spos, lane, hsel, lowm, hoff_s,
-                                                             hoff_c, rs_s, rs_c, cs, cc);
-                            };
-                            if (core_row) scan(std::true_type{});
-                            else scan(std::false_type{});
-                            if (lane == 0 || (lane == 32 && has_b)) acnt[ka] = make_int2(cc, cs);
+                                if (lane == 0 || (lane == 32 && has_b)) acnt[ka] = make_int2(cc, cs);
+                            }
+                        };
+                        // (the row's core flag and the chunk count chosen here, once)
+                        if (core_row) {
+                            if (chunks > 1) pairs(std::true_type{}, std::true_type{});
+                            else pairs(std::false_type{}, std::true_type{});
+                        } else {
+                            if (chunks > 1) pairs(std::true_type{}, std::false_type{});
+                            else pairs(std::false_type{}, std::false_type{});
                         }
                     }
                 }
