@@ -389,10 +389,10 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                         const int chunks = __builtin_amdgcn_readlane(nch, __builtin_ctzll(left));
                         uint64_t pend = left & ballot(nch == chunks);
                         left &= ~pend;
-                        // the pairs of this chunk count; MULTI: more than one chunk (a wave-uniform
-                        // choice made here, once for the chunk count, not per pair)
-                        auto pairs = [&](auto multi_tag, auto core_tag) {
-                            constexpr bool MULTI = decltype(multi_tag)::value;
+                        // the pairs of this chunk count; NCH: 1 or 2 chunks (straight-line code), 0
+                        // for more (a loop); chosen here once for the chunk count, not per pair
+                        auto pairs = [&](auto nch_tag, auto core_tag) {
+                            constexpr int NCH = decltype(nch_tag)::value;
                             constexpr bool CORE = decltype(core_tag)::value;
                             while (pend) {
                                 // the next two atoms: a in the lower half, b in the upper
@@ -414,8 +414,12 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                     const int hoff_c = __mul24(ka, cap_core * 4);
                                     // the two atoms have the same number of chunks: every lane of
                                     // all chunks but the last lies inside its half's range
-                                    const int last = MULTI ? (chunks - 1) * 32 : 0;
-                                    if (MULTI) {
+                                    const int last = NCH == 1 ? 0 : NCH == 2 ? 32 : (chunks - 1) * 32;
+                                    if (NCH == 2) {
+                                        scan_chunk<MODE, CORE, false>(trec[qb], true, ap, chunk, ka, tb, mb, e, t_core,
+                                                                      t_lo, t_shell, spos, lane, hsel, lowm, hoff_s,
+                                                                      hoff_c, rs_s, rs_c, cs, cc);
+                                    } else if (NCH == 0) {
                                         int c0 = 0;
                                         do {
                                             scan_chunk<MODE, CORE, false>(trec[qb + c0], true, ap, chunk, ka, tb, mb,
@@ -432,12 +436,17 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                             }
                         };
                         // (the row's core flag and the chunk count chosen here, once)
+                        using one = std::integral_constant<int, 1>;
+                        using two = std::integral_constant<int, 2>;
+                        using many = std::integral_constant<int, 0>;
                         if (core_row) {
-                            if (chunks > 1) pairs(std::true_type{}, std::true_type{});
-                            else pairs(std::false_type{}, std::true_type{});
+                            if (chunks == 1) pairs(one{}, std::true_type{});
+                            else if (chunks == 2) pairs(two{}, std::true_type{});
+                            else pairs(many{}, std::true_type{});
                         } else {
-                            if (chunks > 1) pairs(std::true_type{}, std::false_type{});
-                            else pairs(std::false_type{}, std::false_type{});
+                            if (chunks == 1) pairs(one{}, std::false_type{});
+                            else if (chunks == 2) pairs(two{}, std::false_type{});
+                            else pairs(many{}, std::false_type{});
                         }
                     }
                 }
