@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define IRBE_ABI_VERSION 2
+#define IRBE_ABI_VERSION 3
 
 typedef struct irbe_ctx* irbe_handle;
 
@@ -86,6 +86,9 @@ enum { IRBE_MIXED_FP32 = 0, IRBE_FP64 = 1 };
 
 /* irbe_config.shell_source */
 enum { IRBE_SHELL_LIST = 0, IRBE_SHELL_STENCIL = 1 };
+
+/* irbe_config.shell_entries */
+enum { IRBE_ENTRIES_AUTO = 0, IRBE_ENTRIES_32 = 32 };
 
 /* compute_forces flags */
 enum { IRBE_ENERGY = 1u, IRBE_VIRIAL = 2u };
@@ -141,6 +144,19 @@ typedef struct {
                               r < lj_cut sigma_ij, its energy shifted to zero there
                               (2^(1/6) for the soft spheres of the paper's
                               primitive-model electrolytes, Sec. 4)              */
+    int32_t shell_entries; /* storage of the shell lists S(i) (split lists only):
+                              IRBE_ENTRIES_AUTO: 16-bit codes, the member's
+                              stencil row and its position in that row's
+                              candidate range, where the build of dense cells
+                              (>= 4 atoms per cell on average) runs, the shell
+                              stencil has at most 64 rows and every row's
+                              candidate range fits the code (otherwise, and once
+                              a build finds a range too long, 32-bit indices);
+                              IRBE_ENTRIES_32: 32-bit sorted indices always.
+                              Lists, batches and results are the same either way:
+                              the codes halve the shell rows' device memory (2
+                              bytes per entry of capacity) and the bytes the list
+                              build writes and the pair kernel reads.            */
 } irbe_config;
 
 /* Create a handle for one system size and parameter set; work is queued on
@@ -288,7 +304,11 @@ irbe_status irbe_get_timing(irbe_handle h, double* ms_host, int64_t capacity, in
  *   IRBE_DBG_ADJ_BATCH   int64 [1]          1 when the last compute_forces_backward
  *                                           read the batch atoms written by the
  *                                           forward, 0 when it read the ranks and
- *                                           the shell rows */
+ *                                           the shell rows (with 16-bit shell
+ *                                           entries: decoded them first into
+ *                                           batch atoms)
+ *   IRBE_DBG_SHELL_BITS  int64 [1]          storage of the current shell lists:
+ *                                           16 (codes) or 32 (sorted indices) */
 enum {
     IRBE_DBG_CELL_START = 1,
     IRBE_DBG_CELL_ATOMS = 2,
@@ -305,7 +325,8 @@ enum {
     IRBE_DBG_COUNTS = 13,
     IRBE_DBG_BATCH_ATOMS = 14,
     IRBE_DBG_ADJ_ATOMICS = 15,
-    IRBE_DBG_ADJ_BATCH = 16
+    IRBE_DBG_ADJ_BATCH = 16,
+    IRBE_DBG_SHELL_BITS = 17
 };
 irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t capacity, int64_t* written);
 

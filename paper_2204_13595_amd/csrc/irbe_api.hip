@@ -232,6 +232,8 @@ int32_t ktable(double beta, double L, std::vector<uint64_t>& U, double& H, doubl
 
 int32_t round_up32(double v) { return (int32_t)((std::ceil(v) + 31.0) / 32.0) * 32; }
 
+// Rows of cap_core and cap_shell entries per atom; shell entries of 2 bytes
+// (16-bit codes) while the handle can use them, else 4.
 hipError_t alloc_lists(irbe_ctx* h, int32_t cap_core, int32_t cap_shell)
 {
     const size_t n = (size_t)h->cfg.n_atoms;
@@ -240,11 +242,24 @@ hipError_t alloc_lists(irbe_ctx* h, int32_t cap_core, int32_t cap_shell)
     h->core = h->shell = nullptr;
     hipError_t e = dalloc(h, &h->core, n * (size_t)cap_core);
     if (e != hipSuccess) return e;
-    e = dalloc(h, &h->shell, n * (size_t)cap_shell);
+    const int32_t eb = h->shell16_ok && h->sgroup != nullptr && irbe::shell16_possible(h) ? 2 : 4;
+    e = dalloc(h, &h->shell, (n * (size_t)cap_shell * eb + 3) / 4);
     if (e != hipSuccess) return e;
+    h->shell_bytes = eb;
     h->cap_core = cap_core;
     h->cap_shell = cap_shell;
     return hipSuccess;
+}
+
+// Shell rows of 4-byte entries once the 16-bit codes have been given up
+// (after the queued work that may still read the old rows).
+hipError_t ensure_shell_rows_32(irbe_ctx* h)
+{
+    if (h->shell_bytes == 4 || h->shell16_ok) return hipSuccess;
+    const hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    h->have_lists = false;
+    return alloc_lists(h, h->cap_core, h->cap_shell);
 }
 
 // Rows for lists of the given longest lengths, grown by at least 30% so that a
@@ -265,6 +280,28 @@ hipError_t grow_lists(irbe_ctx* h, int32_t max_core, int32_t max_shell)
     return alloc_lists(h, nc, ns);
 }
 
+// Sorted index of the 16-bit shell entry e of an atom of list-build group grp,
+// decoded on the host (cs: the cell starts of the build); the layout of the
+// codes is that of ListCode. Clamped to [0, N) as on the device.
+int32_t decode_shell_entry(const ListCode& lc, const std::vector<int32_t>& cs, int32_t grp, uint32_t e)
+{
+    if (grp < 0 || grp >= lc.gpr * lc.n_c * lc.n_c) return 0;
+    auto wrap = [&](int c) { return c < 0 ? c + lc.n_c : (c >= lc.n_c ? c - lc.n_c : c); };
+    const int rid = (int)(e >> lc.pb), p = (int)(e & ((1u << lc.pb) - 1));
+    if (rid >= lc.span * lc.span) return 0;
+    const int rowid = grp / lc.gpr;
+    const int cz = rowid / lc.n_c, cy = rowid % lc.n_c;
+    const int x0 = (grp % lc.gpr) * lc.G;
+    const int span_u = std::min(lc.G, lc.n_c - x0) - 1 + lc.span;
+    const int xu0 = wrap(x0 + lc.lo);
+    const int lenA = std::min(span_u, lc.n_c - xu0);
+    const int z = wrap(cz + rid / lc.span + lc.lo), y = wrap(cy + rid % lc.span + lc.lo);
+    const int64_t row = ((int64_t)z * lc.n_c + y) * lc.n_c;
+    const int32_t a = cs[row + xu0], na = cs[row + xu0 + lenA] - a;
+    const int64_t j = p < na ? (int64_t)a + p : (int64_t)cs[row] + (p - na);
+    return (int32_t)std::min<int64_t>(std::max<int64_t>(j, 0), cs.back() - 1);
+}
+
 irbe_status check_device_error(irbe_ctx* h)
 {
     uint32_t err = 0;
@@ -275,11 +312,19 @@ irbe_status check_device_error(irbe_ctx* h)
     if (err) {
         IRBE_TRY(h, launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1), "clear error word");
         if (err & ERR_NONFINITE) return fail(h, IRBE_ENONFINITE, "non-finite position");
+        // a stencil row's candidates beyond the 16-bit entry codes: 32-bit entries
+        // from the next build on
+        if (err & ERR_SHELL_CODE) h->shell16_ok = false;
         // the rows of some build since the last check were too short: the forces
         // computed from those lists miss entries; grow the rows for the next build
         const hipError_t e = grow_lists(h, std::max(mx[0], h->max_core), std::max(mx[1], h->max_shell));
         if (e == hipErrorInvalidValue) return fail(h, IRBE_ECAPACITY, "more than 65535 list entries per atom");
         if (e != hipSuccess) return hip_fail(h, e, "grow lists");
+        if (err & ERR_SHELL_CODE)
+            return fail(h, IRBE_ECAPACITY,
+                        "a shell stencil row's candidates exceeded the 16-bit entry codes in a build since the last "
+                        "check: forces computed from those lists are wrong; 32-bit entries from now on, build the "
+                        "lists again");
         return fail(h, IRBE_ECAPACITY,
                     "list capacity exceeded by a build since the last check: forces computed from those lists are "
                     "incomplete; the rows have been grown, build the lists again");
@@ -300,6 +345,8 @@ irbe_status poll_list_check(irbe_ctx* h)
     const uint32_t err = (uint32_t)h->chk_host[0];
     h->max_core = h->chk_host[1];
     h->max_shell = h->chk_host[2];
+    // (an overflowing code: 32-bit entries from the next build on)
+    if (err & ERR_SHELL_CODE) h->shell16_ok = false;
     if (err & (ERR_CORE_CAP | ERR_SHELL_CAP)) {
         const hipError_t e = grow_lists(h, h->max_core, h->max_shell);
         if (e == hipErrorInvalidValue) return fail(h, IRBE_ECAPACITY, "more than 65535 list entries per atom");
@@ -428,6 +475,8 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
         return fail(nullptr, IRBE_EINVAL, "bad shell_source");
     if (c.shell_source == IRBE_SHELL_STENCIL && c.p_shell <= 0)
         return fail(nullptr, IRBE_EINVAL, "stencil sampling needs p_shell > 0");
+    if (c.shell_entries != IRBE_ENTRIES_AUTO && c.shell_entries != IRBE_ENTRIES_32)
+        return fail(nullptr, IRBE_EINVAL, "bad shell_entries");
 
     irbe_ctx* h = new (std::nothrow) irbe_ctx();
     if (!h) return fail(nullptr, IRBE_ENOMEM, "host allocation failed");
@@ -437,6 +486,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     h->real_size = h->fp64 ? 8 : 4;
     h->full_list = c.p_shell <= 0;
     h->stencil = c.shell_source == IRBE_SHELL_STENCIL;
+    h->shell16_ok = c.shell_entries == IRBE_ENTRIES_AUTO;
     geometry(c, h->geo);
     if (h->geo.n_c < 3) {
         delete h;
@@ -515,6 +565,7 @@ irbe_status irbe_create(const irbe_config* cfg, void* hip_stream, irbe_handle* o
     h->p_stride = c.p_shell > 0 ? (c.p_shell + 3) / 4 * 4 : 0;
     if (h->p_stride > 0) ALLOC(dalloc(h, &h->ranks, n * (size_t)h->p_stride));
     if (h->stencil) ALLOC(dalloc(h, &h->scell, n));
+    if (!h->full_list && !h->stencil && h->shell16_ok) ALLOC(dalloc(h, &h->sgroup, n));
     ALLOC(dalloc(h, &h->nshell, n));
     ALLOC(dalloc_bytes(h, &h->fsr, 3 * n * rs));
     ALLOC(dalloc(h, &h->pair_part, (size_t)nb64 * kPairPartials));
@@ -678,12 +729,13 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
     if (!h->have_system) return fail(h, IRBE_ESTATE, "irbe_build_lists before irbe_set_system");
     h->have_lists = false;
     h->ranks_valid = false;
-    h->batch_j_valid = false;
+    h->batch_j_valid = h->batch_j_fwd = false;
     if (h->lists_sized && !h->stencil) {
         // steady state: queue the build and a copy of its error word and list
         // lengths, and take in an earlier copy if it has completed; no wait
         const irbe_status st = poll_list_check(h);
         if (st != IRBE_OK) return st;
+        IRBE_TRY(h, ensure_shell_rows_32(h), "reallocate the shell rows");
         IRBE_STAGE(h, IRBE_STAGE_BIN, launch_bin(h, pos), "binning");
         IRBE_TRY(h, launch_fill_i32(h->stream, h->maxcnt, 0, 2), "list build");
         IRBE_STAGE(h, IRBE_STAGE_LISTS, launch_build_lists(h), "list build");
@@ -697,7 +749,8 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
     // the first build (and every build with stencil sampling, whose stencil
     // counts size the batch draw): wait for the list lengths and grow the rows
     IRBE_STAGE(h, IRBE_STAGE_BIN, launch_bin(h, pos), "binning");
-    for (int attempt = 0; attempt < 3; ++attempt) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        IRBE_TRY(h, ensure_shell_rows_32(h), "reallocate the shell rows");
         IRBE_TRY(h, launch_fill_i32(h->stream, h->maxcnt, 0, 2), "list build");
         IRBE_STAGE(h, IRBE_STAGE_LISTS, launch_build_lists(h), "list build");
         int32_t mx[2] = {0, 0};
@@ -709,6 +762,12 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step)
             IRBE_TRY(h, launch_fill_i32(h->stream, (int32_t*)h->err, 0, 1), "clear error word");
             if (err & ERR_NONFINITE) return fail(h, IRBE_ENONFINITE, "non-finite position");
             // capacity bits of this build: the rows grow below and the lists are built again
+            if (err & ERR_SHELL_CODE) {
+                // a stencil row's candidate range too long for the 16-bit codes:
+                // 32-bit entries from now on, and the lists built again
+                h->shell16_ok = false;
+                continue;
+            }
         }
         if (h->stencil && mx[1] > 65535)
             return fail(h, IRBE_EUNSUPPORTED, "more than 65535 atoms in a shell stencil");
@@ -935,6 +994,18 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
                 rk.resize((size_t)n * h->p_stride);
                 IRBE_TRY(h, d2h(rk.data(), h->ranks, rk.size() * 2), "debug");
             }
+        } else if (!is_core && h->shell16) {
+            // 16-bit entries, decoded here
+            std::vector<uint16_t> r16((size_t)n * stride);
+            std::vector<int32_t> cs((size_t)h->geo.n_cells + 1), grp((size_t)n);
+            IRBE_TRY(h, d2h(r16.data(), h->shell, r16.size() * 2), "debug");
+            IRBE_TRY(h, d2h(cs.data(), h->cell_start, cs.size() * 4), "debug");
+            IRBE_TRY(h, d2h(grp.data(), h->sgroup, grp.size() * 4), "debug");
+            rows.assign((size_t)n * stride, 0);
+            for (int64_t k = 0; k < n; ++k)
+                for (int32_t t = 0; t < cnt[k]; ++t)
+                    rows[(size_t)k * stride + t] =
+                        decode_shell_entry(h->lcode, cs, grp[k], r16[(size_t)k * stride + t]);
         } else {
             rows.resize((size_t)n * stride);
             IRBE_TRY(h, d2h(rows.data(), is_core ? h->core : h->shell, rows.size() * 4), "debug");
@@ -1004,6 +1075,12 @@ irbe_status irbe_get_debug(irbe_handle h, int32_t what, void* dst_host, int64_t 
         copy_out(&v, 8, 1);
         return IRBE_OK;
     }
+    case IRBE_DBG_SHELL_BITS: {
+        if (!h->have_lists) return fail(h, IRBE_ESTATE, "no lists built");
+        const int64_t v = h->shell16 ? 16 : 32;
+        copy_out(&v, 8, 1);
+        return IRBE_OK;
+    }
     case IRBE_DBG_ADJ_ATOMICS: {
         unsigned long long c = 0;
         IRBE_TRY(h, d2h(&c, h->adj_atomics, sizeof(c)), "debug");
@@ -1049,6 +1126,25 @@ irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows
     }
     std::vector<int64_t> off((size_t)n_rows + 1, 0);
     std::vector<int32_t> idx;
+    // the first len entries of sorted atom k's shell row as sorted indices
+    std::vector<int32_t> cs16;  // cell starts of the build, for 16-bit entries
+    auto read_shell_row = [&](int32_t k, int64_t len, std::vector<int32_t>& row) -> hipError_t {
+        row.resize((size_t)len);
+        if (!h->shell16)
+            return hipMemcpy(row.data(), h->shell + (int64_t)k * h->cap_shell, (size_t)len * 4, hipMemcpyDeviceToHost);
+        std::vector<uint16_t> r16((size_t)len);
+        int32_t grp = 0;
+        hipError_t e = hipMemcpy(r16.data(), reinterpret_cast<const uint16_t*>(h->shell) + (int64_t)k * h->cap_shell,
+                                 (size_t)len * 2, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(&grp, h->sgroup + k, 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && cs16.empty()) {
+            cs16.resize((size_t)h->geo.n_cells + 1);
+            e = hipMemcpy(cs16.data(), h->cell_start, cs16.size() * 4, hipMemcpyDeviceToHost);
+        }
+        if (e != hipSuccess) return e;
+        for (int64_t t = 0; t < len; ++t) row[(size_t)t] = decode_shell_entry(h->lcode, cs16, grp, r16[(size_t)t]);
+        return hipSuccess;
+    };
     for (int64_t r = 0; r < n_rows; ++r) {
         int32_t k = 0, cnt = 0;
         IRBE_TRY(h, hipMemcpy(&k, h->rank + rows_host[r], 4, hipMemcpyDeviceToHost), "debug");
@@ -1078,18 +1174,20 @@ irbe_status irbe_get_debug_rows(irbe_handle h, int32_t what, const int64_t* rows
             }
             if (is_atoms) {
                 // list sampling: the shell members at the ranks
-                std::vector<int32_t> row((size_t)cnt);
-                IRBE_TRY(h, hipMemcpy(row.data(), h->shell + (int64_t)k * h->cap_shell, (size_t)cnt * 4,
-                                      hipMemcpyDeviceToHost),
-                         "debug");
+                std::vector<int32_t> row;
+                IRBE_TRY(h, read_shell_row(k, cnt, row), "debug");
                 for (auto v : rv) idx.push_back(perm[row[v]]);
             } else {
                 for (auto v : rv) idx.push_back(v);
             }
         } else {
             std::vector<int32_t> row((size_t)len);
-            const int32_t* src = is_core ? h->core + (int64_t)k * h->cap_core : h->shell + (int64_t)k * h->cap_shell;
-            IRBE_TRY(h, hipMemcpy(row.data(), src, (size_t)len * 4, hipMemcpyDeviceToHost), "debug");
+            if (is_core)
+                IRBE_TRY(h, hipMemcpy(row.data(), h->core + (int64_t)k * h->cap_core, (size_t)len * 4,
+                                      hipMemcpyDeviceToHost),
+                         "debug");
+            else
+                IRBE_TRY(h, read_shell_row(k, len, row), "debug");
             for (auto v : row) idx.push_back(perm[v]);
         }
     }

@@ -13,7 +13,22 @@
 namespace irbe {
 
 // Error-word bits set by kernels and read back at the next waiting call.
-enum : uint32_t { ERR_NONFINITE = 1u, ERR_CORE_CAP = 2u, ERR_SHELL_CAP = 4u };
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_CORE_CAP = 2u, ERR_SHELL_CAP = 4u, ERR_SHELL_CODE = 8u };
+
+// 16-bit shell entries. The list build treats the cells of a cell row in groups
+// of G consecutive cells (the last group of a row may be shorter); for stencil
+// row (dz, dy) a group's candidates are the atoms of the union of its cells'
+// x ranges in that row, at most two index ranges of the sorted atoms (the
+// second after the periodic wrap). An entry stores the row's id
+// (dz - lo) * span + (dy - lo) in its high bits and the member's position in
+// that candidate range in its low pb bits; the member is then
+// a + p for p < na, else b + (p - na), with a, na the first atom and length of
+// the first range and b the first atom of the second.
+struct ListCode {
+    const int32_t* cell_start;  // [n_c^3 + 1] of the build
+    const int32_t* sgroup;      // [N] list-build group of each sorted atom
+    int n_c, lo, span, G, gpr, pb;  // gpr: groups per cell row
+};
 
 constexpr int kBlock = 256;          // threads per block of the per-atom kernels
 constexpr int kReduceBlock = 256;    // threads of the deterministic final reductions
@@ -23,7 +38,9 @@ constexpr int kMaxTypesGrad = 4;     // LJ parameter gradients: n_types <= 4
 // atoms per wavefront in the cooperative pair kernels: the adjoint, the forward
 // kernel with list-drawn batches, and the forward kernel with stencil sampling
 constexpr int kAtomsPerWave = 8;
-constexpr int kAtomsPerWaveList = 4;
+constexpr int kAtomsPerWaveList = 4;   // full lists
+constexpr int kAtomsPerWaveSplit = 8;  // split lists (the optimum with 16-bit shell entries; the same with
+                                       // 32-bit ones, so that the per-block sums and results do not change)
 constexpr int kAtomsPerWaveStencil = 16;
 // Shell-adjoint transpose: scatter records staged per block in LDS, then
 // bucketed by destination cell row (y, z) and reduced per row.
@@ -146,7 +163,13 @@ struct irbe_ctx {
 
     int32_t* core = nullptr;          // [N * cap_core]
     int32_t* ncore = nullptr;         // [N]
-    int32_t* shell = nullptr;         // [N * cap_shell]
+    int32_t* shell = nullptr;         // [N * cap_shell] 32-bit sorted indices, or (shell16) 16-bit codes in
+                                      //     the first half of the allocation, rows of cap_shell entries
+    bool shell16 = false;             // the current shell lists hold 16-bit codes (ListCode)
+    int32_t shell_bytes = 4;          // bytes per entry of the shell rows' allocation (2: codes)
+    bool shell16_ok = true;           // cleared for good once a build found a row range too long for the codes
+    irbe::ListCode lcode{};           // decoding of the current lists' codes
+    int32_t* sgroup = nullptr;        // [N] list-build group of each sorted atom (16-bit shell entries)
     int32_t* nshell = nullptr;        // [N]
 
     void* fsr = nullptr;              // real[3N] sorted short-range (+ excluded-pair) force
@@ -187,6 +210,7 @@ struct irbe_ctx {
                                       // with list-drawn batches written by the forward for the backward that
                                       // follows it; allocated on first use
     bool batch_j_valid = false;       // batch_j holds the decode of the current ranks
+    bool batch_j_fwd = false;         // ... written by a forward (not by a decode for the backward)
     bool keep_batch = false;          // the next forward writes batch_j (the last forward had a backward)
     bool fwd_pending = false;         // a forward ran and no backward has followed it yet
     bool adj_used_batch = false;      // the last backward read batch_j instead of the ranks and shell rows
@@ -238,6 +262,9 @@ hipError_t launch_pair_adjoint(irbe_ctx* h, uint64_t step, bool want_q, bool wan
 hipError_t ensure_buckets(irbe_ctx* h, int64_t records);
 // Stencil sampling: allocate the read-back array of the decoded batch, and fill it.
 hipError_t ensure_batch_atoms(irbe_ctx* h);
+// Whether this handle's shell lists can take 16-bit codes (ListCode): split lists
+// built by the tiled kernel over a narrow stencil of at most 64 rows.
+bool shell16_possible(const irbe_ctx* h);
 // Device-memory Floyd bitmaps of at least `words` 32-bit words.
 hipError_t ensure_draw_bits(irbe_ctx* h, size_t words);
 hipError_t launch_stencil_decode(irbe_ctx* h);

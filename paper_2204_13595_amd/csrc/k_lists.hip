@@ -188,9 +188,11 @@ __device__ __forceinline__ void classify(D d2, const Bounds<D>& b, uint64_t keep
 // rest, and the exact test on positions read from memory the few left.
 // Members are appended to the half's rows (byte offsets hoff_s, hoff_c within
 // the descriptors) after cs and cc, which are advanced; a lane reads its own
-// bit of the member masks back for its store.
-template <int MODE, bool CORE, bool LAST>
-__device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x4& ap, int k_base, int k_rel,
+// bit of the member masks back for its store. ENC: shell members are stored as
+// the 16-bit code `code` (stencil row and candidate position) instead of the
+// sorted index.
+template <int MODE, bool CORE, bool LAST, bool ENC>
+__device__ __forceinline__ void scan_chunk(const u32x4& r, int code, bool k_in, const u32x4& ap, int k_base, int k_rel,
                                            const PackedBounds& tb, const MidBounds& mb, int e, uint64_t t_core,
                                            uint64_t t_lo, uint64_t t_shell, const uint4* __restrict__ spos, int lane,
                                            int hsel, uint32_t lowm, int hoff_s, int hoff_c,
@@ -230,8 +232,9 @@ __device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x
         const int ps_lo = __popc(ms_lo);
         // non-members store past the descriptor's range (dropped)
         const int pos = member_pos(ms_lo, ms_hi, lowm, cs);
-        const int off = __builtin_amdgcn_inverse_ballot_w64(m_shell) ? hoff_s + (pos << 2) : kNoStore;
-        __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_s, off, 0, 0);
+        const int off = __builtin_amdgcn_inverse_ballot_w64(m_shell) ? hoff_s + (pos << (ENC ? 1 : 2)) : kNoStore;
+        if (ENC) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)code, rs_s, off, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b32((int)r.w, rs_s, off, 0, 0);
         cs += ps_lo + (hsel & (__popc(ms_hi) - ps_lo));
     }
     if (CORE) {
@@ -244,13 +247,14 @@ __device__ __forceinline__ void scan_chunk(const u32x4& r, bool k_in, const u32x
     }
 }
 
-template <int MODE>
+template <int MODE, bool ENC>
 __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
     int n_c, int lo, int hi, int G, int prune, int trim, int sh, PackedBounds tb, MidBounds mb, int e, uint64_t t_core,
     uint64_t t_lo, uint64_t t_shell, float tfs_hi, const uint4* __restrict__ spos, const u32x4* __restrict__ spk,
     const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ bound_g, int cap_core, int cap_shell,
     int32_t* __restrict__ core, int32_t* __restrict__ ncore, int32_t* __restrict__ shell,
-    int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt, uint32_t* __restrict__ err)
+    int32_t* __restrict__ nshell, int32_t* __restrict__ maxcnt, uint32_t* __restrict__ err, int pb,
+    int32_t* __restrict__ sgroup)
 {
     __shared__ u32x4 trec[kTileCap + kTilePad];  // candidate: packed x | y, packed z, exclusion id, sorted index
     __shared__ u32x4 apk[kListWave];             // atom: packed x | y, packed z, exclusion id, range start | length << 16
@@ -284,8 +288,9 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
         const int ti = act ? wrap(cx - x0, n_c) : 0;  // lane's home cell in [0, gr)
         // the rows of this chunk's atoms, one buffer descriptor per list: stores of an
         // overflowing row stay within them (and the rebuild that follows rewrites them)
+        constexpr int eb = ENC ? 2 : 4;  // bytes per shell entry
         const __amdgpu_buffer_rsrc_t rs_s = __builtin_amdgcn_make_buffer_rsrc(
-            shell + (int64_t)chunk * cap_shell, (short)0, na * cap_shell * 4, kBufferWord3);
+            (char*)shell + (int64_t)chunk * cap_shell * eb, (short)0, na * cap_shell * eb, kBufferWord3);
         const __amdgpu_buffer_rsrc_t rs_c = __builtin_amdgcn_make_buffer_rsrc(
             core + (int64_t)chunk * cap_core, (short)0, na * cap_core * 4, kBufferWord3);
         acnt[lane] = make_int2(0, 0);
@@ -331,6 +336,9 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                 const int eB = lenB > 0 ? cell_start[row + lenB] : jB;
                 const int nA = eA - jA;
                 const int total = nA + (eB - jB);
+                // codes: the row's id above pb bits of candidate position
+                const int rcode = ENC ? ((dz - lo) * span_c + (dy - lo)) << pb : 0;
+                if (ENC && total > (1 << pb) && lane == 0) atomicOr(err, ERR_SHELL_CODE);
                 // lane's range in tile positions: cst[u] = position of the first atom of
                 // tile cell u, one lane per cell (cst borrows the atom records' LDS,
                 // which the first tile rewrites only after every lane has read it)
@@ -409,28 +417,32 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
                                 const int qb = (int)(ap.w & 0xffffu) + hl;
                                 int cs = cn.y, cc = cn.x;  // this half's atom: list lengths so far
                                 // byte offsets of this half's atom's rows in the wave's list rows
-                                const int hoff_s = __mul24(ka, cap_shell * 4);
+                                const int hoff_s = __mul24(ka, cap_shell * eb);
+                                // this lane's candidate code in the pair's first chunk
+                                const int cq = ENC ? rcode + base + qb : 0;
                                 {
                                     const int hoff_c = __mul24(ka, cap_core * 4);
                                     // the two atoms have the same number of chunks: every lane of
                                     // all chunks but the last lies inside its half's range
                                     const int last = NCH == 1 ? 0 : NCH == 2 ? 32 : (chunks - 1) * 32;
                                     if (NCH == 2) {
-                                        scan_chunk<MODE, CORE, false>(trec[qb], true, ap, chunk, ka, tb, mb, e, t_core,
-                                                                      t_lo, t_shell, spos, lane, hsel, lowm, hoff_s,
-                                                                      hoff_c, rs_s, rs_c, cs, cc);
+                                        scan_chunk<MODE, CORE, false, ENC>(trec[qb], cq, true, ap, chunk, ka, tb, mb,
+                                                                           e, t_core, t_lo, t_shell, spos, lane, hsel,
+                                                                           lowm, hoff_s, hoff_c, rs_s, rs_c, cs, cc);
                                     } else if (NCH == 0) {
                                         int c0 = 0;
                                         do {
-                                            scan_chunk<MODE, CORE, false>(trec[qb + c0], true, ap, chunk, ka, tb, mb,
-                                                                          e, t_core, t_lo, t_shell, spos, lane, hsel,
-                                                                          lowm, hoff_s, hoff_c, rs_s, rs_c, cs, cc);
+                                            scan_chunk<MODE, CORE, false, ENC>(trec[qb + c0], cq + c0, true, ap, chunk,
+                                                                               ka, tb, mb, e, t_core, t_lo, t_shell,
+                                                                               spos, lane, hsel, lowm, hoff_s, hoff_c,
+                                                                               rs_s, rs_c, cs, cc);
                                             c0 += 32;
                                         } while (c0 < last);
                                     }
-                                    scan_chunk<MODE, CORE, true>(trec[qb + last], last < lenm, ap, chunk, ka, tb, mb,
-                                                                 e, t_core, t_lo, t_shell, spos, lane, hsel, lowm,
-                                                                 hoff_s, hoff_c, rs_s, rs_c, cs, cc);
+                                    scan_chunk<MODE, CORE, true, ENC>(trec[qb + last], cq + last, last < lenm, ap,
+                                                                      chunk, ka, tb, mb, e, t_core, t_lo, t_shell,
+                                                                      spos, lane, hsel, lowm, hoff_s, hoff_c, rs_s,
+                                                                      rs_c, cs, cc);
                                 }
                                 if (lane == 0 || (lane == 32 && has_b)) acnt[ka] = make_int2(cc, cs);
                             }
@@ -456,6 +468,7 @@ __global__ __launch_bounds__(kListWave) void k_build_lists_tiled(
         if (act) {
             const int2 c = acnt[lane];
             store_counts<MODE>(k, c.x, c.y, cap_core, cap_shell, ncore, nshell, err);
+            if (ENC) sgroup[k] = g;
             maxc = max(maxc, c.x);
             maxs = max(maxs, c.y);
         }
@@ -920,6 +933,17 @@ PackedGeometry packed_geometry(const Geometry& g, bool prune)
 
 }  // namespace
 
+bool shell16_possible(const irbe_ctx* h)
+{
+    const Geometry& g = h->geo;
+    if (h->full_list || h->stencil) return false;
+    const bool narrow = 2 * g.reach + 1 <= g.n_c;
+    const int span = g.hi - g.lo + 1;
+    const double per_cell = (double)h->cfg.n_atoms / (double)g.n_cells;
+    const bool lanes = narrow && per_cell < kLaneMaxPerCell && span * span <= 2 * kListWave;
+    return narrow && !lanes && span * span <= 64;
+}
+
 hipError_t launch_build_lists(irbe_ctx* h)
 {
     Geometry g = h->geo;
@@ -961,10 +985,21 @@ hipError_t launch_build_lists(irbe_ctx* h)
     // FP32 threshold of the outermost list with a relative margin of 2e-6, far
     // above the FP32 rounding of the row gaps: the row pruning never drops a member.
     const float tf_hi = (float)(h->stencil ? g.tl_core : g.tl_shell) * 1.000002f;
+    // 16-bit shell entries, when the rows were allocated for them: split lists of
+    // the tiled build over a stencil of at most 64 rows (a row id of rbits bits,
+    // pb bits of candidate position)
+    const int nrows = span * span;
+    const int rbits = nrows > 1 ? 32 - __builtin_clz((unsigned)(nrows - 1)) : 0;
+    const int pb = 16 - rbits;
+    const bool enc = h->shell_bytes == 2;
+    if (enc && (lanes || !narrow || h->full_list || h->stencil || h->sgroup == nullptr || nrows > 64))
+        return hipErrorInvalidValue;
+    h->shell16 = enc;
+    h->lcode = enc ? ListCode{h->cell_start, h->sgroup, n_c, g.lo, span, G, (n_c + G - 1) / G, pb} : ListCode{};
 #define IRBE_LISTS_ARGS                                                                                           \
     n_c, g.lo, g.hi, G, prune, trim, pg.sh, pg.tb, pg.mb, pg.e, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos,      \
         (const u32x4*)h->spk, h->cell_start, h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell,  \
-        h->nshell, h->maxcnt, h->err
+        h->nshell, h->maxcnt, h->err, pb, h->sgroup
 #define IRBE_LANES_ARGS                                                                                            \
     n_c, g.lo, g.hi, G, pl.tb, g.tl_core, g.tl_lo, g.tl_shell, tf_hi, h->spos, (const u32x4*)h->spk, h->cell_start, \
         h->cell_bound, h->cap_core, h->cap_shell, h->core, h->ncore, h->shell, h->nshell, h->maxcnt, h->err
@@ -987,13 +1022,17 @@ hipError_t launch_build_lists(irbe_ctx* h)
         k_pack_sorted<<<(unsigned)blocks_for(h->cfg.n_atoms, kBlock), kBlock, 0, h->stream>>>(
             h->cfg.n_atoms, pg.sh, pg.e, h->spos, h->smol, (u32x4*)h->spk);
         if (h->full_list)
-            k_build_lists_tiled<kListsFull><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+            k_build_lists_tiled<kListsFull, false><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
         else if (h->stencil)
-            k_build_lists_tiled<kListsCoreOnly><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+            k_build_lists_tiled<kListsCoreOnly, false><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+        else if (g.skin && enc)
+            k_build_lists_tiled<kListsSplitSkin, true><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
         else if (g.skin)
-            k_build_lists_tiled<kListsSplitSkin><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+            k_build_lists_tiled<kListsSplitSkin, false><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+        else if (enc)
+            k_build_lists_tiled<kListsSplit, true><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
         else
-            k_build_lists_tiled<kListsSplit><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
+            k_build_lists_tiled<kListsSplit, false><<<(unsigned)groups, kListWave, 0, h->stream>>>(IRBE_LISTS_ARGS);
     }
 #undef IRBE_LANES_ARGS
 #undef IRBE_LISTS_ARGS

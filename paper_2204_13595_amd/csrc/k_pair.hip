@@ -362,6 +362,42 @@ __device__ __forceinline__ int stencil_rows_atom(const StencilRows<ROWS>& T, int
     return o < la ? T.a[lo_k] + o : T.b[lo_k] + (o - la);
 }
 
+// 16-bit shell entries (ListCode): the stencil rows of one list-build group,
+// one row per lane: first atom and length of the row's first index range, and
+// the first atom of its second range minus that length (zeros past the last
+// row, so that any code reads a defined entry).
+__device__ void group_rows_build(int4* T, int grp, const ListCode& lc, int lane)
+{
+    T[lane] = make_int4(0, 0, 0, 0);
+    if (lane < lc.span * lc.span) {
+        const int rowid = grp / lc.gpr;
+        const int cz = rowid / lc.n_c, cy = rowid - cz * lc.n_c;
+        const int x0 = (grp - rowid * lc.gpr) * lc.G;
+        const int span_u = min(lc.G, lc.n_c - x0) - 1 + lc.span;  // cells of the union x range
+        const int xu0 = wrap_cell(x0 + lc.lo, lc.n_c);
+        const int lenA = min(span_u, lc.n_c - xu0);
+        const int dz = lane / lc.span;
+        const int z = wrap_cell(cz + dz + lc.lo, lc.n_c);
+        const int y = wrap_cell(cy + (lane - dz * lc.span) + lc.lo, lc.n_c);
+        const int row = (z * lc.n_c + y) * lc.n_c;
+        const int a = lc.cell_start[row + xu0];
+        const int na = lc.cell_start[row + xu0 + lenA] - a;
+        T[lane] = make_int4(a, na, lc.cell_start[row] - na, 0);
+    }
+    // (the wavefront's own table: its later reads follow these writes in order)
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Atom (sorted index) of shell entry e through the rows of its group in T,
+// clamped to the last atom: codes of a build that reported a too long row range
+// (forces from such lists are wrong, as the error says) still read in bounds.
+__device__ __forceinline__ int group_rows_atom(const int4* T, int pb, int e, int last)
+{
+    const int4 r = T[e >> pb];
+    const int p = e & ((1 << pb) - 1);
+    return (int)min((uint32_t)(p < r.y ? r.x + p : r.z + p), (uint32_t)last);
+}
+
 // A drawn atom j of atom a (sorted indices) counts as a shell pair: not a
 // itself, not of a's molecule, and in the shell annulus.
 __device__ __forceinline__ bool stencil_member(int64_t a, int j, int mi, int mj, uint4 si, uint4 sj, uint64_t t_core,
@@ -412,6 +448,39 @@ __global__ __launch_bounds__(kDecodeBlock) void k_stencil_decode(int64_t n, int 
             if (j == (int)a || (mi >= 0 && sa.smol[j] == mi)) j = -1;
             out[c] = j;
         }
+    }
+}
+
+// 16-bit shell entries: the drawn atoms of the current batch (the list members
+// at the drawn ranks) into batch_j, for the adjoint when no forward at this
+// step wrote them. One wavefront per apw consecutive atoms, one group's rows
+// per wavefront in LDS.
+__global__ __launch_bounds__(kDecodeBlock) void k_list_decode(int64_t n, int apw, ListCode lc,
+                                                              const uint16_t* __restrict__ shell16, int cap_shell,
+                                                              const int32_t* __restrict__ nshell, int p_shell,
+                                                              int p_stride, const uint16_t* __restrict__ ranks,
+                                                              int32_t* __restrict__ batch_j)
+{
+    __shared__ int4 gt[kDecodeBlock / 64][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t a0 = ((int64_t)blockIdx.x * (kDecodeBlock / 64) + wave) * apw;
+    const int64_t a1 = min(n, a0 + apw);
+    int cur = -1;
+    for (int64_t a = a0; a < a1; ++a) {
+        const int grp = lc.sgroup[a];
+        if (grp != cur) {
+            group_rows_build(gt[wave], grp, lc, lane);
+            cur = grp;
+        }
+        const int m = nshell[a];
+        const bool sample = m > p_shell;
+        const int cnt = sample ? p_shell : m;
+        const uint16_t* srow = shell16 + a * (int64_t)cap_shell;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        int32_t* out = batch_j + a * (int64_t)p_stride;
+        for (int c = lane; c < cnt; c += 64)
+            out[c] = group_rows_atom(gt[wave], lc.pb, srow[sample ? (int)rrow[c] : c], (int)n - 1);
     }
 }
 
@@ -477,7 +546,7 @@ __device__ __forceinline__ void add_excl(PairSum<real>& px, uint4 si, real qi, u
     }
 }
 
-template <typename real, bool FULL, bool EV, bool STENCIL, bool SKIN>
+template <typename real, bool FULL, bool EV, bool STENCIL, bool SKIN, bool ENC>
 __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     int64_t n, int apw, PairParams<real> pp, const uint4* __restrict__ spos, const real* __restrict__ sqr,
     const uint4* __restrict__ spq, const int2* __restrict__ sxr, const int32_t* __restrict__ sxidx,
@@ -485,11 +554,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int32_t* __restrict__ shell, const int32_t* __restrict__ nshell, int cap_shell,
     const LJ<real>* __restrict__ lj_g, int n_types, int p_shell, int p_stride, const uint16_t* __restrict__ ranks,
     StencilArgs sa, uint64_t t_core, uint64_t t_shell, real* __restrict__ fsr, double* __restrict__ part,
-    int32_t* __restrict__ bj_out)
+    int32_t* __restrict__ bj_out, ListCode lc)
 {
     __shared__ LJ<real> lj[256];
     __shared__ double red[kPairPartials * (kCoopBlock / 64)];
     __shared__ StencilRows<STENCIL ? kDecodeRows : 1> srows[kCoopBlock / 64];  // stencil rows of one cell per wave
+    __shared__ int4 gtab[ENC ? kCoopBlock / 64 : 1][ENC ? 64 : 1];  // 16-bit entries: one group's rows per wave
     const int nt2 = n_types * n_types;
     for (int t = threadIdx.x; t < nt2; t += kCoopBlock) lj[t] = lj_g[t];
     __syncthreads();
@@ -513,10 +583,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     const int h_ns = nshell[ah];
     const int2 h_x = sxr[ah];
     const int h_mol = STENCIL ? sa.smol[ah] : 0;
+    const int h_grp = ENC ? lc.sgroup[ah] : 0;
     // shell weight N_S / p~ (1 when every member is taken), one division per lane
     const real h_w = (!FULL && h_ns > p_shell) ? (real)((double)h_ns / (double)p_shell) : (real)1;
     const int nrows = sa.span * sa.span;
     int tcell = -1;  // the cell whose stencil rows sit in srows[wave]
+    int tgrp = -1;   // the group whose rows sit in gtab[wave]
     // first-level indices of one atom's first pass: the lane's first core entry,
     // its two batch ranks (or shell positions) and its first excluded partner
     // Without energies the excluded partners follow the core entries in one slot
@@ -556,6 +628,13 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const int jc = n_jc, r0 = n_r0, r1 = n_r1, jx = n_jx;
         // the next atom's first-level loads go out before this atom's dependent ones
         if (a + 1 < a1) first_level(a + 1, t + 1, n_jc, n_r0, n_r1, n_jx);
+        if (ENC) {
+            const int grp = bcast(h_grp, t);
+            if (grp != tgrp) {
+                group_rows_build(gtab[wave], grp, lc, lane);
+                tgrp = grp;
+            }
+        }
         const uint4 si = make_uint4(bcast(h_s.x, t), bcast(h_s.y, t), bcast(h_s.z, t),
                                     bcast(h_s.w, t));
         const real qi = bcast(h_q, t) * pp.ke;
@@ -567,13 +646,18 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const int2 xr = make_int2(bcast(h_x.x, t), bcast(h_x.y, t));
         const int32_t* crow = core + a * (int64_t)cap_core;
         const int32_t* srow = shell + a * (int64_t)cap_shell;
+        const uint16_t* srow16 = reinterpret_cast<const uint16_t*>(shell) + a * (int64_t)cap_shell;
+        // shell member at position q of the atom's list
+        auto member = [&](int q) -> int {
+            return ENC ? group_rows_atom(gtab[wave], lc.pb, srow16[q], (int)n - 1) : srow[q];
+        };
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
         const bool sample = !FULL && ns > p_shell;
         const int cnt = sample ? p_shell : ns;
         const real w = bcast(h_w, t);
         PairSum<real> pc, ps, px;
-        const int js0 = STENCIL ? r0 : (r0 >= 0 ? srow[r0] : -1);
-        const int js1 = STENCIL ? r1 : (r1 >= 0 ? srow[r1] : -1);
+        const int js0 = STENCIL ? r0 : (r0 >= 0 ? member(r0) : -1);
+        const int js1 = STENCIL ? r1 : (r1 >= 0 ? member(r1) : -1);
         if (!STENCIL && !FULL && bj_out) {
             // the batch atoms, for the backward expected at this step
             int32_t* o = bj_out + a * (int64_t)p_stride;
@@ -654,7 +738,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
                 if (stencil_member(a, j, mi, sa.smol[j], si, sj, t_core, t_shell))
                     add_pair<real, EV>(ps, si, qi, sj, qj, ljof(sj), pp);
             } else {
-                const int j = srow[sample ? (int)rrow[c] : c];
+                const int j = member(sample ? (int)rrow[c] : c);
                 if (!FULL && bj_out) bj_out[a * (int64_t)p_stride + c] = j;
                 uint4 sj;
                 real qj;
@@ -834,6 +918,21 @@ hipError_t launch_stencil_decode(irbe_ctx* h)
     return hipGetLastError();
 }
 
+// 16-bit shell entries: the drawn atoms of the current ranks into h->batch_j.
+static hipError_t launch_list_decode(irbe_ctx* h)
+{
+    if (!h->shell16) return hipErrorInvalidValue;
+    const int64_t n = h->cfg.n_atoms;
+    const hipError_t e = ensure_batch_atoms(h);
+    if (e != hipSuccess) return e;
+    const int apw = 16;
+    const int64_t waves = blocks_for(n, apw);
+    k_list_decode<<<(unsigned)blocks_for(waves, kDecodeBlock / 64), kDecodeBlock, 0, h->stream>>>(
+        n, apw, h->lcode, reinterpret_cast<const uint16_t*>(h->shell), h->cap_shell, h->nshell, h->cfg.p_shell,
+        h->p_stride, h->ranks, h->batch_j);
+    return hipGetLastError();
+}
+
 // Threads per block of the batch draw and the LDS its bitmaps take (one bitmap
 // of the longest list per thread); more than 64 KiB means device memory.
 static int draw_block(const irbe_ctx* h, size_t* lds)
@@ -886,12 +985,12 @@ static hipError_t launch_draw(irbe_ctx* h, uint64_t step)
     if (e == hipSuccess) {
         h->ranks_valid = true;
         h->ranks_step = step;
-        h->batch_j_valid = false;
+        h->batch_j_valid = h->batch_j_fwd = false;
     }
     return e;
 }
 
-template <typename real, bool FULL, bool EV, bool STENCIL, bool SKIN>
+template <typename real, bool FULL, bool EV, bool STENCIL, bool SKIN, bool ENC = false>
 static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
 {
     const int64_t n = h->cfg.n_atoms;
@@ -904,19 +1003,19 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     if (e != hipSuccess) return e;
     // stencil sampling keeps one cell's stencil rows for consecutive atoms: longer
     // runs of atoms per wavefront pay there, shorter ones with list-drawn batches
-    const int apw = STENCIL ? kAtomsPerWaveStencil : kAtomsPerWaveList;
+    const int apw = STENCIL ? kAtomsPerWaveStencil : (FULL ? kAtomsPerWaveList : kAtomsPerWaveSplit);
     const int64_t waves = blocks_for(n, apw);
     const unsigned nb = (unsigned)blocks_for(waves, kCoopBlock / 64);
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     // the batch atoms for the backward, when one followed the last forward (into a
     // buffer that backward allocated: a forward allocates nothing here)
     int32_t* bj_out = (!STENCIL && !FULL && h->keep_batch) ? h->batch_j : nullptr;
-    k_pair_coop<real, FULL, EV, STENCIL, SKIN><<<nb, kCoopBlock, 0, h->stream>>>(
+    k_pair_coop<real, FULL, EV, STENCIL, SKIN, ENC><<<nb, kCoopBlock, 0, h->stream>>>(
         n, apw, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
-        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part, bj_out);
+        h->ranks, stencil_args(h), h->geo.t_core, h->geo.t_shell, (real*)h->fsr, h->pair_part, bj_out, h->lcode);
     h->pair_nb = nb;
-    if (bj_out) h->batch_j_valid = true;
+    if (bj_out) h->batch_j_valid = h->batch_j_fwd = true;
     return hipGetLastError();
 }
 
@@ -940,7 +1039,7 @@ static hipError_t launch_thread_t(irbe_ctx* h, uint64_t step)
         h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride, h->ranks, h->geo.t_core,
         h->geo.t_shell, h->geo.skin, (real*)h->fsr, h->pair_part, bj_out);
     h->pair_nb = nb;
-    if (bj_out) h->batch_j_valid = true;
+    if (bj_out) h->batch_j_valid = h->batch_j_fwd = true;
     return hipGetLastError();
 }
 
@@ -954,18 +1053,23 @@ static hipError_t launch_coop_s(irbe_ctx* h, uint64_t step, bool ev)
     if (h->stencil)
         return ev ? launch_coop_t<real, false, true, true, SKIN>(h, step)
                   : launch_coop_t<real, false, false, true, SKIN>(h, step);
+    if (h->shell16)
+        return ev ? launch_coop_t<real, false, true, false, SKIN, true>(h, step)
+                  : launch_coop_t<real, false, false, false, SKIN, true>(h, step);
     return ev ? launch_coop_t<real, false, true, false, SKIN>(h, step)
               : launch_coop_t<real, false, false, false, SKIN>(h, step);
 }
 
 // Split lists whose longest core list plus batch stays within this many entries
-// take the thread-per-atom kernel.
+// take the thread-per-atom kernel (32-bit shell entries only: the cooperative
+// kernel decodes the 16-bit ones).
 constexpr int kSparsePairs = 32;
 
 template <typename real>
 static hipError_t launch_coop_r(irbe_ctx* h, uint64_t step, bool ev)
 {
-    if (!h->full_list && !h->stencil && h->max_core + std::min(h->max_shell, h->cfg.p_shell) <= kSparsePairs)
+    if (!h->full_list && !h->stencil && !h->shell16 &&
+        h->max_core + std::min(h->max_shell, h->cfg.p_shell) <= kSparsePairs)
         return ev ? launch_thread_t<real, true>(h, step) : launch_thread_t<real, false>(h, step);
     return h->geo.skin ? launch_coop_s<real, true>(h, step, ev) : launch_coop_s<real, false>(h, step, ev);
 }
@@ -1680,12 +1784,23 @@ static hipError_t launch_adj_r(irbe_ctx* h, uint64_t step, bool want_lj, int apw
         return want_lj ? launch_adj_t<real, false, true, BK, true>(h, step, apw, bk, rec_cap, lds)
                        : launch_adj_t<real, false, false, BK, true>(h, step, apw, bk, rec_cap, lds);
     // the batch atoms the forward wrote, when they are those of this step's ranks
-    // (launch_draw keeps them unless it draws again)
+    // (launch_draw keeps them unless it draws again); with 16-bit shell entries
+    // the atoms at the ranks decoded once otherwise
     hipError_t e = launch_draw(h, step);
     if (e != hipSuccess) return e;
-    if (h->batch_j_valid)
-        return want_lj ? launch_adj_t<real, false, true, BK, false, true>(h, step, apw, bk, rec_cap, lds)
-                       : launch_adj_t<real, false, false, BK, false, true>(h, step, apw, bk, rec_cap, lds);
+    const bool from_fwd = h->batch_j_valid && h->batch_j_fwd;
+    if (h->shell16 && !h->batch_j_valid) {
+        e = launch_list_decode(h);
+        if (e != hipSuccess) return e;
+        h->batch_j_valid = true;
+        h->batch_j_fwd = false;
+    }
+    if (h->batch_j_valid) {
+        e = want_lj ? launch_adj_t<real, false, true, BK, false, true>(h, step, apw, bk, rec_cap, lds)
+                    : launch_adj_t<real, false, false, BK, false, true>(h, step, apw, bk, rec_cap, lds);
+        h->adj_used_batch = from_fwd;
+        return e;
+    }
     return want_lj ? launch_adj_t<real, false, true, BK, false>(h, step, apw, bk, rec_cap, lds)
                    : launch_adj_t<real, false, false, BK, false>(h, step, apw, bk, rec_cap, lds);
 }

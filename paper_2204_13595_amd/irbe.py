@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libirbe.so")
 
-IRBE_ABI_VERSION = 2
+IRBE_ABI_VERSION = 3
 IRBE_MIXED_FP32 = 0
 IRBE_FP64 = 1
 IRBE_ENERGY = 1
@@ -26,11 +26,11 @@ SHELL_SOURCE = {"list": 0, "stencil": 1}
 DBG = {
     "cell_start": 1, "cell_atoms": 2, "core_off": 3, "core_idx": 4, "shell_off": 5, "shell_idx": 6,
     "batch_off": 7, "batch_rank": 8, "kvec": 9, "rho": 10, "fcorr": 11, "scalars": 12, "counts": 13,
-    "batch_atoms": 14, "adj_atomics": 15, "adj_batch": 16,
+    "batch_atoms": 14, "adj_atomics": 15, "adj_batch": 16, "shell_bits": 17,
 }
 _DBG_DTYPE = {1: np.int64, 2: np.int64, 3: np.int64, 4: np.int32, 5: np.int64, 6: np.int32, 7: np.int64,
               8: np.int32, 9: np.int32, 10: np.float64, 11: np.float64, 12: np.float64, 13: np.int64, 14: np.int32,
-              15: np.int64, 16: np.int64}
+              15: np.int64, 16: np.int64, 17: np.int64}
 
 STATUS = {0: "IRBE_OK", -1: "IRBE_EINVAL", -2: "IRBE_ENOMEM", -3: "IRBE_EHIP", -4: "IRBE_ECAPACITY",
           -5: "IRBE_ESTATE", -6: "IRBE_EUNSUPPORTED", -7: "IRBE_ENONFINITE", -8: "IRBE_ECONVERGENCE"}
@@ -67,7 +67,7 @@ class Config(ctypes.Structure):
         ("r_core", ctypes.c_double), ("r_shell", ctypes.c_double), ("p_shell", ctypes.c_int32),
         ("p_kspace", ctypes.c_int32), ("n_types", ctypes.c_int32), ("shell_source", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("capacity_hint", ctypes.c_double), ("skin", ctypes.c_double),
-        ("lj_cut", ctypes.c_double),
+        ("lj_cut", ctypes.c_double), ("shell_entries", ctypes.c_int32),
     ]
 
 
@@ -149,7 +149,7 @@ class Handle:
                  p_shell: int = 100, p_kspace: int = 100, seed: int = 13595, n_types: int = 2,
                  precision: str = "mixed", coulomb_k: float = 138.935458, capacity_hint: float = 0.0,
                  shell_source: str = "list", skin: float = 0.0, lj_cut: float = 0.0,
-                 device: torch.device | str | None = None):
+                 shell_entries: int = 0, device: torch.device | str | None = None):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the IRBE HIP library needs a GPU")
@@ -160,7 +160,7 @@ class Handle:
         self.cfg = Config(IRBE_ABI_VERSION, IRBE_FP64 if precision == "fp64" else IRBE_MIXED_FP32, self.n_atoms,
                           float(box), float(beta), float(coulomb_k), float(r_core), float(r_shell), int(p_shell),
                           int(p_kspace), self.n_types, SHELL_SOURCE[shell_source], int(seed), float(capacity_hint),
-                          float(skin), float(lj_cut))
+                          float(skin), float(lj_cut), int(shell_entries))
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             h = ctypes.c_void_p()
