@@ -621,13 +621,37 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         }
         jx = (!kFold && lane < xr.y) ? sxidx[xr.x + lane] : -1;
     };
-    int n_jc = -1, n_r0 = -1, n_r1 = -1, n_jx = -1;
-    if (a0 < a1) first_level(a0, 0, n_jc, n_r0, n_r1, n_jx);
+    // second level of an atom's first pass: the shell entries at its two ranks as
+    // stored (16-bit codes or indices; the atoms themselves with stencil sampling)
+    auto second_level = [&](int64_t a, int r0, int r1, int& e0, int& e1) {
+        if (STENCIL) {
+            e0 = r0;
+            e1 = r1;
+        } else if (ENC) {
+            const uint16_t* s16 = reinterpret_cast<const uint16_t*>(shell) + a * (int64_t)cap_shell;
+            e0 = r0 >= 0 ? (int)s16[r0] : -1;
+            e1 = r1 >= 0 ? (int)s16[r1] : -1;
+        } else {
+            const int32_t* s1 = shell + a * (int64_t)cap_shell;
+            e0 = r0 >= 0 ? s1[r0] : -1;
+            e1 = r1 >= 0 ? s1[r1] : -1;
+        }
+    };
+    // a pipeline over the wavefront's atoms: while atom a's pairs are evaluated,
+    // the shell entries of atom a + 1 and the first level of atom a + 2 are loaded
+    // (issued after atom a's gathers, so that waiting for those does not wait for
+    // them: the vector memory counter is in order)
+    int n_jc = -1, n_e0 = -1, n_e1 = -1, n_jx = -1;  // atom a: first level and shell entries
+    int m_jc = -1, m_r0 = -1, m_r1 = -1, m_jx = -1;  // atom a + 1: first level
+    if (a0 < a1) {
+        int r0, r1;
+        first_level(a0, 0, n_jc, r0, r1, n_jx);
+        second_level(a0, r0, r1, n_e0, n_e1);
+        if (a0 + 1 < a1) first_level(a0 + 1, 1, m_jc, m_r0, m_r1, m_jx);
+    }
     for (int64_t a = a0; a < a1; ++a) {
         const int t = (int)(a - a0);
-        const int jc = n_jc, r0 = n_r0, r1 = n_r1, jx = n_jx;
-        // the next atom's first-level loads go out before this atom's dependent ones
-        if (a + 1 < a1) first_level(a + 1, t + 1, n_jc, n_r0, n_r1, n_jx);
+        const int jc = n_jc, e0 = n_e0, e1 = n_e1, jx = n_jx;
         if (ENC) {
             const int grp = bcast(h_grp, t);
             if (grp != tgrp) {
@@ -656,8 +680,8 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         const int cnt = sample ? p_shell : ns;
         const real w = bcast(h_w, t);
         PairSum<real> pc, ps, px;
-        const int js0 = STENCIL ? r0 : (r0 >= 0 ? member(r0) : -1);
-        const int js1 = STENCIL ? r1 : (r1 >= 0 ? member(r1) : -1);
+        const int js0 = ENC ? (e0 >= 0 ? group_rows_atom(gtab[wave], lc.pb, e0, (int)n - 1) : -1) : e0;
+        const int js1 = ENC ? (e1 >= 0 ? group_rows_atom(gtab[wave], lc.pb, e1, (int)n - 1) : -1) : e1;
         if (!STENCIL && !FULL && bj_out) {
             // the batch atoms, for the backward expected at this step
             int32_t* o = bj_out + a * (int64_t)p_stride;
@@ -678,6 +702,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
             qjx = qjc;
         } else {
             at.get(max(jx, 0), pjx, qjx);
+        }
+        if (a + 1 < a1) {
+            n_jc = m_jc;
+            n_jx = m_jx;
+            second_level(a + 1, m_r0, m_r1, n_e0, n_e1);
+            if (a + 2 < a1) first_level(a + 2, t + 2, m_jc, m_r0, m_r1, m_jx);
         }
         // skin: a core entry counts inside r_core, a list shell entry inside the annulus
         // (the whole ball in full-list mode), at these positions
