@@ -815,6 +815,9 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
     if (threadIdx.x < 12) part[blk * (int64_t)kPairPartials + threadIdx.x] = out;
 }
 
+// Core entries and batch slots of the first pass of k_pair_thread.
+constexpr int kThreadFirst = 12;
+
 // Sparse lists (every atom's core list and batch within a few dozen entries, as
 // in the dilute electrolytes): one thread per atom walks its own core list,
 // excluded partners and batch, so that no wavefront lane idles on an atom with
@@ -850,8 +853,45 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
         PairSum<real> pc, ps, px;
         const int nc = ncore[a];
         const int32_t* crow = core + a * (int64_t)cap_core;
-        // four entries at a time: their index and position loads go out together
-        for (int c0 = 0; c0 < nc; c0 += 4) {
+        const int ns = nshell[a];
+        const bool sample = ns > p_shell;
+        const int cnt = sample ? p_shell : ns;
+        const int32_t* srow = shell + a * (int64_t)cap_shell;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        // first pass over up to kThreadFirst core entries and batch slots, each
+        // level's loads issued together: core indices and batch ranks, then core
+        // positions and shell entries, then shell positions
+        int jc[kThreadFirst], js[kThreadFirst];
+#pragma unroll
+        for (int u = 0; u < kThreadFirst; ++u) jc[u] = u < nc ? crow[u] : -1;
+#pragma unroll
+        for (int u = 0; u < kThreadFirst; ++u) js[u] = u < cnt ? (sample ? (int)rrow[u] : u) : -1;
+        uint4 sc[kThreadFirst];
+        real qc[kThreadFirst];
+#pragma unroll
+        for (int u = 0; u < kThreadFirst; ++u) at.get(max(jc[u], 0), sc[u], qc[u]);
+#pragma unroll
+        for (int u = 0; u < kThreadFirst; ++u) js[u] = js[u] >= 0 ? srow[js[u]] : -1;
+        if (bj_out) {
+            // the batch atoms, for the backward expected at this step
+#pragma unroll
+            for (int u = 0; u < kThreadFirst; ++u)
+                if (u < cnt) bj_out[a * (int64_t)p_stride + u] = js[u];
+        }
+        uint4 ss[kThreadFirst];
+        real qs[kThreadFirst];
+#pragma unroll
+        for (int u = 0; u < kThreadFirst; ++u) at.get(max(js[u], 0), ss[u], qs[u]);
+#pragma unroll
+        for (int u = 0; u < kThreadFirst; ++u)
+            if (jc[u] >= 0 && (!skin || dist2_q(si, sc[u]) <= t_core))
+                add_pair<real, EV>(pc, si, qi, sc[u], qc[u], ljof(sc[u]), pp);
+#pragma unroll
+        for (int u = 0; u < kThreadFirst; ++u)
+            if (js[u] >= 0 && (!skin || in_annulus(si, ss[u], t_core, t_shell)))
+                add_pair<real, EV>(ps, si, qi, ss[u], qs[u], ljof(ss[u]), pp);
+        // the rest four entries at a time: their index and position loads go out together
+        for (int c0 = kThreadFirst; c0 < nc; c0 += 4) {
             int j[4];
             uint4 sj[4];
             real qj[4];
@@ -871,12 +911,7 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_thread(
             at.get(sxidx[xr.x + c], sj, qj);
             add_excl<real, EV>(px, si, qi, sj, qj, pp);
         }
-        const int ns = nshell[a];
-        const bool sample = ns > p_shell;
-        const int cnt = sample ? p_shell : ns;
-        const int32_t* srow = shell + a * (int64_t)cap_shell;
-        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
-        for (int c0 = 0; c0 < cnt; c0 += 4) {
+        for (int c0 = kThreadFirst; c0 < cnt; c0 += 4) {
             int r[4], j[4];
             uint4 sj[4];
             real qj[4];
