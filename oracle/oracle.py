@@ -1,4 +1,4 @@
-"""Python driver of the FP64 CPU oracle (test infrastructure only).
+"""Python front end of the FP64 CPU oracle (test infrastructure only).
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this module. It loads ``liborc.so`` built from ``irbe_oracle.c`` (plain
