@@ -466,20 +466,39 @@ __global__ __launch_bounds__(kDecodeBlock) void k_list_decode(int64_t n, int apw
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t a0 = ((int64_t)blockIdx.x * (kDecodeBlock / 64) + wave) * apw;
     const int64_t a1 = min(n, a0 + apw);
+    // an atom's first two slots: their ranks (or list positions), -1 past the batch
+    auto slots = [&](int64_t a, int& q0, int& q1) {
+        const int m = nshell[a];
+        const bool sample = m > p_shell;
+        const int cnt = sample ? p_shell : m;
+        const uint16_t* rrow = ranks + a * (int64_t)p_stride;
+        q0 = lane < cnt ? (sample ? (int)rrow[lane] : lane) : -1;
+        q1 = lane + 64 < cnt ? (sample ? (int)rrow[lane + 64] : lane + 64) : -1;
+    };
     int cur = -1;
+    int n_q0 = -1, n_q1 = -1;
+    if (a0 < a1) slots(a0, n_q0, n_q1);
     for (int64_t a = a0; a < a1; ++a) {
+        const int q0 = n_q0, q1 = n_q1;
+        const uint16_t* srow = shell16 + a * (int64_t)cap_shell;
+        // this atom's entries, then the next atom's ranks (in flight while these decode)
+        const int e0 = q0 >= 0 ? (int)srow[q0] : 0;
+        const int e1 = q1 >= 0 ? (int)srow[q1] : 0;
+        if (a + 1 < a1) slots(a + 1, n_q0, n_q1);
         const int grp = lc.sgroup[a];
         if (grp != cur) {
             group_rows_build(gt[wave], grp, lc, lane);
             cur = grp;
         }
+        int32_t* out = batch_j + a * (int64_t)p_stride;
+        if (q0 >= 0) out[lane] = group_rows_atom(gt[wave], lc.pb, e0, (int)n - 1);
+        if (q1 >= 0) out[lane + 64] = group_rows_atom(gt[wave], lc.pb, e1, (int)n - 1);
+        // the rest (batches of more than 128)
         const int m = nshell[a];
         const bool sample = m > p_shell;
         const int cnt = sample ? p_shell : m;
-        const uint16_t* srow = shell16 + a * (int64_t)cap_shell;
         const uint16_t* rrow = ranks + a * (int64_t)p_stride;
-        int32_t* out = batch_j + a * (int64_t)p_stride;
-        for (int c = lane; c < cnt; c += 64)
+        for (int c = lane + 128; c < cnt; c += 64)
             out[c] = group_rows_atom(gt[wave], lc.pb, srow[sample ? (int)rrow[c] : c], (int)n - 1);
     }
 }
