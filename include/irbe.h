@@ -201,10 +201,11 @@ irbe_status irbe_build_lists(irbe_handle h, const void* pos, uint64_t step);
  * W_ab = sum over pairs of (r_i - r_j)_a f_ij,b plus the k-space term; the
  * starred terms are the estimators matching Eq. (2.3) in expectation.
  * When the last forward of the handle was followed by a backward, a forward with
- * list-drawn batches also writes its batch atoms (N x p_shell int32 in a buffer
- * that backward allocated), which irbe_compute_forces_backward at the same step
- * reads in place of the ranks and shell rows (results bitwise the same); a forward
- * not followed by a backward stops this for the next one. */
+ * sampled batches also writes its batch atoms (N x p_shell int32 in a buffer that
+ * backward allocated; with stencil sampling -1 for the atom itself and its
+ * molecule), which irbe_compute_forces_backward at the same step reads in place of
+ * the ranks and shell rows, or of decoding the stencil ranks (results bitwise the
+ * same); a forward not followed by a backward stops this for the next one. */
 irbe_status irbe_compute_forces(irbe_handle h, const void* pos, uint64_t step, void* force, uint32_t flags,
                                 double* energy_virial);
 

@@ -907,9 +907,9 @@ irbe_status irbe_compute_forces_backward(irbe_handle h, const void* pos, uint64_
     if (!h->have_lists) return fail(h, IRBE_ESTATE, "backward before irbe_build_lists");
     if (grad_lj && h->cfg.n_types > kMaxTypesGrad)
         return fail(h, IRBE_EUNSUPPORTED, "LJ gradients need n_types <= 4");
-    // a backward that follows a forward: the next forward with list-drawn batches
-    // also writes the batch atoms, for the backward expected after it
-    if (h->fwd_pending && !h->stencil && !h->full_list) {
+    // a backward that follows a forward: the next forward (list-drawn or stencil-
+    // drawn batches) also writes the batch atoms, for the backward expected after it
+    if (h->fwd_pending && !h->full_list) {
         IRBE_TRY(h, ensure_batch_atoms(h), "allocating the batch atoms");
         h->keep_batch = true;
     }

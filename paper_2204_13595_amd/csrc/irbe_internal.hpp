@@ -205,10 +205,10 @@ struct irbe_ctx {
     unsigned long long* adj_atomics = nullptr;  // [1] shell-adjoint records of the last backward added by atomics
     bool adj_all_atomic = false;      // the last backward added every shell-adjoint record by atomics
     uint16_t* ranks = nullptr;        // [N * p_stride] shell batch ranks of the current step
-    int32_t* batch_j = nullptr;       // [N * p_stride] the drawn atoms (sorted index) of the current ranks: with
-                                      // stencil sampling (-1: i or i's molecule) for the adjoint and read-back,
-                                      // with list-drawn batches written by the forward for the backward that
-                                      // follows it; allocated on first use
+    int32_t* batch_j = nullptr;       // [N * p_stride] the drawn atoms (sorted index) of the current ranks (with
+                                      // stencil sampling -1: i or i's molecule), for the adjoint and read-back:
+                                      // written by the forward for the backward that follows it, or decoded
+                                      // (stencil ranks, 16-bit shell entries); allocated on first use
     bool batch_j_valid = false;       // batch_j holds the decode of the current ranks
     bool batch_j_fwd = false;         // ... written by a forward (not by a decode for the backward)
     bool keep_batch = false;          // the next forward writes batch_j (the last forward had a backward)

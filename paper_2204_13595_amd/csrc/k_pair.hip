@@ -701,15 +701,17 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         PairSum<real> pc, ps, px;
         const int js0 = ENC ? (e0 >= 0 ? group_rows_atom(gtab[wave], lc.pb, e0, (int)n - 1) : -1) : e0;
         const int js1 = ENC ? (e1 >= 0 ? group_rows_atom(gtab[wave], lc.pb, e1, (int)n - 1) : -1) : e1;
-        if (!STENCIL && !FULL && bj_out) {
-            // the batch atoms, for the backward expected at this step
-            int32_t* o = bj_out + a * (int64_t)p_stride;
-            if (lane < cnt) o[lane] = js0;
-            if (lane + 64 < cnt) o[lane + 64] = js1;
-        }
         const int mi = STENCIL ? bcast(h_mol, t) : 0;
         const int mj0 = STENCIL ? sa.smol[max(js0, 0)] : 0;
         const int mj1 = STENCIL ? sa.smol[max(js1, 0)] : 0;
+        if (!FULL && bj_out) {
+            // the batch atoms, for the backward expected at this step (with stencil
+            // sampling -1 for i itself and i's molecule, as k_stencil_decode writes)
+            auto bj = [&](int j, int mj) { return STENCIL && (j == (int)a || (mi >= 0 && mj == mi)) ? -1 : j; };
+            int32_t* o = bj_out + a * (int64_t)p_stride;
+            if (lane < cnt) o[lane] = bj(js0, mj0);
+            if (lane + 64 < cnt) o[lane + 64] = bj(js1, mj1);
+        }
         // (unused slots load atom 0, so that every position is one 16-byte load)
         uint4 pjc, pj0, pj1, pjx;
         real qjc, qj0, qj1, qjx;
@@ -781,10 +783,12 @@ __global__ __launch_bounds__(kCoopBlock) void k_pair_coop(
         for (int c = lane + 128; c < cnt; c += 64) {
             if (STENCIL) {
                 const int j = stencil_rows_atom(srows[wave], nrows, sample ? (int)rrow[c] : c);
+                const int mj = sa.smol[j];
+                if (bj_out) bj_out[a * (int64_t)p_stride + c] = (j == (int)a || (mi >= 0 && mj == mi)) ? -1 : j;
                 uint4 sj;
                 real qj;
                 at.get(j, sj, qj);
-                if (stencil_member(a, j, mi, sa.smol[j], si, sj, t_core, t_shell))
+                if (stencil_member(a, j, mi, mj, si, sj, t_core, t_shell))
                     add_pair<real, EV>(ps, si, qi, sj, qj, ljof(sj), pp);
             } else {
                 const int j = member(sample ? (int)rrow[c] : c);
@@ -1093,7 +1097,7 @@ static hipError_t launch_coop_t(irbe_ctx* h, uint64_t step)
     if ((int64_t)nb > h->part_blocks) return hipErrorInvalidValue;
     // the batch atoms for the backward, when one followed the last forward (into a
     // buffer that backward allocated: a forward allocates nothing here)
-    int32_t* bj_out = (!STENCIL && !FULL && h->keep_batch) ? h->batch_j : nullptr;
+    int32_t* bj_out = (!FULL && h->keep_batch) ? h->batch_j : nullptr;
     k_pair_coop<real, FULL, EV, STENCIL, SKIN, ENC><<<nb, kCoopBlock, 0, h->stream>>>(
         n, apw, pp, h->spos, (const real*)h->sq_r, h->spq, h->sxr, h->sxidx, h->core, h->ncore, h->cap_core,
         h->shell, h->nshell, h->cap_shell, (const LJ<real>*)h->lj, h->cfg.n_types, h->cfg.p_shell, h->p_stride,
@@ -1864,9 +1868,14 @@ static hipError_t launch_adj_r(irbe_ctx* h, uint64_t step, bool want_lj, int apw
     if (h->full_list)
         return want_lj ? launch_adj_t<real, true, true, false, false>(h, step, apw, bk, 0, 0)
                        : launch_adj_t<real, true, false, false, false>(h, step, apw, bk, 0, 0);
-    if (h->stencil)
-        return want_lj ? launch_adj_t<real, false, true, BK, true>(h, step, apw, bk, rec_cap, lds)
-                       : launch_adj_t<real, false, false, BK, true>(h, step, apw, bk, rec_cap, lds);
+    if (h->stencil) {
+        // (the batch atoms the forward wrote when it was asked to, else decoded)
+        const bool from_fwd = h->ranks_valid && h->ranks_step == step && h->batch_j_valid && h->batch_j_fwd;
+        const hipError_t e = want_lj ? launch_adj_t<real, false, true, BK, true>(h, step, apw, bk, rec_cap, lds)
+                                     : launch_adj_t<real, false, false, BK, true>(h, step, apw, bk, rec_cap, lds);
+        h->adj_used_batch = from_fwd;
+        return e;
+    }
     // the batch atoms the forward wrote, when they are those of this step's ranks
     // (launch_draw keeps them unless it draws again); with 16-bit shell entries
     // the atoms at the ranks decoded once otherwise

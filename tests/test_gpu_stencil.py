@@ -161,3 +161,33 @@ def test_stencil_electrolyte_parity(orc, valence):
                                     mode="stencil")
     assert _rms_rel(gp.cpu().numpy(), r_pos) < 1e-10
     assert _rms_rel(gq.cpu().numpy(), r_q) < 1e-10
+
+
+@pytest.mark.parametrize("precision,p_shell", [("fp64", 100), ("mixed", 100), ("fp64", 2000)])
+def test_stencil_backward_reads_forward_batch(precision, p_shell):
+    """Once a backward has followed a forward, the next forward writes its decoded
+    batch atoms (-1 for i and i's molecule; p~ = 2000 also past the first 128
+    slots) and the backward at that step reads them in place of decoding the
+    ranks: gradients bitwise those of a handle that decodes them (to FP64 rounding
+    when shell records took the order-dependent atomics)."""
+    w = inputs.workload("water4k")
+    ha, pos, *_ = _setup(w, precision, p_shell=p_shell)
+    G = torch.tensor(np.random.default_rng(9).standard_normal((w.n_atoms, 3)), dtype=pos.dtype, device=pos.device)
+    for step in (1, 2):
+        ha.build_lists(pos, step)
+        ha.compute_forces(pos, step)
+        got = ha.compute_forces_backward(pos, step, G)
+        assert int(ha.debug("adj_batch")[0]) == (1 if step == 2 else 0)
+    hb, *_ = _setup(w, precision, p_shell=p_shell)
+    hb.build_lists(pos, 2)
+    hb.compute_forces(pos, 2)
+    ref = hb.compute_forces_backward(pos, 2, G)
+    assert int(hb.debug("adj_batch")[0]) == 0
+    atomics = int(ha.debug("adj_atomics")[0]) != 0 or int(hb.debug("adj_atomics")[0]) != 0
+    for x, y in zip(got, ref):
+        if atomics:
+            assert float((x - y).abs().max()) <= 1e-12 * float(y.abs().max())
+        else:
+            assert torch.equal(x, y)
+    ha.close()
+    hb.close()
