@@ -14,11 +14,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _handle(w, precision, p_shell=100, p_kspace=100):
+def _handle(w, precision, p_shell=100, p_kspace=100, shell_entries=0):
     from paper_2204_13595_amd import irbe
     dt = torch.float64 if precision == "fp64" else torch.float32
     dev = torch.device("cuda", 0)
-    h = irbe.Handle(w.n_atoms, w.box, p_shell=p_shell, p_kspace=p_kspace, precision=precision, device=dev)
+    h = irbe.Handle(w.n_atoms, w.box, p_shell=p_shell, p_kspace=p_kspace, precision=precision,
+                    shell_entries=shell_entries, device=dev)
     pos = torch.tensor(w.pos, dtype=dt, device=dev)
     q = torch.tensor(w.charge, dtype=dt, device=dev)
     h.set_system(torch.tensor(w.atom_type, device=dev), q, torch.tensor(w.molecule, device=dev), w.lj_sigma, w.lj_eps)
@@ -41,11 +42,14 @@ def _compare(h, pos, step):
     assert torch.equal(f2, f_ref2)
 
 
-@pytest.mark.parametrize("precision,p_shell", [("mixed", 100), ("fp64", 100), ("mixed", 0)])
-def test_noalloc_matches_compute_forces_large_then_small(precision, p_shell):
+@pytest.mark.parametrize("precision,p_shell,entries", [("mixed", 100, 0), ("fp64", 100, 0), ("mixed", 0, 0),
+                                                       ("mixed", 100, 32)])
+def test_noalloc_matches_compute_forces_large_then_small(precision, p_shell, entries):
+    """water4k takes 16-bit shell entries by default (entries = 32: indices);
+    water512, whose stencil wraps the box, 32-bit ones."""
     for name, step in (("water4k", 3), ("water512", 7)):
         w = inputs.workload(name)
-        h, pos = _handle(w, precision, p_shell=p_shell)
+        h, pos = _handle(w, precision, p_shell=p_shell, shell_entries=entries)
         h.build_lists(pos, step)
         _compare(h, pos, step)
         # the handle keeps working as before: the normal path after the no-alloc one
